@@ -1,0 +1,527 @@
+/*
+ * bsp_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-thread CPU simulation of the two BSP sorting
+ * algorithms of Gerbessiotis & Siniolakis, "BSP Sorting: An Experimental
+ * Study": Sort_Det_BSP (Section 5.1, Figure SortD) and Sort_IRan_BSP
+ * (Section 5.2, Figure SortRI), both with the duplicate-key handling of
+ * Section 5.1.1. The p BSP processors are simulated one after the other.
+ *
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * may call this library. It shares no code, header or table with the GPU
+ * library; the two are compared on the same inputs.
+ *
+ * Working representation. Every key is first mapped to an unsigned 64-bit
+ * "order key" whose unsigned order is the key order (int32/int64: numeric;
+ * float32: IEEE-754 totalOrder of the bit pattern, so -0 < +0). The sort
+ * carries, with each key, its original index; the caller gathers raw keys and
+ * payloads with the returned permutation.
+ *
+ * Parity status: every function below is pinned by the CPU tests (brute
+ * force on tiny inputs, closed forms of Lemma `balance`, library sorts), except
+ * that the random sample positions of Sort_IRan_BSP cannot be compared with the
+ * paper's own runs (its generator is not given): parity unpinned for the
+ * choice of RAN sample, self-consistent only.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+#define ORA_OK 0
+#define ORA_EINVAL 1
+#define ORA_ENOMEM 2
+
+enum { ORA_DET = 0, ORA_RAN = 1 };
+
+/* ------------------------------------------------------------------------ */
+/* Key order                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* int32: two's complement numeric order == unsigned order after flipping the sign bit. */
+uint64_t ora_order_i32(int32_t v) { return (uint64_t)((uint32_t)v ^ 0x80000000u); }
+
+/* int64: same, 64-bit. */
+uint64_t ora_order_i64(int64_t v) { return (uint64_t)v ^ 0x8000000000000000ull; }
+
+/* float32 bits: negative patterns are reversed (all bits flipped), non-negative
+ * ones get the sign bit set, which is IEEE-754 totalOrder on the bit pattern. */
+uint64_t ora_order_f32(uint32_t bits) {
+    return (bits & 0x80000000u) ? (uint64_t)(uint32_t)~bits : (uint64_t)(bits | 0x80000000u);
+}
+
+/* kind: 0 int32, 1 int64, 2 float32 (raw bits). */
+void ora_order_keys(int kind, const void* keys, int64_t n, uint64_t* out) {
+    for (int64_t i = 0; i < n; i++) {
+        if (kind == 0) out[i] = ora_order_i32(((const int32_t*)keys)[i]);
+        else if (kind == 1) out[i] = ora_order_i64(((const int64_t*)keys)[i]);
+        else out[i] = ora_order_f32(((const uint32_t*)keys)[i]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Keyed permutation for the random sample                                   */
+/* ------------------------------------------------------------------------ */
+
+/* SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014). */
+uint64_t ora_mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* A permutation of [0, n): a 4-round balanced Feistel network on 2h bits
+ * (2h >= ceil(log2 n)), round function mix64(seed + golden*(round+1) + right),
+ * restricted to [0, n) by cycle walking (Black & Rogaway 2002). */
+int64_t ora_feistel(uint64_t seed, int64_t n, int64_t t) {
+    if (n <= 1) return 0;
+    int bits = 0;
+    while (((int64_t)1 << bits) < n) bits++;
+    int h = (bits + 1) / 2;
+    uint64_t mask = ((uint64_t)1 << h) - 1;
+    uint64_t x = (uint64_t)t;
+    do {
+        uint64_t L = x >> h, R = x & mask;
+        for (uint64_t j = 0; j < 4; j++) {
+            uint64_t f = ora_mix64(seed + 0x9E3779B97F4A7C15ull * (j + 1) + R) & mask;
+            uint64_t nl = R;
+            R = L ^ f;
+            L = nl;
+        }
+        x = (L << h) | R;
+    } while (x >= (uint64_t)n);
+    return (int64_t)x;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Records: a key tagged with its position g in the block-sorted array       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { uint64_t key; int64_t pos; } rec_t;
+
+/* Record order of the duplicate handling (Section 5.1.1): key first, then
+ * the tag. With contiguous blocks the tag (processor, local index) orders
+ * exactly like the global position g in the block-sorted array. */
+static int rec_less(rec_t a, rec_t b) { return a.key < b.key || (a.key == b.key && a.pos < b.pos); }
+
+static int rec_cmp(const void* pa, const void* pb) {
+    rec_t a = *(const rec_t*)pa, b = *(const rec_t*)pb;
+    if (rec_less(a, b)) return -1;
+    if (rec_less(b, a)) return 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step O0/O1: validation and blocks                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Processor k owns positions [ora_block_start(k), ora_block_start(k+1)):
+ * the input is evenly distributed, sizes differ by at most one. */
+int64_t ora_block_start(int64_t n, int p, int k) { return (int64_t)(((__int128)k * n) / p); }
+
+int ora_validate(int64_t n, int p, int s, int variant) {
+    if (n < 0 || p < 1 || s < 1) return ORA_EINVAL;
+    if ((int64_t)p > (n > 1 ? n : 1)) return ORA_EINVAL;       /* the method needs p <= n */
+    if (variant != ORA_DET && variant != ORA_RAN) return ORA_EINVAL;
+    if (variant == ORA_RAN && (int64_t)s * p - 1 > n) return ORA_EINVAL;  /* without replacement */
+    return ORA_OK;
+}
+
+int64_t ora_sample_size(int p, int s, int variant) {
+    return variant == ORA_DET ? (int64_t)p * s : (int64_t)p * s - 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step O2: local sort (Figure SortD steps 2-3; Sort_Seq must be stable)      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { uint64_t key; int64_t idx; } item_t;
+
+static int item_cmp(const void* pa, const void* pb) {
+    const item_t* a = (const item_t*)pa;
+    const item_t* b = (const item_t*)pb;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    return a->idx < b->idx ? -1 : (a->idx > b->idx ? 1 : 0);  /* ties keep input order */
+}
+
+/* B_key/B_idx receive the block-sorted keys and the original index of each. */
+static void local_sort(const uint64_t* ok, int64_t n, int p, uint64_t* B_key, int64_t* B_idx, item_t* tmp) {
+    for (int k = 0; k < p; k++) {
+        int64_t a = ora_block_start(n, p, k), b = ora_block_start(n, p, k + 1);
+        for (int64_t g = a; g < b; g++) { tmp[g - a].key = ok[g]; tmp[g - a].idx = g; }
+        qsort(tmp, (size_t)(b - a), sizeof(item_t), item_cmp);
+        for (int64_t g = a; g < b; g++) { B_key[g] = tmp[g - a].key; B_idx[g] = tmp[g - a].idx; }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Step O3: sample extraction                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Regular oversampling (Figure SortD step 4; proof of Lemma `balance`):
+ * block k of size m_k is cut into s segments of x = ceil(ceil(n/p)/s) keys,
+ * the key closing each segment is taken, and the last one is the block
+ * maximum. Positions past the end of a short block are clamped to its last
+ * key, which stands in for the padding by the maximum key of the proof. */
+static void det_sample(const uint64_t* B_key, int64_t n, int p, int s, rec_t* smp) {
+    int64_t m = (n + p - 1) / p;
+    int64_t x = (m + s - 1) / s;
+    int64_t t = 0;
+    for (int k = 0; k < p; k++) {
+        int64_t a = ora_block_start(n, p, k), mk = ora_block_start(n, p, k + 1) - a;
+        for (int64_t j = 1; j <= s; j++) {
+            int64_t q = j * x < mk ? j * x : mk;
+            smp[t].pos = a + q - 1;
+            smp[t].key = B_key[a + q - 1];
+            t++;
+        }
+    }
+}
+
+/* Random oversampling (Figure SortRI step 4): s*p - 1 distinct positions of
+ * the block-sorted array, drawn uniformly without replacement as the images
+ * of 0..s*p-2 under a keyed permutation of [0, n). */
+static void ran_sample(const uint64_t* B_key, int64_t n, int p, int s, uint64_t seed, rec_t* smp) {
+    int64_t ns = (int64_t)s * p - 1;
+    for (int64_t t = 0; t < ns; t++) {
+        int64_t g = ora_feistel(seed, n, t);
+        smp[t].pos = g;
+        smp[t].key = B_key[g];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Steps O4-O6: sample sort, splitters, bucket of every record               */
+/* ------------------------------------------------------------------------ */
+
+/* Number of splitters strictly below record r: the splitters are sorted, so
+ * this is a lower-bound search (records equal to a splitter go left). */
+static int64_t bucket_of(rec_t r, const rec_t* S, int64_t nsplit) {
+    int64_t lo = 0, hi = nsplit;  /* answer in [lo, hi] */
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (rec_less(S[mid], r)) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole method                                                               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * ora_sort: sorts n order keys with p simulated processors and oversampling
+ * parameter s (the splitter stride of the sorted sample).
+ *   perm[j]     original index of output element j (required)
+ *   B_idx[g]    original index of the block-sorted array element g (optional)
+ *   smp_key/pos sorted sample records (optional, ora_sample_size entries)
+ *   spl_key/pos the p-1 splitters (optional)
+ *   C[k*p+i]    keys of processor k that fall in bucket i (optional)
+ *   Z_idx[j]    original index of element j after routing (optional)
+ * Returns ORA_OK, ORA_EINVAL (arguments) or ORA_ENOMEM.
+ */
+int ora_sort(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t seed,
+             int64_t* perm, int64_t* B_idx_out, uint64_t* smp_key, int64_t* smp_pos,
+             uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out) {
+    int rc = ora_validate(n, p, s, variant);
+    if (rc) return rc;
+    if (n <= 1) {
+        if (n == 1) perm[0] = 0;
+        if (n == 1 && B_idx_out) B_idx_out[0] = 0;
+        if (n == 1 && Z_idx_out) Z_idx_out[0] = 0;
+        if (C_out) C_out[0] = n;
+        int64_t ns = n == 1 ? ora_sample_size(p, s, variant) : 0;
+        for (int64_t t = 0; t < ns; t++) {
+            if (smp_key) smp_key[t] = ok[0];
+            if (smp_pos) smp_pos[t] = 0;
+        }
+        return ORA_OK;
+    }
+    int64_t ns = ora_sample_size(p, s, variant);
+    uint64_t* B_key = (uint64_t*)malloc(sizeof(uint64_t) * n);
+    int64_t* B_idx = (int64_t*)malloc(sizeof(int64_t) * n);
+    item_t* tmp = (item_t*)malloc(sizeof(item_t) * ((n + p - 1) / p));
+    rec_t* smp = (rec_t*)malloc(sizeof(rec_t) * (ns > 0 ? ns : 1));
+    rec_t* S = (rec_t*)malloc(sizeof(rec_t) * p);
+    int64_t* C = (int64_t*)calloc((size_t)p * p, sizeof(int64_t));
+    int64_t* off = (int64_t*)malloc(sizeof(int64_t) * p * p);
+    int64_t* Z_idx = (int64_t*)malloc(sizeof(int64_t) * n);
+    uint64_t* Z_key = (uint64_t*)malloc(sizeof(uint64_t) * n);
+    int64_t* bucket = (int64_t*)malloc(sizeof(int64_t) * n);
+    if (!B_key || !B_idx || !tmp || !smp || !S || !C || !off || !Z_idx || !Z_key || !bucket) {
+        rc = ORA_ENOMEM;
+        goto done;
+    }
+
+    /* O2: every processor sorts its share (stable). */
+    local_sort(ok, n, p, B_key, B_idx, tmp);
+    if (B_idx_out) memcpy(B_idx_out, B_idx, sizeof(int64_t) * n);
+
+    /* O3: sample. O4: sort it by (key, tag). */
+    if (variant == ORA_DET) det_sample(B_key, n, p, s, smp);
+    else ran_sample(B_key, n, p, s, seed, smp);
+    qsort(smp, (size_t)ns, sizeof(rec_t), rec_cmp);
+    for (int64_t t = 0; t < ns; t++) {
+        if (smp_key) smp_key[t] = smp[t].key;
+        if (smp_pos) smp_pos[t] = smp[t].pos;
+    }
+
+    /* O5: p-1 evenly spaced splitters, the sample records at 1-based ranks
+     * s, 2s, ..., (p-1)s (Figure SortD step 6, Figure SortRI step 7). */
+    for (int i = 1; i < p; i++) S[i - 1] = smp[(int64_t)i * s - 1];
+    for (int i = 1; i < p; i++) {
+        if (spl_key) spl_key[i - 1] = S[i - 1].key;
+        if (spl_pos) spl_pos[i - 1] = S[i - 1].pos;
+    }
+
+    /* O6: partition each processor's sorted keys by the splitters
+     * (Figure SortD step 9) and count C[k][i]. */
+    for (int k = 0; k < p; k++) {
+        int64_t a = ora_block_start(n, p, k), b = ora_block_start(n, p, k + 1);
+        int64_t prev = 0;
+        for (int64_t g = a; g < b; g++) {
+            rec_t r = {B_key[g], g};
+            int64_t bk = bucket_of(r, S, p - 1);
+            if (bk < prev) { rc = ORA_EINVAL; goto done; }  /* cannot happen: block is sorted */
+            prev = bk;
+            bucket[g] = bk;
+            C[(int64_t)k * p + bk]++;
+        }
+    }
+    if (C_out) memcpy(C_out, C, sizeof(int64_t) * p * p);
+
+    /* O7: the p independent prefix computations: bucket i starts after all
+     * smaller buckets, and within bucket i the keys from processor k follow
+     * those of processors 0..k-1. */
+    {
+        int64_t base = 0;
+        for (int i = 0; i < p; i++) {
+            int64_t run = base;
+            for (int k = 0; k < p; k++) {
+                off[(int64_t)k * p + i] = run;
+                run += C[(int64_t)k * p + i];
+            }
+            base = run;
+        }
+    }
+
+    /* O8: routing, order preserving (Figure SortD steps 10-11). */
+    {
+        int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * p * p);
+        if (!cur) { rc = ORA_ENOMEM; goto done; }
+        memcpy(cur, off, sizeof(int64_t) * p * p);
+        for (int k = 0; k < p; k++) {
+            int64_t a = ora_block_start(n, p, k), b = ora_block_start(n, p, k + 1);
+            for (int64_t g = a; g < b; g++) {
+                int64_t d = cur[(int64_t)k * p + bucket[g]]++;
+                Z_key[d] = B_key[g];
+                Z_idx[d] = B_idx[g];
+            }
+        }
+        free(cur);
+    }
+    if (Z_idx_out) memcpy(Z_idx_out, Z_idx, sizeof(int64_t) * n);
+
+    /* O9: every processor merges the sorted runs it received; on equal keys
+     * the run from the lower-numbered processor goes first (Section 5.1.1).
+     * A binary heap over the p run heads, ordered by (key, source). */
+    {
+        int* heap = (int*)malloc(sizeof(int) * p);
+        int64_t* head = (int64_t*)malloc(sizeof(int64_t) * p);
+        int64_t* end = (int64_t*)malloc(sizeof(int64_t) * p);
+        if (!heap || !head || !end) { free(heap); free(head); free(end); rc = ORA_ENOMEM; goto done; }
+        int64_t outpos = 0;
+        for (int i = 0; i < p; i++) {
+            int hn = 0;
+            for (int k = 0; k < p; k++) {
+                head[k] = off[(int64_t)k * p + i];
+                end[k] = head[k] + C[(int64_t)k * p + i];
+                if (head[k] < end[k]) {
+                    /* sift up */
+                    int c = hn++;
+                    heap[c] = k;
+                    while (c > 0) {
+                        int par = (c - 1) / 2;
+                        int u = heap[c], v = heap[par];
+                        int less = Z_key[head[u]] < Z_key[head[v]] ||
+                                   (Z_key[head[u]] == Z_key[head[v]] && u < v);
+                        if (!less) break;
+                        heap[c] = v; heap[par] = u; c = par;
+                    }
+                }
+            }
+            while (hn > 0) {
+                int k = heap[0];
+                perm[outpos++] = Z_idx[head[k]];
+                head[k]++;
+                if (head[k] == end[k]) heap[0] = heap[--hn];
+                /* sift down */
+                int c = 0;
+                for (;;) {
+                    int l = 2 * c + 1, r = l + 1, m = c;
+                    if (l < hn) {
+                        int u = heap[l], v = heap[m];
+                        if (Z_key[head[u]] < Z_key[head[v]] || (Z_key[head[u]] == Z_key[head[v]] && u < v)) m = l;
+                    }
+                    if (r < hn) {
+                        int u = heap[r], v = heap[m];
+                        if (Z_key[head[u]] < Z_key[head[v]] || (Z_key[head[u]] == Z_key[head[v]] && u < v)) m = r;
+                    }
+                    if (m == c) break;
+                    int t = heap[c]; heap[c] = heap[m]; heap[m] = t; c = m;
+                }
+            }
+        }
+        free(heap); free(head); free(end);
+    }
+
+done:
+    free(B_key); free(B_idx); free(tmp); free(smp); free(S); free(C); free(off);
+    free(Z_idx); free(Z_key); free(bucket);
+    return rc;
+}
+
+/* Bucket of each record (key, g) of a block-sorted array against given
+ * splitters: the definition used by step O6, exported so that a per-key GPU
+ * ranking can be compared against it. */
+void ora_rank(const uint64_t* B_key, int64_t n, const uint64_t* spl_key, const int64_t* spl_pos,
+              int nsplit, int64_t* bucket) {
+    rec_t* S = (rec_t*)malloc(sizeof(rec_t) * (nsplit > 0 ? nsplit : 1));
+    for (int i = 0; i < nsplit; i++) { S[i].key = spl_key[i]; S[i].pos = spl_pos[i]; }
+    for (int64_t g = 0; g < n; g++) {
+        rec_t r = {B_key[g], g};
+        bucket[g] = bucket_of(r, S, nsplit);
+    }
+    free(S);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Learned bucketing reference (not in the paper): a two-stage CDF model      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The model maps a key to a predicted bucket; the exact splitter check then
+ * corrects it, so it only affects speed. Definitions (double precision):
+ *   x(u)  = (u - lo) / (hi - lo) for an order key u, lo/hi the smallest and
+ *           largest sorted-sample key (x = 0 when hi == lo)
+ *   root  r(x) = a (x - mu_r) + b ; leaf(x) = clamp(floor(L r(x)), 0, L-1)
+ *   leaf  f_l(x) = c_l (x - mu_l) + d_l ; bucket(x) = clamp(floor(p f), 0, p-1)
+ * Training data: the sorted sample, record t with target y_t = (t+0.5)/(p s),
+ * whose bucket under the splitter rule is floor(t/s).
+ * Loss: (1/N) sum_t (f(x_t) - y_t)^2 over the N sample records.
+ */
+
+/* Gradient and Gram (Hessian) sums of the loss of one linear model
+ * f(x) = c (x - mu) + d over the records t with leaf[t] == l, for all L
+ * models at once. Outputs per model (all scaled by 2/N):
+ *   g[2l]   = dLoss/dc, g[2l+1] = dLoss/dd
+ *   h[3l..] = (sum (x-mu)^2, sum (x-mu), count)
+ * Also returns the loss. */
+double ora_rmi_grad(const double* x, const double* y, const int32_t* leaf, int64_t N, int L,
+                    const double* c, const double* d, const double* mu, double* g, double* h) {
+    double loss = 0.0;
+    for (int l = 0; l < L; l++) { g[2 * l] = g[2 * l + 1] = 0.0; h[3 * l] = h[3 * l + 1] = h[3 * l + 2] = 0.0; }
+    for (int64_t t = 0; t < N; t++) {
+        int l = leaf[t];
+        double dx = x[t] - mu[l];
+        double r = c[l] * dx + d[l] - y[t];
+        loss += r * r;
+        g[2 * l] += r * dx;
+        g[2 * l + 1] += r;
+        h[3 * l] += dx * dx;
+        h[3 * l + 1] += dx;
+        h[3 * l + 2] += 1.0;
+    }
+    double sc = N > 0 ? 2.0 / (double)N : 0.0;
+    for (int l = 0; l < L; l++) {
+        g[2 * l] *= sc; g[2 * l + 1] *= sc;
+        h[3 * l] *= sc; h[3 * l + 1] *= sc; h[3 * l + 2] *= sc;
+    }
+    return N > 0 ? loss / (double)N : 0.0;
+}
+
+/* One Newton step per model from gradient g and Gram h: for a quadratic loss
+ * this lands on the least-squares solution. A model whose Gram matrix is
+ * singular (fewer than two distinct x) only moves its intercept; a model with
+ * no records keeps its parameters. */
+void ora_rmi_newton(int L, const double* g, const double* h, double* c, double* d) {
+    for (int l = 0; l < L; l++) {
+        double sxx = h[3 * l], sx = h[3 * l + 1], sn = h[3 * l + 2];
+        if (sn <= 0.0) continue;
+        double det = sxx * sn - sx * sx;
+        if (det > 1e-300 && sxx > 0.0 && det > 1e-12 * sxx * sn) {
+            double dc = (sn * g[2 * l] - sx * g[2 * l + 1]) / det;
+            double dd = (-sx * g[2 * l] + sxx * g[2 * l + 1]) / det;
+            c[l] -= dc;
+            d[l] -= dd;
+        } else {
+            d[l] -= g[2 * l + 1] / sn;
+        }
+    }
+}
+
+/* Full reference fit on sorted sample order keys; writes the model.
+ * root: (a, b, mu_r); leaves: c[L], d[L], mu[L]; lo/hi as defined above.
+ * Leaves with no sample take c = 0 and d = (number of samples in lower
+ * leaves) / (p s), so that they predict the bucket where their keys belong. */
+void ora_rmi_fit(const uint64_t* smp_key, int64_t N, int p, int s, int L, int iters,
+                 double* root3, double* c, double* d, double* mu, double* lohi) {
+    double lo = N ? (double)smp_key[0] : 0.0, hi = N ? (double)smp_key[N - 1] : 0.0;
+    double inv = hi > lo ? 1.0 / (hi - lo) : 0.0;
+    lohi[0] = lo; lohi[1] = hi;
+    double* x = (double*)malloc(sizeof(double) * (N ? N : 1));
+    double* y = (double*)malloc(sizeof(double) * (N ? N : 1));
+    int32_t* lf = (int32_t*)malloc(sizeof(int32_t) * (N ? N : 1));
+    double* g = (double*)malloc(sizeof(double) * 2 * (L > 1 ? L : 1));
+    double* h = (double*)malloc(sizeof(double) * 3 * (L > 1 ? L : 1));
+    for (int64_t t = 0; t < N; t++) {
+        x[t] = ((double)smp_key[t] - lo) * inv;
+        y[t] = ((double)t + 0.5) / ((double)p * (double)s);
+        lf[t] = 0;
+    }
+    /* root */
+    double mur = 0.0;
+    for (int64_t t = 0; t < N; t++) mur += x[t];
+    mur = N ? mur / (double)N : 0.0;
+    double ra = 0.0, rb = 0.0;
+    for (int it = 0; it < iters; it++) {
+        double gg[2], hh[3];
+        ora_rmi_grad(x, y, lf, N, 1, &ra, &rb, &mur, gg, hh);
+        ora_rmi_newton(1, gg, hh, &ra, &rb);
+    }
+    root3[0] = ra; root3[1] = rb; root3[2] = mur;
+    /* leaf assignment by the fitted root */
+    for (int64_t t = 0; t < N; t++) {
+        double r = ra * (x[t] - mur) + rb;
+        double f = floor(r * (double)L);
+        lf[t] = f < 0 ? 0 : (f > L - 1 ? L - 1 : (int32_t)f);
+    }
+    /* leaf centres: mean x of the leaf's records */
+    int64_t* cnt = (int64_t*)calloc((size_t)L, sizeof(int64_t));
+    for (int l = 0; l < L; l++) { mu[l] = 0.0; c[l] = 0.0; d[l] = 0.0; }
+    for (int64_t t = 0; t < N; t++) { mu[lf[t]] += x[t]; cnt[lf[t]]++; }
+    for (int l = 0; l < L; l++) mu[l] = cnt[l] ? mu[l] / (double)cnt[l] : 0.0;
+    for (int it = 0; it < iters; it++) {
+        ora_rmi_grad(x, y, lf, N, L, c, d, mu, g, h);
+        ora_rmi_newton(L, g, h, c, d);
+    }
+    int64_t below = 0;
+    for (int l = 0; l < L; l++) {
+        if (cnt[l] == 0) { c[l] = 0.0; d[l] = (double)below / ((double)p * (double)s); }
+        below += cnt[l];
+    }
+    free(cnt); free(x); free(y); free(lf); free(g); free(h);
+}
+
+/* Predicted bucket of an order key under a fitted model (double precision). */
+int64_t ora_rmi_predict(uint64_t u, int p, int L, const double* root3, const double* c, const double* d,
+                        const double* mu, const double* lohi) {
+    double inv = lohi[1] > lohi[0] ? 1.0 / (lohi[1] - lohi[0]) : 0.0;
+    double x = ((double)u - lohi[0]) * inv;
+    double r = root3[0] * (x - root3[2]) + root3[1];
+    double fl = floor(r * (double)L);
+    int l = fl < 0 ? 0 : (fl > L - 1 ? L - 1 : (int)fl);
+    double f = c[l] * (x - mu[l]) + d[l];
+    double fb = floor(f * (double)p);
+    return fb < 0 ? 0 : (fb > p - 1 ? p - 1 : (int64_t)fb);
+}
