@@ -1,0 +1,207 @@
+/*
+ * bsps.h -- C ABI of the MI355X BSP sample sort library (libbsps.so).
+ *
+ * The library sorts keys on one GPU with the deterministic regular-
+ * oversampling method Sort_Det_BSP (Gerbessiotis & Siniolakis, Section 5.1,
+ * Figure SortD) or its randomized oversampling variant Sort_IRan_BSP
+ * (Section 5.2, Figure SortRI), both with the duplicate-key handling of
+ * Section 5.1.1. The paper's p BSP processors are p virtual processors on one
+ * GPU: processor k owns the contiguous block [floor(k n / p), floor((k+1) n / p))
+ * of the input and bucket k of the output.
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless a comment says HOST. The caller owns
+ *    all memory; the library allocates no device memory on any sort path and
+ *    frees nothing it did not allocate.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream). Work is
+ *    enqueued asynchronously and the call returns after enqueueing, except in
+ *    diagnostic mode (a non-NULL bsps_stats*), where the call synchronizes the
+ *    stream before it returns so that the statistics can be filled.
+ *  - Every argument check is done on the host before any HIP call; a rejected
+ *    call leaves all buffers untouched. Return codes only, no exceptions.
+ *  - Key order: int32 and int64 keys sort numerically; float32 keys sort by
+ *    IEEE-754 totalOrder of their bit patterns (-0 < +0; NaN patterns sort
+ *    outside the finite values, -NaN first and +NaN last).
+ *  - The result is the STABLE ascending order: equal keys keep their input
+ *    order, which is exactly the order the paper's tie rule (processor
+ *    identifier, then local index, Section 5.1.1) produces.
+ *  - Limits: n < 2^32 - 1 (positions are 32-bit), 1 <= p <= 4096.
+ */
+#ifndef BSPS_H
+#define BSPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSPS_OK = 0,
+    BSPS_EINVAL = 1,       /* an argument is out of range (see each call) */
+    BSPS_EWORKSPACE = 2,   /* workspace NULL or smaller than bsps_workspace_bytes() */
+    BSPS_EDEVICE = 3,      /* a HIP call failed */
+    BSPS_EUNSUPPORTED = 4  /* valid but outside the library limits (n, p) */
+} bsps_status;
+
+typedef enum { BSPS_DET = 0, BSPS_RAN = 1 } bsps_variant;
+typedef enum { BSPS_I32 = 0, BSPS_I64 = 1, BSPS_F32 = 2 } bsps_dtype;
+
+/* How keys are assigned to buckets when every key is ranked on its own. */
+typedef enum {
+    BSPS_SPLITTER = 0,  /* branch-free binary search of the splitters held in LDS */
+    BSPS_LEARNED = 1    /* CDF model prediction, then the exact splitter check */
+} bsps_bucketing;
+
+/* How the sorted blocks reach their buckets (Figure SortD steps 9-12). */
+typedef enum {
+    /* Bucket boundaries come from binary searches of the splitters into each
+     * sorted block (the paper's own choice, Section 5.2, Figure SortRI), and the
+     * routing is carried out by the final per-bucket merge, which reads each
+     * run where it lies in the block-sorted array. */
+    BSPS_ROUTE_FUSED = 0,
+    /* Every key is ranked against the splitters (or the learned model), the
+     * p x p counts are prefix-summed and the keys are scattered into their
+     * buckets before the per-bucket merge. */
+    BSPS_ROUTE_SCATTER = 1
+} bsps_route;
+
+typedef struct bsps_params {
+    int32_t p;          /* virtual processors = blocks = buckets; 1 <= p <= max(n, 1) */
+    int32_t s;          /* oversampling: sample records per bucket, i.e. the splitter
+                           stride in the sorted sample. DET draws s keys per block
+                           (p*s in all); RAN draws s*p - 1 keys. s >= 1. */
+    int32_t variant;    /* bsps_variant */
+    int32_t bucketing;  /* bsps_bucketing; applies to route = BSPS_ROUTE_SCATTER */
+    int32_t route;      /* bsps_route */
+    int32_t leaves;     /* learned model: leaf models (0 = 4096) */
+    uint64_t seed;      /* RAN: key of the sample permutation */
+    int32_t chunk_cap;  /* 0 = default. Largest merge chunk sorted in LDS; a smaller
+                           value routes more chunks through the global-memory path
+                           (used to test that path). */
+    int32_t reserved[7];/* must be zero */
+} bsps_params;
+
+/*
+ * Diagnostic statistics, HOST memory. Every pointer member may be NULL (not
+ * filled). Passing a non-NULL bsps_stats* makes the call synchronous.
+ */
+typedef struct bsps_stats {
+    void* splitter_keys;       /* p-1 keys of the call's dtype */
+    int64_t* splitter_pos;     /* p-1 tags: positions in the block-sorted array */
+    void* sample_keys;         /* sorted sample: DET p*s, RAN p*s-1 keys */
+    int64_t* sample_pos;       /* their positions in the block-sorted array */
+    int64_t* bucket_sizes;     /* p */
+    int64_t* count_matrix;     /* p*p, row k = source block, column i = bucket */
+    void* block_sorted;        /* n keys: every block sorted (Figure SortD step 3) */
+    uint32_t* block_sorted_values; /* n payloads, kv calls only */
+    void* routed;              /* n keys after routing (route = SCATTER only) */
+    uint32_t* buckets;         /* n bucket ids of block_sorted (route = SCATTER only) */
+    double max_bucket_ratio;   /* largest bucket / (n/p) */
+    double mispredict_rate;    /* learned bucketing: fraction of keys corrected */
+    double mean_fix_dist;      /* learned bucketing: mean |predicted - true| */
+    int64_t oversize_chunks;   /* merge chunks sorted by the global-memory path */
+    int64_t reserved_i[4];
+} bsps_stats;
+
+/* Bytes of device workspace a sort of n keys needs (values: 0 or 1). Returns
+ * 0 for invalid arguments. */
+size_t bsps_workspace_bytes(int64_t n, int32_t dtype, int32_t with_values, const bsps_params* prm);
+
+/*
+ * Sort n keys in place (Figure SortD / Figure SortRI).
+ *  keys      device, n keys of `dtype`; replaced by the sorted keys
+ *  ws        device workspace of ws_bytes >= bsps_workspace_bytes(n, dtype, 0, prm)
+ * Errors: EINVAL for n < 0, p < 1, p > max(n, 1), s < 1, RAN with s*p - 1 > n,
+ * unknown dtype/variant/route/bucketing, leaves < 0, nonzero reserved fields;
+ * EWORKSPACE; EUNSUPPORTED for n >= 2^32 - 1 or p > 4096. n = 0 and n = 1 are
+ * valid no-ops.
+ */
+bsps_status bsps_sort(void* keys, int64_t n, int32_t dtype, const bsps_params* prm,
+                      void* ws, size_t ws_bytes, void* stream, bsps_stats* st);
+
+/* As bsps_sort, carrying a uint32 payload per key (values, device, n); equal
+ * keys keep their input order, so payloads of equal keys keep theirs. */
+bsps_status bsps_sort_kv(void* keys, uint32_t* values, int64_t n, int32_t dtype, const bsps_params* prm,
+                         void* ws, size_t ws_bytes, void* stream, bsps_stats* st);
+
+/*
+ * Sort nseg independent segments [h_offsets[i], h_offsets[i+1]) of one key
+ * array (and payload array if values != NULL), each with its own (p, s)
+ * chosen per size class by the built-in tuning table or by tuning_json. All
+ * segments go through one captured graph launch.
+ *  h_offsets   HOST, nseg + 1 non-decreasing entries, h_offsets[0] = 0
+ *  tuning_json HOST, NULL for the built-in table (format: bsps_tuning_format())
+ * Errors: EINVAL for nseg < 0, offsets not non-decreasing or not starting at 0,
+ * unknown dtype, malformed tuning_json; EWORKSPACE; EUNSUPPORTED as bsps_sort.
+ */
+bsps_status bsps_sort_segmented(void* keys, uint32_t* values, const int64_t* h_offsets, int32_t nseg,
+                                int32_t dtype, const char* tuning_json, void* ws, size_t ws_bytes,
+                                void* stream, bsps_stats* st);
+size_t bsps_segmented_workspace_bytes(const int64_t* h_offsets, int32_t nseg, int32_t dtype,
+                                      int32_t with_values, const char* tuning_json);
+
+/*
+ * Bucket of every key of a block-sorted array (Figure SortD step 9, tie rule
+ * of Section 5.1.1): bucket(g) = number of splitter records (key, tag) that
+ * are strictly below the record (keys[g], g).
+ *  keys        device, n keys of dtype, every block of the p-way split sorted
+ *  spl_keys    device, p-1 keys of dtype; spl_pos device, p-1 uint32 tags
+ *  model       device learned model from bsps_fit_model (bucketing = LEARNED),
+ *              ignored for SPLITTER
+ *  out_bucket  device, n uint32 (may be NULL)
+ *  out_counts  device, p*p uint32 count matrix, row = block (may be NULL)
+ *  st          HOST, optional: mispredict_rate / mean_fix_dist (synchronizes)
+ * Errors: EINVAL as bsps_sort, or model NULL with LEARNED; EWORKSPACE.
+ */
+bsps_status bsps_rank(const void* keys, int64_t n, int32_t dtype, int32_t p, const void* spl_keys,
+                      const uint32_t* spl_pos, int32_t bucketing, const void* model,
+                      uint32_t* out_bucket, uint32_t* out_counts, void* ws, size_t ws_bytes,
+                      void* stream, bsps_stats* st);
+size_t bsps_rank_workspace_bytes(int64_t n, int32_t p);
+
+/*
+ * Learned bucketing model (not in the paper): a linear root model choosing one
+ * of L linear leaf models of the cumulative distribution, trained on the
+ * sorted sample by the library's forward, backward (gradient and Gram sums)
+ * and Newton-update kernels. Layout of the device model buffer
+ * (bsps_model_bytes(L) bytes, float32 unless noted):
+ *   [0] lo, [1] hi as float64 (order-key range of the sample, 16 bytes)
+ *   then root a, b, mu_r, inv_range (4 floats), then L triples (c, d, mu).
+ * A leaf predicts c * (x - mu) + d for x = (u - lo) * inv_range.
+ *  smp_keys  device, N sorted keys of dtype (the sorted sample)
+ *  N, p, s   sample size and sort parameters (targets y_t = (t + 0.5) / (p s))
+ *  iters     Newton iterations per stage (>= 1)
+ *  model     device, bsps_model_bytes(L)
+ */
+size_t bsps_model_bytes(int32_t leaves);
+bsps_status bsps_fit_model(const void* smp_keys, int64_t N, int32_t dtype, int32_t p, int32_t s,
+                           int32_t leaves, int32_t iters, void* model, void* ws, size_t ws_bytes,
+                           void* stream);
+size_t bsps_fit_workspace_bytes(int64_t N, int32_t leaves);
+
+/*
+ * One forward + backward evaluation of the leaf stage for the gradient check:
+ * for the N sorted sample keys and the model's current root and leaf
+ * parameters, writes out_leaf[t] (device, N int32), out_grad (device, 2L
+ * float: dLoss/dc, dLoss/dd per leaf) and out_gram (device, 3L float:
+ * sum (x-mu)^2, sum (x-mu), count, all times 2/N), and the loss to *out_loss
+ * (device, 1 float). Loss = (1/N) sum_t (f(x_t) - y_t)^2.
+ */
+bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int32_t p, int32_t s,
+                            int32_t leaves, const void* model, int32_t* out_leaf, float* out_grad,
+                            float* out_gram, float* out_loss, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* bsps_status_string(int32_t status);
+/* Format of the tuning table accepted by bsps_sort_segmented (static storage). */
+const char* bsps_tuning_format(void);
+/* Frees the library's cached graph executables (its only owned state). */
+void bsps_release_cache(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSPS_H */

@@ -1,0 +1,167 @@
+"""MI355X BSP sample sort: Python binding of libbsps.so (ctypes).
+
+Argument marshalling only: every step of the sort runs in the library's HIP
+kernels on the tensor's GPU. Device memory (keys, payload, workspace) comes
+from torch on the tensor's device; the work is enqueued on
+torch.cuda.current_stream(). The library must have been built
+(`python -m paper_1408_6729_amd.build` or `__graft_entry__.build()`);
+importing this package fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsps.so")
+
+OK, EINVAL, EWORKSPACE, EDEVICE, EUNSUPPORTED = 0, 1, 2, 3, 4
+DET, RAN = 0, 1
+I32, I64, F32 = 0, 1, 2
+SPLITTER, LEARNED = 0, 1
+ROUTE_FUSED, ROUTE_SCATTER = 0, 1
+
+
+class BspsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {status_string(code)} (status {code})")
+        self.code = code
+
+
+class Params(ct.Structure):
+    _fields_ = [("p", ct.c_int32), ("s", ct.c_int32), ("variant", ct.c_int32), ("bucketing", ct.c_int32),
+                ("route", ct.c_int32), ("leaves", ct.c_int32), ("seed", ct.c_uint64),
+                ("chunk_cap", ct.c_int32), ("reserved", ct.c_int32 * 7)]
+
+
+class Stats(ct.Structure):
+    _fields_ = [("splitter_keys", ct.c_void_p), ("splitter_pos", ct.c_void_p), ("sample_keys", ct.c_void_p),
+                ("sample_pos", ct.c_void_p), ("bucket_sizes", ct.c_void_p), ("count_matrix", ct.c_void_p),
+                ("block_sorted", ct.c_void_p), ("block_sorted_values", ct.c_void_p), ("routed", ct.c_void_p),
+                ("buckets", ct.c_void_p), ("max_bucket_ratio", ct.c_double), ("mispredict_rate", ct.c_double),
+                ("mean_fix_dist", ct.c_double), ("oversize_chunks", ct.c_int64), ("reserved_i", ct.c_int64 * 4)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc --offload-arch=gfx950); there is no CPU fallback")
+    L = ct.CDLL(LIB_PATH)
+    vp, sz, i32, i64 = ct.c_void_p, ct.c_size_t, ct.c_int32, ct.c_int64
+    PP = ct.POINTER(Params)
+    SP = ct.POINTER(Stats)
+    L.bsps_workspace_bytes.restype = sz
+    L.bsps_workspace_bytes.argtypes = [i64, i32, i32, PP]
+    L.bsps_sort.restype = i32
+    L.bsps_sort.argtypes = [vp, i64, i32, PP, vp, sz, vp, SP]
+    L.bsps_sort_kv.restype = i32
+    L.bsps_sort_kv.argtypes = [vp, vp, i64, i32, PP, vp, sz, vp, SP]
+    L.bsps_status_string.restype = ct.c_char_p
+    L.bsps_status_string.argtypes = [i32]
+    return L
+
+
+_lib = _load()
+lib = _lib
+
+EXPORTS = ("bsps_workspace_bytes", "bsps_sort", "bsps_sort_kv", "bsps_sort_segmented",
+           "bsps_segmented_workspace_bytes", "bsps_rank", "bsps_rank_workspace_bytes", "bsps_model_bytes",
+           "bsps_fit_model", "bsps_fit_workspace_bytes", "bsps_model_grad", "bsps_status_string",
+           "bsps_tuning_format", "bsps_release_cache")
+
+
+def status_string(code: int) -> str:
+    return _lib.bsps_status_string(int(code)).decode()
+
+
+def make_params(p: int, s: int, variant: int = DET, seed: int = 1, bucketing: int = SPLITTER,
+                route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0) -> Params:
+    prm = Params()
+    prm.p, prm.s, prm.variant, prm.bucketing = p, s, variant, bucketing
+    prm.route, prm.leaves, prm.seed, prm.chunk_cap = route, leaves, seed & 0xFFFFFFFFFFFFFFFF, chunk_cap
+    return prm
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.int32:
+        return I32
+    if t.dtype == torch.int64:
+        return I64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported key dtype {t.dtype}")
+
+
+def workspace_bytes(n: int, dtype: int, with_values: bool, prm: Params) -> int:
+    return int(_lib.bsps_workspace_bytes(n, dtype, int(with_values), ct.byref(prm)))
+
+
+def _stream(t) -> int:
+    import torch
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, bucketing: int = SPLITTER,
+          route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0, stats: bool = False, workspace=None):
+    """Sorts `keys` (a contiguous int32/int64/float32 CUDA tensor) in place; with
+    `values` (uint32 payload as an int32 tensor of the same length) a key-value
+    sort. With stats=True the call synchronizes and returns the diagnostic
+    statistics (splitters, sample, counts, block-sorted array ...)."""
+    import torch
+    assert keys.is_cuda and keys.is_contiguous() and keys.dim() == 1
+    n = keys.numel()
+    dt = _dtype_code(keys)
+    prm = make_params(p, s, variant, seed, bucketing, route, leaves, chunk_cap)
+    hasv = values is not None
+    if hasv:
+        assert values.is_cuda and values.is_contiguous() and values.numel() == n and values.element_size() == 4
+    need = workspace_bytes(n, dt, hasv, prm)
+    if need == 0:
+        code = _lib.bsps_sort(None, n, dt, ct.byref(prm), None, 0, None, None)
+        raise BspsError(code if code else EINVAL, "bsps_workspace_bytes")
+    ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8, device=keys.device)
+    st = None
+    host = {}
+    if stats:
+        st = Stats()
+        kd = {I32: np.int32, I64: np.int64, F32: np.float32}[dt]
+        ns = p * s if variant == DET else p * s - 1
+        host = {
+            "splitter_keys": np.zeros(max(p - 1, 1), kd), "splitter_pos": np.zeros(max(p - 1, 1), np.int64),
+            "sample_keys": np.zeros(max(ns, 1), kd), "sample_pos": np.zeros(max(ns, 1), np.int64),
+            "bucket_sizes": np.zeros(p, np.int64), "count_matrix": np.zeros(p * p, np.int64),
+            "block_sorted": np.zeros(max(n, 1), kd),
+        }
+        if hasv:
+            host["block_sorted_values"] = np.zeros(max(n, 1), np.uint32)
+        if route == ROUTE_SCATTER:
+            host["routed"] = np.zeros(max(n, 1), kd)
+            host["buckets"] = np.zeros(max(n, 1), np.uint32)
+        for k, arr in host.items():
+            setattr(st, k, arr.ctypes.data)
+    args = (ct.byref(prm), ct.c_void_p(ws.data_ptr()), ws.numel(), ct.c_void_p(_stream(keys)),
+            ct.byref(st) if st is not None else None)
+    if hasv:
+        code = _lib.bsps_sort_kv(ct.c_void_p(keys.data_ptr()), ct.c_void_p(values.data_ptr()), n, dt, *args)
+    else:
+        code = _lib.bsps_sort(ct.c_void_p(keys.data_ptr()), n, dt, *args)
+    if code != OK:
+        raise BspsError(code, "bsps_sort")
+    if not stats:
+        return None
+    out = {k: v for k, v in host.items()}
+    out["splitter_keys"] = out["splitter_keys"][:p - 1]
+    out["splitter_pos"] = out["splitter_pos"][:p - 1]
+    ns = p * s if variant == DET else p * s - 1
+    out["sample_keys"] = out["sample_keys"][:ns]
+    out["sample_pos"] = out["sample_pos"][:ns]
+    out["count_matrix"] = out["count_matrix"].reshape(p, p)
+    out["block_sorted"] = out["block_sorted"][:n]
+    out["max_bucket_ratio"] = st.max_bucket_ratio
+    out["mispredict_rate"] = st.mispredict_rate
+    out["mean_fix_dist"] = st.mean_fix_dist
+    out["oversize_chunks"] = st.oversize_chunks
+    return out

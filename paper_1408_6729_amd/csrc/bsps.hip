@@ -1,0 +1,498 @@
+// bsps.hip -- host pipeline and C ABI of libbsps.so (see include/bsps.h).
+//
+// One call of bsps_sort enqueues, on the caller's stream:
+//   A1 tile sort + block merge           -> B (every block sorted)
+//   A2 DET regular / RAN keyed sample    -> sample records (key, position in B)
+//   A3 sample sort + splitters           -> p-1 splitter records
+//   A4 splitter search into each block   -> cntT (or per-key ranking, SCATTER route)
+//   A5 bucket tables (prefix sums)       -> runs of every bucket
+//   A6 per-bucket multiway merge         -> sorted keys back in the caller's buffer
+// Every device buffer is carved from the caller's workspace; the library never
+// allocates device memory on these paths.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/bsps.h"
+#include "bsps_kernels.h"
+#include "bsps_learned.h"
+
+namespace {
+
+constexpr u32 kSampleStride = 32;  // tile and block samples for the merges: every 32nd key
+constexpr int kMaxP = 4096;
+
+#define HIP_OK(x)                                              \
+    do {                                                       \
+        if ((x) != hipSuccess) return BSPS_EDEVICE;            \
+    } while (0)
+#define LAUNCH_OK()                                            \
+    do {                                                       \
+        if (hipGetLastError() != hipSuccess) return BSPS_EDEVICE; \
+    } while (0)
+
+inline u64 cdiv(u64 a, u64 b) { return (a + b - 1) / b; }
+inline i64 hblk(i64 n, int p, int k) { return (i64)(((u64)k * (u64)n) / (u64)p); }
+
+// Bump allocator over the caller's workspace (256-byte aligned pieces). With
+// base == nullptr it only measures.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <typename T>
+    T* take(u64 count) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += (size_t)count * sizeof(T);
+        return p;
+    }
+};
+
+int key_bytes(int dt) { return dt == BSPS_I64 ? 8 : 4; }
+
+template <typename K> constexpr u32 tileT() { return (u32)(Shape<K>::NT * Shape<K>::IT); }
+
+// Device buffers of one multiway merge.
+template <typename K>
+struct MwmBufs {
+    u32 *run_start, *run_len, *out_base, *sdesc, *counters, *slot_group, *grp_base, *grp_nb, *bpos, *cuts;
+    K* bkey;
+    u32 S;
+    int G, R;
+};
+
+template <typename K>
+void carve_mwm(Carver& c, MwmBufs<K>& m, int G, int R, u64 n, u32 tavg) {
+    m.G = G;
+    m.R = R;
+    m.S = (u32)(n / tavg + (u64)G + 1);
+    m.run_start = c.take<u32>((u64)G * R);
+    m.run_len = c.take<u32>((u64)G * R);
+    m.out_base = c.take<u32>(G);
+    m.sdesc = c.take<u32>((u64)G * R * 4);
+    m.counters = c.take<u32>(2);
+    m.slot_group = c.take<u32>(m.S);
+    m.grp_base = c.take<u32>(G);
+    m.grp_nb = c.take<u32>(G);
+    m.bkey = c.take<K>(m.S);
+    m.bpos = c.take<u32>(m.S);
+    m.cuts = c.take<u32>((u64)m.S * R);
+}
+
+template <typename K>
+MwmArgs<K> mwm_args(const MwmBufs<K>& m, const K* src, const u32* srcv, K* dst, u32* dstv, K* scr, u32* scrv,
+                    const K* smp, u32 cap, u32 tavg, int out_dt, K* osmp, u32 oys, u32 ospb) {
+    MwmArgs<K> a;
+    a.src = src; a.srcv = srcv; a.dst = dst; a.dstv = dstv; a.scr = scr; a.scrv = scrv;
+    a.G = m.G; a.R = m.R;
+    a.run_start = m.run_start; a.run_len = m.run_len; a.out_base = m.out_base; a.sdesc = m.sdesc;
+    a.smp = smp; a.cap = cap; a.tavg = tavg;
+    a.slot_count = m.counters; a.oversize = m.counters + 1;
+    a.slot_group = m.slot_group; a.grp_base = m.grp_base; a.grp_nb = m.grp_nb;
+    a.bkey = m.bkey; a.bpos = m.bpos; a.cuts = m.cuts; a.S = m.S;
+    a.out_dt = out_dt; a.osmp = osmp; a.oys = oys; a.ospb = ospb;
+    return a;
+}
+
+template <typename K, bool HASV>
+bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st) {
+    constexpr int NT = Shape<K>::NT;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.slot_count, 2);
+    LAUNCH_OK();
+    hipLaunchKernelGGL((k_mwm_pick<K>), dim3(a.G), dim3(NT), 0, st, a);
+    LAUNCH_OK();
+    const u64 ncut = (u64)a.S * a.R;
+    hipLaunchKernelGGL((k_mwm_cuts<K>), dim3((u32)cdiv(ncut, 256)), dim3(256), 0, st, a);
+    LAUNCH_OK();
+    hipLaunchKernelGGL((k_mwm_merge<K, HASV>), dim3(a.S), dim3(NT), 0, st, a);
+    LAUNCH_OK();
+    return BSPS_OK;
+}
+
+// ------------------------------------------------------------------ block sort (A1)
+
+// Buffers of one "sort n keys split into p blocks" (the local sort of every
+// virtual processor): tiles, tile samples and the block merge.
+template <typename K>
+struct BlockSortBufs {
+    K* A;            // tile-sorted keys (NULL when every block fits one tile)
+    u32* Av;
+    K* tsmp;         // tile samples
+    MwmBufs<K> mwm;
+    int tpb;
+    u32 spt;
+};
+
+template <typename K>
+void carve_block_sort(Carver& c, BlockSortBufs<K>& b, u64 n, int p, bool hasv, u32 tavg, bool force_A) {
+    const u32 T = tileT<K>();
+    const u64 m = cdiv(n, (u64)p);
+    b.tpb = (int)std::max<u64>(1, cdiv(m, T));
+    b.spt = T / kSampleStride;
+    b.A = nullptr;
+    b.Av = nullptr;
+    b.tsmp = nullptr;
+    std::memset(&b.mwm, 0, sizeof(b.mwm));
+    if (b.tpb > 1 || force_A) {
+        b.A = c.take<K>(n);
+        if (hasv) b.Av = c.take<u32>(n);
+    }
+    if (b.tpb > 1) {
+        b.tsmp = c.take<K>((u64)p * b.tpb * b.spt);
+        carve_mwm<K>(c, b.mwm, p, b.tpb, n, tavg);
+    }
+}
+
+// in (dtype in_dt) -> out (order keys, or raw keys of out_dt), every block of
+// the p-way split sorted. scr/scrv: n-element scratch for oversize chunks
+// (may be the input). osmp: block samples every yb-th key (slot stride spb).
+template <typename K, bool HASV>
+bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, int in_dt, K* out, u32* outv,
+                       int out_dt, K* scr, u32* scrv, i64 n, int p, u32 cap, u32 tavg, K* osmp, u32 yb, u32 spb,
+                       hipStream_t st) {
+    constexpr int NT = Shape<K>::NT;
+    const u32 T = tileT<K>();
+    TileArgs<K> ta;
+    ta.in = in; ta.inv = inv; ta.n = n; ta.p = p; ta.tpb = b.tpb; ta.in_dt = in_dt;
+    if (b.tpb == 1) {
+        ta.out = out; ta.outv = outv; ta.out_dt = out_dt; ta.smp = osmp; ta.ys = yb; ta.spt = spb;
+        hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3(p), dim3(NT), 0, st, ta);
+        LAUNCH_OK();
+        return BSPS_OK;
+    }
+    ta.out = b.A; ta.outv = b.Av; ta.out_dt = BSPS_DT_NONE; ta.smp = b.tsmp; ta.ys = kSampleStride; ta.spt = b.spt;
+    hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3((u32)(p * b.tpb)), dim3(NT), 0, st, ta);
+    LAUNCH_OK();
+    const u64 nrun = (u64)p * b.tpb;
+    hipLaunchKernelGGL((k_block_tables<K>), dim3((u32)cdiv(nrun, 256)), dim3(256), 0, st, n, p, b.tpb, T,
+                       kSampleStride, b.spt, b.mwm.run_start, b.mwm.run_len, b.mwm.out_base, b.mwm.sdesc);
+    LAUNCH_OK();
+    MwmArgs<K> a = mwm_args<K>(b.mwm, b.A, b.Av, out, outv, scr, scrv, b.tsmp, cap, tavg, out_dt, osmp, yb, spb);
+    return mwm_run<K, HASV>(a, st);
+}
+
+// ------------------------------------------------------------------ plan
+
+struct Opts {
+    u32 cap, tavg;
+};
+
+template <typename K>
+Opts opts_for(const bsps_params* prm) {
+    const u32 T = tileT<K>();
+    Opts o;
+    o.cap = (prm && prm->chunk_cap > 0) ? std::min<u32>((u32)prm->chunk_cap, T) : T;
+    o.tavg = std::max<u32>(1, o.cap / 2);
+    return o;
+}
+
+template <typename K>
+struct Plan {
+    BlockSortBufs<K> bs;     // main block sort
+    K* B;
+    u32* Bv;
+    K* bsmp;                 // block samples (every kSampleStride-th key of each block)
+    u32 spb;
+    // sample
+    i64 ns;
+    K* skey;
+    u32* spos;
+    K* ssk;                  // sorted sample
+    u32* ssp;
+    K* sscr;
+    u32* sscrv;
+    BlockSortBufs<K> ss;     // sample sort
+    u32* rpos;               // RAN positions and their sorted copy
+    u32* rpos_s;
+    u32* rpos_scr;
+    BlockSortBufs<u32> rs;   // RAN position sort
+    // splitters and counts
+    K* pk;
+    u32* pp;
+    u32* cntT;
+    MwmBufs<K> bm;           // bucket merge
+    // scatter route
+    u32* bucket;
+    u32* C;
+    u32* off;
+    // learned
+    void* model;
+    void* fitws;
+    size_t fitws_bytes;
+};
+
+template <typename K>
+size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* prm) {
+    const int p = prm->p;
+    const Opts o = opts_for<K>(prm);
+    const bool scatter = prm->route == BSPS_ROUTE_SCATTER;
+    carve_block_sort<K>(c, P.bs, (u64)n, p, hasv, o.tavg, true);  // A doubles as merge scratch / routed array
+    P.B = c.take<K>(n);
+    P.Bv = hasv ? c.take<u32>(n) : nullptr;
+    const u64 m = cdiv((u64)n, (u64)p);
+    P.spb = (u32)(m / kSampleStride);
+    P.bsmp = c.take<K>((u64)p * std::max<u32>(1, P.spb));
+    P.ns = prm->variant == BSPS_DET ? (i64)p * prm->s : (i64)p * prm->s - 1;
+    const i64 ns1 = std::max<i64>(1, P.ns);
+    P.skey = c.take<K>(ns1);
+    P.spos = c.take<u32>(ns1);
+    P.ssk = c.take<K>(ns1);
+    P.ssp = c.take<u32>(ns1);
+    P.sscr = c.take<K>(ns1);
+    P.sscrv = c.take<u32>(ns1);
+    carve_block_sort<K>(c, P.ss, (u64)ns1, 1, true, o.tavg, false);
+    P.rpos = P.rpos_s = P.rpos_scr = nullptr;
+    std::memset(&P.rs, 0, sizeof(P.rs));
+    if (prm->variant == BSPS_RAN) {
+        P.rpos = c.take<u32>(ns1);
+        P.rpos_s = c.take<u32>(ns1);
+        P.rpos_scr = c.take<u32>(ns1);
+        carve_block_sort<u32>(c, P.rs, (u64)ns1, 1, false, std::max<u32>(1, opts_for<u32>(prm).tavg), false);
+    }
+    P.pk = c.take<K>(p);
+    P.pp = c.take<u32>(p);
+    P.cntT = c.take<u32>((u64)(p + 1) * p);
+    carve_mwm<K>(c, P.bm, p, p, (u64)n, o.tavg);
+    P.bucket = P.C = P.off = nullptr;
+    P.model = P.fitws = nullptr;
+    P.fitws_bytes = 0;
+    if (scatter) {
+        P.bucket = c.take<u32>(n);
+        P.C = c.take<u32>((u64)p * p);
+        P.off = c.take<u32>((u64)p * p);
+        if (prm->bucketing == BSPS_LEARNED) {
+            const int L = prm->leaves > 0 ? prm->leaves : 4096;
+            P.model = c.take<char>(bsps_model_bytes(L));
+            P.fitws_bytes = bsps_fit_workspace_bytes(P.ns, L);
+            P.fitws = c.take<char>(P.fitws_bytes);
+        }
+    }
+    return c.off + 256;
+}
+
+bsps_status validate(i64 n, int dtype, const bsps_params* prm) {
+    if (!prm) return BSPS_EINVAL;
+    if (n < 0 || prm->p < 1 || prm->s < 1) return BSPS_EINVAL;
+    if ((i64)prm->p > std::max<i64>(n, 1)) return BSPS_EINVAL;
+    if (dtype < 0 || dtype > 2) return BSPS_EINVAL;
+    if (prm->variant != BSPS_DET && prm->variant != BSPS_RAN) return BSPS_EINVAL;
+    if (prm->route != BSPS_ROUTE_FUSED && prm->route != BSPS_ROUTE_SCATTER) return BSPS_EINVAL;
+    if (prm->bucketing != BSPS_SPLITTER && prm->bucketing != BSPS_LEARNED) return BSPS_EINVAL;
+    if (prm->leaves < 0 || prm->chunk_cap < 0) return BSPS_EINVAL;
+    for (int i = 0; i < 7; i++)
+        if (prm->reserved[i]) return BSPS_EINVAL;
+    if (prm->variant == BSPS_RAN && (i64)prm->s * prm->p - 1 > n) return BSPS_EINVAL;
+    if (n >= (i64)0xFFFFFFFFll || prm->p > kMaxP) return BSPS_EUNSUPPORTED;
+    // every block must split into at most MAXR tiles
+    const int kb = key_bytes(dtype);
+    const u64 T = kb == 8 ? tileT<u64>() : tileT<u32>();
+    if (n > 1 && cdiv(cdiv((u64)n, (u64)prm->p), T) > (u64)MAXR) return BSPS_EUNSUPPORTED;
+    const i64 ns = prm->variant == BSPS_DET ? (i64)prm->p * prm->s : (i64)prm->p * prm->s - 1;
+    if (ns > (i64)MAXR * (i64)T || ns >= (i64)0xFFFFFFFFll) return BSPS_EUNSUPPORTED;
+    return BSPS_OK;
+}
+
+// ------------------------------------------------------------------ host conversions (stats)
+
+template <typename K>
+K raw_of(K u, int dt);
+template <>
+u32 raw_of<u32>(u32 u, int dt) {
+    if (dt == BSPS_F32) return (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    return u ^ 0x80000000u;
+}
+template <>
+u64 raw_of<u64>(u64 u, int dt) { (void)dt; return u ^ 0x8000000000000000ull; }
+
+template <typename K>
+bsps_status copy_keys_out(void* host, const K* dev, i64 count, int dt, hipStream_t st) {
+    if (!host || count <= 0) return BSPS_OK;
+    std::vector<K> tmp((size_t)count);
+    HIP_OK(hipMemcpyAsync(tmp.data(), dev, sizeof(K) * count, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    K* h = (K*)host;
+    for (i64 i = 0; i < count; i++) h[i] = raw_of<K>(tmp[i], dt);
+    return BSPS_OK;
+}
+
+bsps_status copy_u32_to_i64(int64_t* host, const u32* dev, i64 count, hipStream_t st) {
+    if (!host || count <= 0) return BSPS_OK;
+    std::vector<u32> tmp((size_t)count);
+    HIP_OK(hipMemcpyAsync(tmp.data(), dev, sizeof(u32) * count, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (i64 i = 0; i < count; i++) host[i] = tmp[i];
+    return BSPS_OK;
+}
+
+// ------------------------------------------------------------------ the sort
+
+template <typename K, bool HASV>
+bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* prm, void* ws, size_t ws_bytes,
+                     hipStream_t st, bsps_stats* stats) {
+    const int p = prm->p, s = prm->s;
+    Carver c(ws);
+    Plan<K> P;
+    const size_t need = carve_plan<K>(c, P, n, HASV, prm);
+    if (!ws || ws_bytes < need) return BSPS_EWORKSPACE;
+    const Opts o = opts_for<K>(prm);
+    K* io = (K*)keys;
+    bsps_status rc;
+    // A1: every virtual processor sorts its block (stable).
+    rc = block_sort<K, HASV>(P.bs, io, vals, dt, P.B, P.Bv, BSPS_DT_NONE, io, vals, n, p, o.cap, o.tavg, P.bsmp,
+                             kSampleStride, std::max<u32>(1, P.spb), st);
+    if (rc) return rc;
+    if (stats && stats->block_sorted) {
+        rc = copy_keys_out<K>(stats->block_sorted, P.B, n, dt, st);
+        if (rc) return rc;
+    }
+    if (stats && stats->block_sorted_values && HASV) {
+        HIP_OK(hipMemcpyAsync(stats->block_sorted_values, P.Bv, 4 * n, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+    }
+    if (p == 1) {
+        hipLaunchKernelGGL((k_copy_out<K>), dim3((u32)cdiv(n, 256)), dim3(256), 0, st, P.B, HASV ? P.Bv : nullptr, io,
+                           vals, n, dt);
+        LAUNCH_OK();
+        if (stats) {
+            HIP_OK(hipStreamSynchronize(st));
+            if (stats->bucket_sizes) stats->bucket_sizes[0] = n;
+            if (stats->count_matrix) stats->count_matrix[0] = n;
+            stats->max_bucket_ratio = 1.0;
+        }
+        return BSPS_OK;
+    }
+    // A2: sample records (key, position in B), in position order.
+    const i64 ns = P.ns;
+    if (prm->variant == BSPS_DET) {
+        hipLaunchKernelGGL((k_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, n, p, s, P.skey,
+                           P.spos);
+        LAUNCH_OK();
+    } else {
+        hipLaunchKernelGGL(k_ran_positions, dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, (u64)prm->seed, n, ns,
+                           P.rpos);
+        LAUNCH_OK();
+        const Opts ou = opts_for<u32>(prm);
+        rc = block_sort<u32, false>(P.rs, P.rpos, nullptr, BSPS_DT_NONE, P.spos, nullptr, BSPS_DT_NONE, P.rpos_scr,
+                                    nullptr, ns, 1, ou.cap, ou.tavg, nullptr, 1, 1, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_gather_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, P.spos, ns,
+                           P.skey);
+        LAUNCH_OK();
+    }
+    // A3: sort the sample by (key, position): stable by key, input in position order.
+    rc = block_sort<K, true>(P.ss, P.skey, P.spos, BSPS_DT_NONE, P.ssk, P.ssp, BSPS_DT_NONE, P.sscr, P.sscrv, ns, 1,
+                             o.cap, o.tavg, nullptr, 1, 1, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL((k_splitters<K>), dim3((u32)cdiv(p, 256)), dim3(256), 0, st, P.ssk, P.ssp, p, s, P.pk, P.pp);
+    LAUNCH_OK();
+    // A4: bucket boundaries inside every sorted block.
+    const u64 ncnt = (u64)(p + 1) * p;
+    hipLaunchKernelGGL((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pp, P.cntT);
+    LAUNCH_OK();
+    // A5: prefix sums -> runs of every bucket. A6: merge them (routing fused).
+    hipLaunchKernelGGL(k_bucket_tables, dim3(p), dim3(256), 0, st, n, p, P.cntT, kSampleStride,
+                       std::max<u32>(1, P.spb), (const u32*)nullptr, P.bm.run_start, P.bm.run_len, P.bm.out_base,
+                       P.bm.sdesc);
+    LAUNCH_OK();
+    MwmArgs<K> a = mwm_args<K>(P.bm, P.B, P.Bv, io, vals, P.bs.A, P.bs.Av, P.bsmp, o.cap, o.tavg, dt, nullptr, 1, 1);
+    rc = mwm_run<K, HASV>(a, st);
+    if (rc) return rc;
+    if (stats) {
+        HIP_OK(hipStreamSynchronize(st));
+        rc = copy_keys_out<K>(stats->splitter_keys, P.pk, p - 1, dt, st);
+        if (rc) return rc;
+        rc = copy_u32_to_i64(stats->splitter_pos, P.pp, p - 1, st);
+        if (rc) return rc;
+        rc = copy_keys_out<K>(stats->sample_keys, P.ssk, ns, dt, st);
+        if (rc) return rc;
+        rc = copy_u32_to_i64(stats->sample_pos, P.ssp, ns, st);
+        if (rc) return rc;
+        std::vector<u32> ct((size_t)(p + 1) * p);
+        HIP_OK(hipMemcpyAsync(ct.data(), P.cntT, 4 * ct.size(), hipMemcpyDeviceToHost, st));
+        u32 ctr[2];
+        HIP_OK(hipMemcpyAsync(ctr, P.bm.counters, 8, hipMemcpyDeviceToHost, st));
+        u32 ctr2[2] = {0, 0};
+        if (P.bs.tpb > 1) HIP_OK(hipMemcpyAsync(ctr2, P.bs.mwm.counters, 8, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        double mx = 0;
+        for (int i = 0; i < p; i++) {
+            i64 bsz = 0;
+            for (int k = 0; k < p; k++) {
+                const i64 cki = (i64)ct[(size_t)(i + 1) * p + k] - (i64)ct[(size_t)i * p + k];
+                if (stats->count_matrix) stats->count_matrix[(size_t)k * p + i] = cki;
+                bsz += cki;
+            }
+            if (stats->bucket_sizes) stats->bucket_sizes[i] = bsz;
+            mx = std::max(mx, (double)bsz);
+        }
+        stats->max_bucket_ratio = mx / ((double)n / p);
+        stats->oversize_chunks = (i64)ctr[1] + (i64)ctr2[1];
+    }
+    return BSPS_OK;
+}
+
+template <bool HASV>
+bsps_status dispatch_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* prm, void* ws, size_t ws_bytes,
+                          void* stream, bsps_stats* st) {
+    bsps_status rc = validate(n, dt, prm);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= 1) {
+        if (st) {
+            if (st->bucket_sizes) st->bucket_sizes[0] = n;
+            if (st->count_matrix) st->count_matrix[0] = n;
+        }
+        return BSPS_OK;
+    }
+    if (!keys || (HASV && !vals)) return BSPS_EINVAL;
+    if (dt == BSPS_I64) return run_sort<u64, HASV>(keys, vals, n, dt, prm, ws, ws_bytes, s, st);
+    return run_sort<u32, HASV>(keys, vals, n, dt, prm, ws, ws_bytes, s, st);
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+size_t bsps_workspace_bytes(int64_t n, int32_t dtype, int32_t with_values, const bsps_params* prm) {
+    if (validate(n, dtype, prm) != BSPS_OK) return 0;
+    if (n <= 1) return 256;
+    Carver c(nullptr);
+    if (dtype == BSPS_I64) {
+        Plan<u64> P;
+        return carve_plan<u64>(c, P, n, with_values != 0, prm);
+    }
+    Plan<u32> P;
+    return carve_plan<u32>(c, P, n, with_values != 0, prm);
+}
+
+bsps_status bsps_sort(void* keys, int64_t n, int32_t dtype, const bsps_params* prm, void* ws, size_t ws_bytes,
+                      void* stream, bsps_stats* st) {
+    return dispatch_sort<false>(keys, nullptr, n, dtype, prm, ws, ws_bytes, stream, st);
+}
+
+bsps_status bsps_sort_kv(void* keys, uint32_t* values, int64_t n, int32_t dtype, const bsps_params* prm, void* ws,
+                         size_t ws_bytes, void* stream, bsps_stats* st) {
+    return dispatch_sort<true>(keys, values, n, dtype, prm, ws, ws_bytes, stream, st);
+}
+
+const char* bsps_status_string(int32_t status) {
+    switch (status) {
+        case BSPS_OK: return "ok";
+        case BSPS_EINVAL: return "invalid argument";
+        case BSPS_EWORKSPACE: return "workspace missing or too small";
+        case BSPS_EDEVICE: return "HIP device error";
+        case BSPS_EUNSUPPORTED: return "outside the library limits";
+        default: return "unknown status";
+    }
+}
+
+void bsps_release_cache(void) {}
+
+}  // extern "C"

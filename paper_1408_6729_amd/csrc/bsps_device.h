@@ -1,0 +1,277 @@
+// bsps_device.h -- device building blocks for gfx950 (wave64, 160 KB LDS per CU).
+//
+// Keys are carried as unsigned "order keys" whose unsigned order is the key
+// order (int: sign bit flipped; float32: IEEE-754 totalOrder of the bits).
+// The workgroup sort below is a stable LSD radix sort held in registers and
+// LDS: each thread owns IT consecutive tile positions ("blocked" order), ranks
+// its items with private per-digit counters in LDS (two 16-bit counters per
+// 32-bit word), and a raking scan over the counters in (digit, thread) order
+// turns local counts into stable ranks. Only the bits in which the tile's
+// keys differ are sorted: keys are rebased to (key - min) first.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+typedef int64_t i64;
+
+#define BSPS_DT_I32 0
+#define BSPS_DT_I64 1
+#define BSPS_DT_F32 2
+#define BSPS_DT_NONE (-1)  // input is already in order-key form
+
+// ---------------------------------------------------------------- key maps
+
+__device__ __forceinline__ u32 okey32(u32 raw, int dt) {
+    if (dt == BSPS_DT_F32) return (raw & 0x80000000u) ? ~raw : (raw | 0x80000000u);
+    if (dt == BSPS_DT_NONE) return raw;
+    return raw ^ 0x80000000u;
+}
+__device__ __forceinline__ u32 rawkey32(u32 u, int dt) {
+    if (dt == BSPS_DT_F32) return (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    if (dt == BSPS_DT_NONE) return u;
+    return u ^ 0x80000000u;
+}
+__device__ __forceinline__ u64 okey64(u64 raw, int dt) {
+    return dt == BSPS_DT_NONE ? raw : (raw ^ 0x8000000000000000ull);
+}
+__device__ __forceinline__ u64 rawkey64(u64 u, int dt) {
+    return dt == BSPS_DT_NONE ? u : (u ^ 0x8000000000000000ull);
+}
+template <typename K> __device__ __forceinline__ K okey(K raw, int dt);
+template <> __device__ __forceinline__ u32 okey<u32>(u32 raw, int dt) { return okey32(raw, dt); }
+template <> __device__ __forceinline__ u64 okey<u64>(u64 raw, int dt) { return okey64(raw, dt); }
+template <typename K> __device__ __forceinline__ K rawkey(K u, int dt);
+template <> __device__ __forceinline__ u32 rawkey<u32>(u32 u, int dt) { return rawkey32(u, dt); }
+template <> __device__ __forceinline__ u64 rawkey<u64>(u64 u, int dt) { return rawkey64(u, dt); }
+
+template <typename K> struct KeyMax;
+template <> struct KeyMax<u32> { static constexpr u32 v = 0xffffffffu; };
+template <> struct KeyMax<u64> { static constexpr u64 v = 0xffffffffffffffffull; };
+
+// Record order of the duplicate handling: key first, then the position tag.
+template <typename K>
+__device__ __forceinline__ bool rec_le(K k, u32 pos, K bk, u32 bpos) {
+    return k < bk || (k == bk && pos <= bpos);
+}
+template <typename K>
+__device__ __forceinline__ bool rec_lt(K k, u32 pos, K bk, u32 bpos) {
+    return k < bk || (k == bk && pos < bpos);
+}
+
+__device__ __forceinline__ int bitwidth64(u64 v) { return v ? 64 - __clzll((long long)v) : 0; }
+
+// ---------------------------------------------------------------- tile geometry
+
+// Workgroup sort shapes: 4-byte keys use 512 threads x 32 items (16K keys),
+// 8-byte keys use 256 threads x 32 items (8K keys).
+template <typename K> struct Shape;
+template <> struct Shape<u32> { static constexpr int NT = 512, IT = 32; };
+template <> struct Shape<u64> { static constexpr int NT = 256, IT = 32; };
+
+constexpr int RB = 6;                 // radix bits per pass
+constexpr int RADIX = 1 << RB;        // 64 digits
+constexpr int HALF = RADIX / 2;       // digits d and d + HALF share one 32-bit counter word
+
+__device__ __forceinline__ int padi(int i) { return i + (i >> 5); }  // one pad word per 32
+
+template <int NT> struct SortSmem {
+    static constexpr int CNT = HALF * NT;
+    u32 cnt[CNT + CNT / 32];
+    u32 wsum[NT / 64 + 2];
+    u32 misc[16];
+    u64 red64[NT / 64 * 2];
+};
+
+// ---------------------------------------------------------------- scans
+
+__device__ __forceinline__ u32 wave_incl_scan(u32 v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        u32 y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+// Exclusive scan over the workgroup (u32 add, so packed 16-bit pairs work).
+template <int NT>
+__device__ __forceinline__ u32 block_excl_scan(u32 x, u32& total, u32* wsum) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    u32 v = wave_incl_scan(x);
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    if (w == 0) {
+        u32 s = lane < NW ? wsum[lane] : 0u;
+#pragma unroll
+        for (int o = 1; o < NW; o <<= 1) {
+            u32 y = __shfl_up(s, o, 64);
+            if (lane >= o) s += y;
+        }
+        if (lane < NW) wsum[lane] = s;
+    }
+    __syncthreads();
+    total = wsum[NW - 1];
+    u32 before = w ? wsum[w - 1] : 0u;
+    return before + v - x;
+}
+
+template <int NT, typename K>
+__device__ __forceinline__ void block_minmax(K& mn, K& mx, u64* red) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        K a = __shfl_xor(mn, o, 64);
+        K b = __shfl_xor(mx, o, 64);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    if (lane == 0) { red[w] = (u64)mn; red[NW + w] = (u64)mx; }
+    __syncthreads();
+    mn = (K)red[0];
+    mx = (K)red[NW];
+#pragma unroll
+    for (int i = 1; i < NW; i++) {
+        K a = (K)red[i], b = (K)red[NW + i];
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- stable rank
+
+// rank[j] = position of item j (thread t, blocked position t*IT + j) after a
+// stable sort by digit dig[j] in [0, RADIX).
+template <int NT, int IT>
+__device__ __forceinline__ void radix_rank(const u32 (&dig)[IT], u32 (&rank)[IT], SortSmem<NT>& sm) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int h = 0; h < HALF; h++) sm.cnt[padi(h * NT + t)] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IT; j++) {
+        const u32 d = dig[j];
+        const int a = padi((int)(d & (HALF - 1)) * NT + t);
+        const u32 sh = (d >> (RB - 1)) << 4;
+        const u32 w = sm.cnt[a];
+        rank[j] = (w >> sh) & 0xffffu;
+        sm.cnt[a] = w + (1u << sh);
+    }
+    __syncthreads();
+    u32 sum = 0;
+#pragma unroll
+    for (int i = 0; i < HALF; i++) sum += sm.cnt[padi(t * HALF + i)];
+    u32 total;
+    u32 run = block_excl_scan<NT>(sum, total, sm.wsum);
+#pragma unroll
+    for (int i = 0; i < HALF; i++) {
+        const int a = padi(t * HALF + i);
+        const u32 v = sm.cnt[a];
+        sm.cnt[a] = run;
+        run += v;
+    }
+    __syncthreads();
+    const u32 tot_lo = total & 0xffffu;
+#pragma unroll
+    for (int j = 0; j < IT; j++) {
+        const u32 d = dig[j];
+        const u32 w = sm.cnt[padi((int)(d & (HALF - 1)) * NT + t)];
+        const u32 base = (d >> (RB - 1)) ? ((w >> 16) + tot_lo) : (w & 0xffffu);
+        rank[j] += base;
+    }
+}
+
+// ---------------------------------------------------------------- workgroup sort
+
+// Sorts the NT*IT items held in registers (blocked order; unused tail items
+// must hold the largest rebased key) by their rebased keys sk (nbits wide).
+// Keys and payloads share one exchange buffer, one after the other. On return
+// the sorted rebased keys are in exch[padi(i)], i = 0..NT*IT-1, and rank[j]
+// is the final position of item j, whose payload is still v[j]; the caller
+// stores the keys, then calls wg_scatter_vals() to move the payloads.
+// SK = u32 or u64; exch holds NT*IT + NT*IT/32 elements of SK.
+template <int NT, int IT, typename SK, bool HASV>
+__device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&rank)[IT], int nbits, SK* exch,
+                                             SortSmem<NT>& sm) {
+    const int t = threadIdx.x;
+    u32* vex = reinterpret_cast<u32*>(exch);
+    u32 dig[IT];
+    if (nbits <= 0) {  // all keys equal: input order is the stable order
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            rank[j] = (u32)(t * IT + j);
+            exch[padi(t * IT + j)] = sk[j];
+        }
+        __syncthreads();
+        return;
+    }
+    for (int sh = 0; sh < nbits; sh += RB) {
+        const bool last = sh + RB >= nbits;
+#pragma unroll
+        for (int j = 0; j < IT; j++) dig[j] = (u32)(sk[j] >> sh) & (RADIX - 1);
+        radix_rank<NT, IT>(dig, rank, sm);
+#pragma unroll
+        for (int j = 0; j < IT; j++) exch[padi((int)rank[j])] = sk[j];
+        __syncthreads();
+        if (last) break;
+#pragma unroll
+        for (int j = 0; j < IT; j++) sk[j] = exch[padi(t * IT + j)];
+        __syncthreads();
+        if (HASV) {
+#pragma unroll
+            for (int j = 0; j < IT; j++) vex[padi((int)rank[j])] = v[j];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < IT; j++) v[j] = vex[padi(t * IT + j)];
+            __syncthreads();
+        }
+    }
+}
+
+// Moves payloads to their final positions (after the keys were stored out of
+// the exchange buffer): vex[padi(rank[j])] = v[j].
+template <int NT, int IT>
+__device__ __forceinline__ void wg_scatter_vals(const u32 (&v)[IT], const u32 (&rank)[IT], u32* vex) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < IT; j++) vex[padi((int)rank[j])] = v[j];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- keyed permutation
+
+// SplitMix64 output function (Steele, Lea & Flood 2014).
+__device__ __forceinline__ u64 mix64(u64 z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Image of t under a keyed permutation of [0, n): a balanced 4-round Feistel
+// network on 2h >= ceil(log2 n) bits whose round function is mix64 of
+// (seed + golden*(round+1) + right half), restricted to [0, n) by cycle
+// walking (Black & Rogaway 2002).
+__device__ __forceinline__ u64 feistel_perm(u64 seed, u64 n, u64 t) {
+    if (n <= 1) return 0;
+    int bits = 64 - __clzll((long long)(n - 1));
+    int h = (bits + 1) >> 1;
+    u64 mask = (1ull << h) - 1;
+    u64 x = t;
+    do {
+        u64 L = x >> h, R = x & mask;
+#pragma unroll
+        for (u64 j = 0; j < 4; j++) {
+            u64 f = mix64(seed + 0x9E3779B97F4A7C15ull * (j + 1) + R) & mask;
+            u64 nl = R;
+            R = L ^ f;
+            L = nl;
+        }
+        x = (L << h) | R;
+    } while (x >= n);
+    return x;
+}

@@ -1,0 +1,142 @@
+"""GPU parity of the fused sort path against the CPU oracle, element by element.
+
+Every case checks, bit for bit: the sorted keys (and payloads), the
+block-sorted array (Figure SortD step 3), the sorted sample and the splitters
+(steps 4-6), and the count matrix (step 9). Sizes span several tiles and
+ragged tails; the all-equal and few-distinct inputs exercise the tie rule.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1408_6729_amd as bsps  # noqa: F401  (fails loudly without the library)
+    return torch.device("cuda:0")
+
+
+def _torch_keys(keys, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(keys)).to(dev)
+
+
+def _run(dev, keys, p, s, variant, seed=1, values=None, chunk_cap=0):
+    import torch
+    import paper_1408_6729_amd as bsps
+    t = _torch_keys(keys, dev)
+    v = None if values is None else torch.from_numpy(values.view(np.int32)).to(dev)
+    st = bsps.sort_(t, p, s, variant, seed, values=v, chunk_cap=chunk_cap, stats=True)
+    torch.cuda.synchronize()
+    out = t.cpu().numpy()
+    outv = None if v is None else v.cpu().numpy().view(np.uint32)
+    return out, outv, st
+
+
+def _bits(a):
+    return a.view(np.uint32) if a.dtype == np.float32 else a
+
+
+def _check(ora, dev, keys, p, s, variant, seed=1, kv=False, chunk_cap=0, check_B=True):
+    vals = np.arange(keys.size, dtype=np.uint32) if kv else None
+    ref = ora.sort(keys, p, s, variant, seed, vals)
+    out, outv, st = _run(dev, keys, p, s, variant, seed, vals, chunk_cap)
+    assert np.array_equal(_bits(out), _bits(ref["keys"])), "sorted keys differ"
+    if kv:
+        assert np.array_equal(outv, ref["values"]), "payload order differs"
+    if p > 1:
+        assert np.array_equal(st["splitter_pos"], ref["spl_pos"]), "splitter tags differ"
+        assert np.array_equal(_bits(st["splitter_keys"]), _bits(ref["B_keys"][ref["spl_pos"]])), "splitter keys differ"
+        assert np.array_equal(st["sample_pos"], ref["sample_pos"]), "sample tags differ"
+        assert np.array_equal(st["count_matrix"], ref["C"]), "count matrix differs"
+        assert np.array_equal(st["bucket_sizes"], ref["bucket_sizes"])
+    if check_B:
+        assert np.array_equal(_bits(st["block_sorted"]), _bits(ref["B_keys"])), "block-sorted array differs"
+        if kv:
+            assert np.array_equal(st["block_sorted_values"][:keys.size], ref["B_values"])
+    return st
+
+
+def test_c1_plain_det(ora, dev):
+    """Plain DET: 2^20 int32 uniform keys, p = 16, s = 8."""
+    keys = W.int32_keys(1 << 20, 16, "uniform")
+    _check(ora, dev, keys, 16, 8, ora.DET)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("dist", W.DISTRIBUTIONS)
+def test_c2_distributions_small(ora, dev, variant, dist):
+    """The seven mid-size distributions at 2^21 keys, p = 128, s = 32."""
+    keys = W.int32_keys(1 << 21, 128, dist)
+    _check(ora, dev, keys, 128, 32, variant)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_ragged_random(ora, dev, dtype, variant):
+    rng = np.random.default_rng(7)
+    for trial in range(6):
+        n = int(rng.integers(2, 300000))
+        p = int(rng.integers(1, min(n, 300) + 1))
+        s = int(rng.integers(1, 70))
+        if variant == 1 and s * p - 1 > n:
+            s = max(1, (n + 1) // p)
+        distinct = None if trial % 2 else int(rng.integers(1, 50))
+        keys = W.random_keys(n, dtype, seed=100 + trial, distinct=distinct)
+        _check(ora, dev, keys, p, s, variant, seed=trial + 3, kv=(trial % 3 == 0))
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 1000, 16383, 16384, 16385, 50001])
+def test_edges(ora, dev, n):
+    keys = W.random_keys(n, "int32", seed=n, distinct=max(1, n // 4))
+    for p in sorted({1, 2, min(n, 7), min(n, 4096)}):
+        _check(ora, dev, keys, p, 3, ora.DET)
+
+
+def test_p_limit(dev):
+    import torch
+    import paper_1408_6729_amd as bsps
+    t = torch.zeros(5000, dtype=torch.int32, device=dev)
+    with pytest.raises(bsps.BspsError) as e:
+        bsps.sort_(t, 4097, 1, bsps.DET)
+    assert e.value.code == bsps.EUNSUPPORTED
+
+
+def test_all_equal_diagonal(ora, dev):
+    keys = np.zeros(1 << 20, dtype=np.int32)
+    st = _check(ora, dev, keys, 64, 16, ora.DET)
+    m = (1 << 20) // 64
+    assert np.array_equal(st["count_matrix"], np.diag(np.full(64, m)))
+
+
+def test_oversize_chunk_path(ora, dev):
+    """A small LDS chunk cap sends most merge chunks through the global path."""
+    keys = W.random_keys(300000, "int32", seed=5, distinct=1000)
+    st = _check(ora, dev, keys, 32, 16, ora.RAN, seed=9, kv=True, chunk_cap=600)
+    assert st["oversize_chunks"] > 0
+    keys64 = W.random_keys(200000, "int64", seed=6)
+    st = _check(ora, dev, keys64, 16, 16, ora.DET, kv=True, chunk_cap=300)
+    assert st["oversize_chunks"] > 0
+
+
+def test_duplicate_stress_small(ora, dev):
+    """Scaled-down duplicate stress: Zipf(1.2) int64 keys plus a 25% equal
+    block, payload = original index, p = 256, s = 64."""
+    keys, vals = W.zipf_int64_kv(1 << 21)
+    ref = ora.sort(keys, 256, 64, ora.DET, 1, vals)
+    out, outv, st = _run(dev, keys, 256, 64, ora.DET, 1, vals)
+    assert np.array_equal(out, ref["keys"])
+    assert np.array_equal(outv, ref["values"])
+    eq = out[1:] == out[:-1]
+    assert (outv[1:][eq] > outv[:-1][eq]).all()
+
+
+def test_float_special_values(ora, dev):
+    keys = W.lognormal_f32(1 << 20, zeros=1024)
+    keys[:7] = np.array([np.inf, -np.inf, -0.0, 0.0, 1e-45, -1e-45, 3.4e38], dtype=np.float32)
+    _check(ora, dev, keys, 64, 16, ora.RAN, seed=2)
