@@ -25,7 +25,9 @@
  *  - The result is the STABLE ascending order: equal keys keep their input
  *    order, which is exactly the order the paper's tie rule (processor
  *    identifier, then local index, Section 5.1.1) produces.
- *  - Limits: n < 2^32 - 1 (positions are 32-bit), 1 <= p <= 4096.
+ *  - Limits: n < 2^32 - 1 (positions are 32-bit), 1 <= p <= 1024, and each block
+ *    of about n/p keys splits into at most 1024 tiles (16K keys for 4-byte keys,
+ *    8K for int64), i.e. n/p <= 2^24 (2^23 for int64).
  */
 #ifndef BSPS_H
 #define BSPS_H
@@ -115,7 +117,7 @@ size_t bsps_workspace_bytes(int64_t n, int32_t dtype, int32_t with_values, const
  *  ws        device workspace of ws_bytes >= bsps_workspace_bytes(n, dtype, 0, prm)
  * Errors: EINVAL for n < 0, p < 1, p > max(n, 1), s < 1, RAN with s*p - 1 > n,
  * unknown dtype/variant/route/bucketing, leaves < 0, nonzero reserved fields;
- * EWORKSPACE; EUNSUPPORTED for n >= 2^32 - 1 or p > 4096. n = 0 and n = 1 are
+ * EWORKSPACE; EUNSUPPORTED beyond the limits above. n = 0 and n = 1 are
  * valid no-ops.
  */
 bsps_status bsps_sort(void* keys, int64_t n, int32_t dtype, const bsps_params* prm,

@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbsps.so")
+LIB_PATH = os.environ.get("BSPS_LIB") or os.path.join(_HERE, "libbsps.so")
 
 OK, EINVAL, EWORKSPACE, EDEVICE, EUNSUPPORTED = 0, 1, 2, 3, 4
 DET, RAN = 0, 1

@@ -24,7 +24,7 @@
 namespace {
 
 constexpr u32 kSampleStride = 32;  // tile and block samples for the merges: every 32nd key
-constexpr int kMaxP = 4096;
+constexpr int kMaxP = MAXR;  // p <= 1024
 
 #define HIP_OK(x)                                              \
     do {                                                       \
@@ -75,7 +75,7 @@ void carve_mwm(Carver& c, MwmBufs<K>& m, int G, int R, u64 n, u32 tavg) {
     m.run_len = c.take<u32>((u64)G * R);
     m.out_base = c.take<u32>(G);
     m.sdesc = c.take<u32>((u64)G * R * 4);
-    m.counters = c.take<u32>(2);
+    m.counters = c.take<u32>(4);
     m.slot_group = c.take<u32>(m.S);
     m.grp_base = c.take<u32>(G);
     m.grp_nb = c.take<u32>(G);
@@ -92,24 +92,41 @@ MwmArgs<K> mwm_args(const MwmBufs<K>& m, const K* src, const u32* srcv, K* dst, 
     a.G = m.G; a.R = m.R;
     a.run_start = m.run_start; a.run_len = m.run_len; a.out_base = m.out_base; a.sdesc = m.sdesc;
     a.smp = smp; a.cap = cap; a.tavg = tavg;
-    a.slot_count = m.counters; a.oversize = m.counters + 1;
+    a.slot_count = m.counters; a.oversize = m.counters + 1; a.work = m.counters + 2;
     a.slot_group = m.slot_group; a.grp_base = m.grp_base; a.grp_nb = m.grp_nb;
     a.bkey = m.bkey; a.bpos = m.bpos; a.cuts = m.cuts; a.S = m.S;
     a.out_dt = out_dt; a.osmp = osmp; a.oys = oys; a.ospb = ospb;
     return a;
 }
 
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
 template <typename K, bool HASV>
 bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st) {
     constexpr int NT = Shape<K>::NT;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.slot_count, 2);
+    const int cus = device_cus();
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.slot_count, 4);
     LAUNCH_OK();
     hipLaunchKernelGGL((k_mwm_pick<K>), dim3(a.G), dim3(NT), 0, st, a);
     LAUNCH_OK();
     const u64 ncut = (u64)a.S * a.R;
-    hipLaunchKernelGGL((k_mwm_cuts<K>), dim3((u32)cdiv(ncut, 256)), dim3(256), 0, st, a);
+    const u32 gcut = (u32)std::min<u64>(cdiv(ncut, 256), (u64)1 << 20);  // one search per thread: latency-bound
+    hipLaunchKernelGGL((k_mwm_cuts<K>), dim3(gcut), dim3(256), 0, st, a);
     LAUNCH_OK();
-    hipLaunchKernelGGL((k_mwm_merge<K, HASV>), dim3(a.S), dim3(NT), 0, st, a);
+#ifndef BSPS_MERGE_WGS_PER_CU
+#define BSPS_MERGE_WGS_PER_CU 2
+#endif
+    const u32 gmerge = BSPS_MERGE_WGS_PER_CU > 0 ? (u32)std::min<u64>(a.S, (u64)cus * BSPS_MERGE_WGS_PER_CU) : a.S;
+    hipLaunchKernelGGL((k_mwm_merge<K, HASV>), dim3(gmerge), dim3(NT), 0, st, a);
     LAUNCH_OK();
     return BSPS_OK;
 }
@@ -187,7 +204,7 @@ Opts opts_for(const bsps_params* prm) {
     const u32 T = tileT<K>();
     Opts o;
     o.cap = (prm && prm->chunk_cap > 0) ? std::min<u32>((u32)prm->chunk_cap, T) : T;
-    o.tavg = std::max<u32>(1, o.cap / 2);
+    o.tavg = std::max<u32>(1, o.cap / 4);  // floor of the adaptive chunk target
     return o;
 }
 
@@ -494,5 +511,18 @@ const char* bsps_status_string(int32_t status) {
 }
 
 void bsps_release_cache(void) {}
+
+#ifdef BSPS_TIMING
+int bsps_debug_phases(unsigned long long* out, int reset) {
+    unsigned long long h[8];
+    if (hipMemcpyFromSymbol(h, HIP_SYMBOL(g_phase), sizeof(h)) != hipSuccess) return 1;
+    for (int i = 0; i < 8; i++) out[i] = h[i];
+    if (reset) {
+        unsigned long long z[8] = {0};
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z)) != hipSuccess) return 1;
+    }
+    return 0;
+}
+#endif
 
 }  // extern "C"

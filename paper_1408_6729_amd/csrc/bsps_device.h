@@ -70,18 +70,34 @@ template <typename K> struct Shape;
 template <> struct Shape<u32> { static constexpr int NT = 512, IT = 32; };
 template <> struct Shape<u64> { static constexpr int NT = 256, IT = 32; };
 
+#ifndef BSPS_DIG_RECOMPUTE
+#define BSPS_DIG_RECOMPUTE 1  // recompute digits instead of keeping them in registers
+#endif
+#ifndef BSPS_WG_PER_CU
+#define BSPS_WG_PER_CU 2      // occupancy target of the sorting kernels (workgroups per CU)
+#endif
+
 constexpr int RB = 6;                 // radix bits per pass
 constexpr int RADIX = 1 << RB;        // 64 digits
 constexpr int HALF = RADIX / 2;       // digits d and d + HALF share one 32-bit counter word
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }  // one pad word per 32
 
-template <int NT> struct SortSmem {
+// The digit counters and the key exchange buffer are never live at the same
+// time (ranking ends with a barrier before keys are scattered), so they share
+// one LDS region: `u` holds HALF*NT counter words or NT*IT exchange slots of
+// 8 bytes, whichever is larger, each with one pad word per 32.
+template <int NT, int KB> struct SortSmem {
     static constexpr int CNT = HALF * NT;
-    u32 cnt[CNT + CNT / 32];
+    static constexpr int CNTW = CNT + CNT / 32;
+    static constexpr int EXW = (NT * 32 + NT) * KB / 4;  // IT = 32 items of KB bytes
+    static constexpr int UW = CNTW > EXW ? CNTW : EXW;
+    u32 u[UW];
     u32 wsum[NT / 64 + 2];
     u32 misc[16];
     u64 red64[NT / 64 * 2];
+    __device__ __forceinline__ u32* cnt() { return u; }
+    template <typename T> __device__ __forceinline__ T* ex() { return reinterpret_cast<T*>(u); }
 };
 
 // ---------------------------------------------------------------- scans
@@ -146,62 +162,73 @@ __device__ __forceinline__ void block_minmax(K& mn, K& mx, u64* red) {
 // ---------------------------------------------------------------- stable rank
 
 // rank[j] = position of item j (thread t, blocked position t*IT + j) after a
-// stable sort by digit dig[j] in [0, RADIX).
-template <int NT, int IT>
-__device__ __forceinline__ void radix_rank(const u32 (&dig)[IT], u32 (&rank)[IT], SortSmem<NT>& sm) {
+// stable sort by digit dig[j] in [0, RADIX). Counter word (h, t) sits at
+// h*ROW + t + t/32 (row stride ROW = NT + NT/32): thread t's raking slice of
+// HALF words in flattened (h, t) order is contiguous and the per-item
+// read-modify-writes of a wave hit consecutive banks.
+template <int NT, int IT, typename DF>
+__device__ __forceinline__ void radix_rank(DF digf, u32 (&rank)[IT], u32* cnt, u32* wsum) {
     const int t = threadIdx.x;
+#if BSPS_DIG_RECOMPUTE
+#define DIG(j) digf(j)
+#else
+    u32 dig[IT];
 #pragma unroll
-    for (int h = 0; h < HALF; h++) sm.cnt[padi(h * NT + t)] = 0u;
+    for (int j = 0; j < IT; j++) dig[j] = digf(j);
+#define DIG(j) dig[j]
+#endif
+#pragma unroll
+    for (int h = 0; h < HALF; h++) cnt[padi(h * NT + t)] = 0u;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < IT; j++) {
-        const u32 d = dig[j];
+        const u32 d = DIG(j);
         const int a = padi((int)(d & (HALF - 1)) * NT + t);
         const u32 sh = (d >> (RB - 1)) << 4;
-        const u32 w = sm.cnt[a];
+        const u32 w = cnt[a];
         rank[j] = (w >> sh) & 0xffffu;
-        sm.cnt[a] = w + (1u << sh);
+        cnt[a] = w + (1u << sh);
     }
     __syncthreads();
     u32 sum = 0;
 #pragma unroll
-    for (int i = 0; i < HALF; i++) sum += sm.cnt[padi(t * HALF + i)];
+    for (int i = 0; i < HALF; i++) sum += cnt[padi(t * HALF + i)];
     u32 total;
-    u32 run = block_excl_scan<NT>(sum, total, sm.wsum);
+    u32 run = block_excl_scan<NT>(sum, total, wsum);
 #pragma unroll
     for (int i = 0; i < HALF; i++) {
         const int a = padi(t * HALF + i);
-        const u32 v = sm.cnt[a];
-        sm.cnt[a] = run;
+        const u32 v = cnt[a];
+        cnt[a] = run;
         run += v;
     }
     __syncthreads();
     const u32 tot_lo = total & 0xffffu;
 #pragma unroll
     for (int j = 0; j < IT; j++) {
-        const u32 d = dig[j];
-        const u32 w = sm.cnt[padi((int)(d & (HALF - 1)) * NT + t)];
+        const u32 d = DIG(j);
+        const u32 w = cnt[padi((int)(d & (HALF - 1)) * NT + t)];
         const u32 base = (d >> (RB - 1)) ? ((w >> 16) + tot_lo) : (w & 0xffffu);
         rank[j] += base;
     }
+#undef DIG
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------- workgroup sort
 
 // Sorts the NT*IT items held in registers (blocked order; unused tail items
-// must hold the largest rebased key) by their rebased keys sk (nbits wide).
-// Keys and payloads share one exchange buffer, one after the other. On return
-// the sorted rebased keys are in exch[padi(i)], i = 0..NT*IT-1, and rank[j]
-// is the final position of item j, whose payload is still v[j]; the caller
-// stores the keys, then calls wg_scatter_vals() to move the payloads.
+// must hold the largest rebased key) by their rebased keys sk (nbits wide). Keys and payloads share one exchange buffer, one after
+// the other. On return the sorted keys are in exch[padi(i)], i = 0..NT*IT-1,
+// and rank[j] is the final position of item j, whose payload is still v[j];
+// the caller stores the keys, then calls wg_scatter_vals() for the payloads.
 // SK = u32 or u64; exch holds NT*IT + NT*IT/32 elements of SK.
 template <int NT, int IT, typename SK, bool HASV>
 __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&rank)[IT], int nbits, SK* exch,
-                                             SortSmem<NT>& sm) {
+                                             u32* cnt, u32* wsum) {
     const int t = threadIdx.x;
     u32* vex = reinterpret_cast<u32*>(exch);
-    u32 dig[IT];
-    if (nbits <= 0) {  // all keys equal: input order is the stable order
+    if (nbits <= 0) {  // all sort keys equal: input order is the stable order
 #pragma unroll
         for (int j = 0; j < IT; j++) {
             rank[j] = (u32)(t * IT + j);
@@ -212,9 +239,7 @@ __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&r
     }
     for (int sh = 0; sh < nbits; sh += RB) {
         const bool last = sh + RB >= nbits;
-#pragma unroll
-        for (int j = 0; j < IT; j++) dig[j] = (u32)(sk[j] >> sh) & (RADIX - 1);
-        radix_rank<NT, IT>(dig, rank, sm);
+        radix_rank<NT, IT>([&](int j) { return (u32)(sk[j] >> sh) & (RADIX - 1); }, rank, cnt, wsum);
 #pragma unroll
         for (int j = 0; j < IT; j++) exch[padi((int)rank[j])] = sk[j];
         __syncthreads();

@@ -24,7 +24,24 @@
 #pragma once
 #include "bsps_device.h"
 
-constexpr int MAXR = 4096;  // runs per merge group (tiles per block, or p)
+constexpr int MAXR = 1024;  // runs per merge group (tiles per block, or p)
+
+#ifdef BSPS_TIMING
+__device__ unsigned long long g_phase[8];
+#define PHASE(k)                                                               \
+    do {                                                                       \
+        __syncthreads();                                                       \
+        if (threadIdx.x == 0) {                                                \
+            const unsigned long long now = __builtin_amdgcn_s_memtime();       \
+            atomicAdd(&g_phase[k], now - t_last);                              \
+            t_last = now;                                                      \
+        }                                                                      \
+    } while (0)
+#define PHASE_START unsigned long long t_last = __builtin_amdgcn_s_memtime()
+#else
+#define PHASE(k) do {} while (0)
+#define PHASE_START do {} while (0)
+#endif
 
 // ======================================================================= tables
 
@@ -46,6 +63,7 @@ struct MwmArgs {
     u32 tavg;              // target chunk size
     u32* slot_count;       // [1] slots handed out (zeroed before the pick kernel)
     u32* oversize;         // [1] oversize chunks (statistics)
+    u32* work;             // [1] next slot for the persistent merge workgroups
     u32* slot_group;       // [S]
     u32* grp_base;         // [G]
     u32* grp_nb;           // [G] boundaries of the group (chunks = nb + 1 when non-empty)
@@ -103,11 +121,50 @@ __global__ void k_zero_u32(u32* p, int n) {
 
 // ======================================================================= tile sort
 
+// Stores the sorted tile held in the exchange buffer (rebased keys) to out and
+// emits every ys-th key (ys a power of two) to the sample array.
+template <typename K, typename SK, int NT, int IT>
+__device__ __forceinline__ void store_sorted(const SK* ex, K mn, int cnt, K* out, int out_dt, K* smp, i64 sbase,
+                                             u32 ysh) {
+    const int t = threadIdx.x;
+    const u32 ym = (1u << ysh) - 1;
+#pragma unroll
+    for (int j = 0; j < IT; j++) {
+        const int i = j * NT + t;
+        if (i < cnt) {
+            const K u = (K)ex[padi(i)] + mn;
+            out[i] = rawkey<K>(u, out_dt);
+            if (smp && (((u32)i + 1) & ym) == 0) smp[sbase + (((u32)i + 1) >> ysh) - 1] = u;
+        }
+    }
+}
+
+// Loads IT consecutive elements p[0..IT) (blocked order) into registers;
+// 16-byte vector loads when the run is whole and aligned.
+template <typename T, int IT>
+__device__ __forceinline__ void load_blocked(const T* p, int valid, T (&r)[IT]) {
+    static_assert((IT * sizeof(T)) % 16 == 0, "vector path needs whole 16-byte groups");
+    if (valid >= IT && (((uintptr_t)p) & 15) == 0) {
+        const uint4* q = reinterpret_cast<const uint4*>(p);
+        constexpr int PER = 16 / sizeof(T);
+#pragma unroll
+        for (int k = 0; k < IT / PER; k++) {
+            const uint4 w = q[k];
+            const T* e = reinterpret_cast<const T*>(&w);
+#pragma unroll
+            for (int m = 0; m < PER; m++) r[k * PER + m] = e[m];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < IT; j++) r[j] = j < valid ? p[j] : (T)0;
+    }
+}
+
 template <typename K, bool HASV>
-__global__ __launch_bounds__(Shape<K>::NT) void k_tile_sort(TileArgs<K> a) {
+__global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(TileArgs<K> a) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
-    __shared__ SortSmem<NT> sm;
-    __shared__ K exch[T + T / 32];
+    __shared__ SortSmem<NT, (int)sizeof(K)> sm;
+    u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x;
     const int k = blockIdx.x / a.tpb, tt = blockIdx.x % a.tpb;
     const i64 st = blk_start(a.n, a.p, k), en = blk_start(a.n, a.p, k + 1);
@@ -115,114 +172,101 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_tile_sort(TileArgs<K> a) {
     i64 cnt64 = en - base;
     const int cnt = cnt64 <= 0 ? 0 : (cnt64 > T ? T : (int)cnt64);
     if (cnt == 0) return;
-    K mn = KeyMax<K>::v, mx = 0;
-    for (int i = t; i < cnt; i += NT) {
-        K u = okey<K>(a.in[base + i], a.in_dt);
-        exch[padi(i)] = u;
-        mn = u < mn ? u : mn;
-        mx = u > mx ? u : mx;
-    }
-    block_minmax<NT, K>(mn, mx, sm.red64);  // includes barriers
-    const int nbits = bitwidth64((u64)(mx - mn));
+    const int i0 = t * IT;
+    const int valid = cnt - i0;  // items of this thread: positions i0 .. i0+IT-1
+    K kr[IT];
     u32 v[IT], rank[IT];
-    u32* vex = reinterpret_cast<u32*>(exch);
-    const bool wide = sizeof(K) == 8 && nbits > 32;
-    if (wide) {
+    load_blocked<K, IT>(a.in + base + i0, valid, kr);
+    if (HASV) load_blocked<u32, IT>(a.inv + base + i0, valid, v);
+    K mn = KeyMax<K>::v, mx = 0;
+#pragma unroll
+    for (int j = 0; j < IT; j++) {
+        kr[j] = okey<K>(kr[j], a.in_dt);
+        if (j < valid) {
+            mn = kr[j] < mn ? kr[j] : mn;
+            mx = kr[j] > mx ? kr[j] : mx;
+        }
+    }
+    block_minmax<NT, K>(mn, mx, sm.red64);
+    const int nbits = bitwidth64((u64)(mx - mn));
+    const u32 ysh = a.ys ? (u32)(__ffs(a.ys) - 1) : 0u;
+    K* out = a.out + base;
+    const i64 sbase = (i64)blockIdx.x * a.spt;
+    if (sizeof(K) == 8 && nbits > 32) {
         u64 sk[IT];
 #pragma unroll
-        for (int j = 0; j < IT; j++) {
-            const int i = t * IT + j;
-            sk[j] = i < cnt ? (u64)(exch[padi(i)] - mn) : (u64)(mx - mn);
-        }
-        __syncthreads();
-        if (HASV) {
-            for (int i = t; i < cnt; i += NT) vex[padi(i)] = a.inv[base + i];
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < IT; j++) v[j] = vex[padi(t * IT + j)];
-            __syncthreads();
-        }
-        wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, nbits, reinterpret_cast<u64*>(exch), sm);
-        u64* ex = reinterpret_cast<u64*>(exch);
-        for (int i = t; i < cnt; i += NT) {
-            K u = (K)(ex[padi(i)] + (u64)mn);
-            a.out[base + i] = rawkey<K>(u, a.out_dt);
-            if (a.smp && ((i + 1) % a.ys) == 0) a.smp[(i64)blockIdx.x * a.spt + (i + 1) / a.ys - 1] = u;
-        }
+        for (int j = 0; j < IT; j++) sk[j] = j < valid ? (u64)(kr[j] - mn) : (u64)(mx - mn);
+        wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
+        store_sorted<K, u64, NT, IT>(sm.template ex<u64>(), mn, cnt, out, a.out_dt, a.smp, sbase, ysh);
     } else {
         u32 sk[IT];
 #pragma unroll
-        for (int j = 0; j < IT; j++) {
-            const int i = t * IT + j;
-            sk[j] = i < cnt ? (u32)(exch[padi(i)] - mn) : (u32)(mx - mn);
-        }
-        __syncthreads();
-        if (HASV) {
-            for (int i = t; i < cnt; i += NT) vex[padi(i)] = a.inv[base + i];
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < IT; j++) v[j] = vex[padi(t * IT + j)];
-            __syncthreads();
-        }
-        wg_sort_regs<NT, IT, u32, HASV>(sk, v, rank, nbits, vex, sm);
-        for (int i = t; i < cnt; i += NT) {
-            K u = (K)vex[padi(i)] + mn;
-            a.out[base + i] = rawkey<K>(u, a.out_dt);
-            if (a.smp && ((i + 1) % a.ys) == 0) a.smp[(i64)blockIdx.x * a.spt + (i + 1) / a.ys - 1] = u;
-        }
+        for (int j = 0; j < IT; j++) sk[j] = j < valid ? (u32)(kr[j] - mn) : (u32)(mx - mn);
+        wg_sort_regs<NT, IT, u32, HASV>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
+        store_sorted<K, u32, NT, IT>(vex, mn, cnt, out, a.out_dt, a.smp, sbase, ysh);
     }
     if (HASV) {
         wg_scatter_vals<NT, IT>(v, rank, vex);
-        for (int i = t; i < cnt; i += NT) a.outv[base + i] = vex[padi(i)];
+        u32* ov = a.outv + base;
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            const int i = j * NT + t;
+            if (i < cnt) ov[i] = vex[padi(i)];
+        }
     }
 }
 
 // ======================================================================= MWM: pick boundaries
 
 // One workgroup per group: sort (a regular subsample of) the group's samples
-// and keep every q-th as a chunk boundary.
+// and keep every q-th as a chunk boundary. The chunk target leaves room for
+// the spread of chunk sizes: a chunk holds q samples' worth of keys plus, per
+// run, less than one sample stride y more or fewer, so its size varies by
+// about y * sqrt(R / 3); the target is cap minus four such spreads (but at
+// least a.tavg, the floor the slot capacity was sized for).
 template <typename K>
 __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
-    __shared__ SortSmem<NT> sm;
-    __shared__ K exch[T + T / 32];
+    __shared__ SortSmem<NT, (int)sizeof(K)> sm;
     __shared__ u32 spre[MAXR + 1];
     __shared__ u32 sh_nb, sh_base;
+    u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x, g = blockIdx.x, R = a.R;
-    // prefix of the runs' sample counts, and the group size
-    u32 locS = 0, locN = 0;
-    for (int r = t; r < R; r += NT) {
-        locS += a.sdesc[((i64)g * R + r) * 4 + 1];
-        locN += a.run_len[(i64)g * R + r];
-    }
-    // chunked exclusive scan of sample counts in run order: thread t handles runs t*RPT..
+    const u32* sd = a.sdesc + (i64)g * R * 4;
+    // exclusive prefix of the runs' sample counts (runs in order), group size
     const int RPT = (R + NT - 1) / NT;
-    u32 mys = 0;
-    for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) mys += a.sdesc[((i64)g * R + r) * 4 + 1];
+    u32 mys = 0, myn = 0;
+    for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
+        mys += sd[r * 4 + 1];
+        myn += a.run_len[(i64)g * R + r];
+    }
     u32 totS;
     u32 ex = block_excl_scan<NT>(mys, totS, sm.wsum);
     for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
         spre[r] = ex;
-        ex += a.sdesc[((i64)g * R + r) * 4 + 1];
+        ex += sd[r * 4 + 1];
     }
     if (t == 0) spre[R] = totS;
-    u32 totN;
     __syncthreads();
-    (void)block_excl_scan<NT>(locN, totN, sm.wsum);
-    (void)locS;
+    u32 totN;
+    (void)block_excl_scan<NT>(myn, totN, sm.wsum);
     const u32 Sraw = totS, N = totN;
     u32 nb = 0, f = 1, Sg = 0, q = 1;
     if (N > a.cap && Sraw > 0) {
         f = (Sraw + T - 1) / T;
         Sg = Sraw / f;
-        u64 qq = ((u64)a.tavg * Sg + N - 1) / N;
+        const float yeff = (float)N / (float)Sg;
+        const float spread = 4.0f * yeff * sqrtf((float)R / 3.0f);
+        float tgf = (float)a.cap - spread;
+        u32 tg = tgf < (float)a.tavg ? a.tavg : (u32)tgf;
+        u64 qq = ((u64)tg * Sg + N - 1) / N;
         q = qq < 1 ? 1u : (u32)qq;
         nb = Sg / q;
     }
     if (t == 0) {
         u32 slots = N > 0 ? nb + 1 : 0;
         u32 b = slots ? atomicAdd(a.slot_count, slots) : 0u;
-        if (b + slots > a.S) { slots = 0; nb = 0; b = a.S; }  // cannot happen: slot bound n/tavg + G
+        if (b + slots > a.S) { slots = 0; b = a.S; }  // cannot happen: capacity n/tavg + G
         sh_base = b;
         sh_nb = slots ? nb : 0u;
         a.grp_base[g] = b;
@@ -245,13 +289,12 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
         key[j] = 0;
         if (i < Sg) {
             const u32 c = (i + 1) * f - 1;
-            int lo = 0, hi = R;  // largest r with spre[r] <= c
+            int lo = 0, hi = R;  // largest r with spre[r] <= c (a run with samples)
             while (hi - lo > 1) {
                 int mid = (lo + hi) >> 1;
                 if (spre[mid] <= c) lo = mid; else hi = mid;
             }
-            const u32 si = a.sdesc[((i64)g * R + lo) * 4 + 0] + (c - spre[lo]);
-            key[j] = a.smp[si];
+            key[j] = a.smp[sd[lo * 4 + 0] + (c - spre[lo])];
             v[j] = c;
             mn = key[j] < mn ? key[j] : mn;
             mx = key[j] > mx ? key[j] : mx;
@@ -259,21 +302,19 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     }
     block_minmax<NT, K>(mn, mx, sm.red64);
     const int nbits = bitwidth64((u64)(mx - mn));
-    u32* vex = reinterpret_cast<u32*>(exch);
     if (sizeof(K) == 8 && nbits > 32) {
         u64 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u64)(key[j] - mn) : (u64)(mx - mn);
-        wg_sort_regs<NT, IT, u64, true>(sk, v, rank, nbits, reinterpret_cast<u64*>(exch), sm);
-        // keep the boundary keys in registers of the threads that own them
-        u64* e = reinterpret_cast<u64*>(exch);
+        wg_sort_regs<NT, IT, u64, true>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
+        u64* e = sm.template ex<u64>();
 #pragma unroll
         for (int j = 0; j < IT; j++) key[j] = (K)(e[padi(t * IT + j)] + (u64)mn);
     } else {
         u32 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u32)(key[j] - mn) : (u32)(mx - mn);
-        wg_sort_regs<NT, IT, u32, true>(sk, v, rank, nbits, vex, sm);
+        wg_sort_regs<NT, IT, u32, true>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
 #pragma unroll
         for (int j = 0; j < IT; j++) key[j] = (K)vex[padi(t * IT + j)] + mn;
     }
@@ -290,9 +331,8 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
                 int mid = (lo + hi) >> 1;
                 if (spre[mid] <= c) lo = mid; else hi = mid;
             }
-            const u32* d = a.sdesc + ((i64)g * R + lo) * 4;
             a.bkey[gb + b - 1] = key[j];
-            a.bpos[gb + b - 1] = d[2] + (c - spre[lo]) * d[3];
+            a.bpos[gb + b - 1] = sd[lo * 4 + 2] + (c - spre[lo]) * sd[lo * 4 + 3];
         }
     }
 }
@@ -300,25 +340,41 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
 // ======================================================================= MWM: exact cuts
 
 // cuts[slot*R + r] = number of records of run r that are <= the boundary record
-// of that slot (key first, then position).
+// of that slot (key first, then position). The run's own samples (every
+// stride-th key, stored compactly) are searched first; the cut then lies
+// within one stride of the run, which is searched last.
 template <typename K>
 __global__ void k_mwm_cuts(MwmArgs<K> a) {
-    const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    const u32 slot = (u32)(idx / a.R);
-    const int r = (int)(idx % a.R);
-    if (slot >= *a.slot_count || slot >= a.S) return;
-    const u32 g = a.slot_group[slot];
-    const u32 c = slot - a.grp_base[g];
-    if (c >= a.grp_nb[g]) return;
-    const K bk = a.bkey[slot];
-    const u32 bp = a.bpos[slot];
-    const u32 rs = a.run_start[(i64)g * a.R + r];
-    u32 lo = 0, hi = a.run_len[(i64)g * a.R + r];
-    while (lo < hi) {
-        const u32 mid = (lo + hi) >> 1;
-        if (rec_le<K>(a.src[rs + mid], rs + mid, bk, bp)) lo = mid + 1; else hi = mid;
+    const u32 nslot = min(a.S, *a.slot_count);
+    const i64 total = (i64)nslot * a.R;
+    for (i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
+        const u32 slot = (u32)(idx / a.R);
+        const int r = (int)(idx % a.R);
+        const u32 g = a.slot_group[slot];
+        const u32 c = slot - a.grp_base[g];
+        if (c >= a.grp_nb[g]) continue;
+        const K bk = a.bkey[slot];
+        const u32 bp = a.bpos[slot];
+        const i64 gr = (i64)g * a.R + r;
+        const u32 rs = a.run_start[gr];
+        const u32 len = a.run_len[gr];
+        const u32* d = a.sdesc + gr * 4;
+        const u32 sidx = d[0], scnt = d[1], pb = d[2], sstr = d[3];
+        // J = samples of this run that are <= the boundary
+        u32 lo = 0, hi = scnt;
+        while (lo < hi) {
+            const u32 mid = (lo + hi) >> 1;
+            if (rec_le<K>(a.smp[sidx + mid], pb + mid * sstr, bk, bp)) lo = mid + 1; else hi = mid;
+        }
+        const u32 J = lo;
+        u32 wlo = J > 0 ? pb + (J - 1) * sstr - rs + 1 : 0u;
+        u32 whi = J < scnt ? pb + J * sstr - rs : len;
+        while (wlo < whi) {
+            const u32 mid = (wlo + whi) >> 1;
+            if (rec_le<K>(a.src[rs + mid], rs + mid, bk, bp)) wlo = mid + 1; else whi = mid;
+        }
+        a.cuts[(i64)slot * a.R + r] = wlo;
     }
-    a.cuts[(i64)slot * a.R + r] = lo;
 }
 
 // ======================================================================= MWM: chunk sort
@@ -327,7 +383,7 @@ template <typename K, bool HASV>
 __device__ void mwm_emit(const MwmArgs<K>& a, u32 g, u32 o, K u, u32 gstart) {
     if (a.osmp) {
         const u32 rel = o - gstart + 1;
-        if (rel % a.oys == 0) a.osmp[(i64)g * a.ospb + rel / a.oys - 1] = u;
+        if ((rel & (a.oys - 1)) == 0) a.osmp[(i64)g * a.ospb + rel / a.oys - 1] = u;
     }
 }
 
@@ -336,7 +392,7 @@ __device__ void mwm_emit(const MwmArgs<K>& a, u32 g, u32 o, K u, u32 gstart) {
 // digit passes alternating scr <-> dst; the last step writes dst.
 template <typename K, bool HASV>
 __device__ void mwm_oversize(const MwmArgs<K>& a, u32 g, u32 slot, u32 c, u32 nb, const u32* ppre, u32 N,
-                             u32 out, SortSmem<Shape<K>::NT>& sm, K* exch) {
+                             u32 out, SortSmem<Shape<K>::NT, (int)sizeof(K)>& sm, K* exch) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
     const int t = threadIdx.x, R = a.R;
     const int lane = t & 63, w = t >> 6, NW = NT / 64;
@@ -398,7 +454,7 @@ __device__ void mwm_oversize(const MwmArgs<K>& a, u32 g, u32 slot, u32 c, u32 nb
                 u32 inc = wave_incl_scan(hv);
                 tbase[t] = inc - hv;
             }
-            radix_rank<NT, IT>(dig, rank, sm);  // begins with a barrier-protected reset
+            radix_rank<NT, IT>([&](int j) { return dig[j]; }, rank, sm.cnt(), sm.wsum);
 #pragma unroll
             for (int j = 0; j < IT; j++) {
                 const u32 i = b0 + t * IT + j;
@@ -430,114 +486,174 @@ __device__ void mwm_oversize(const MwmArgs<K>& a, u32 g, u32 slot, u32 c, u32 nb
     (void)nb;
 }
 
+template <typename K>
+struct MergeSmem {
+    static constexpr int NT = Shape<K>::NT, T = NT * Shape<K>::IT;
+    SortSmem<NT, (int)sizeof(K)> sm;
+    u32 ppre[MAXR + 1];   // chunk offset of each piece
+    u32 soff[MAXR];       // source position of each piece
+    u32 slot;
+};
+
 template <typename K, bool HASV>
-__global__ __launch_bounds__(Shape<K>::NT) void k_mwm_merge(MwmArgs<K> a) {
-    constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
-    __shared__ SortSmem<NT> sm;
-    __shared__ K exch[T + T / 32];
-    __shared__ u32 ppre[MAXR + 1];
+__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 slot, MergeSmem<K>& S);
+
+// Persistent merge: workgroups take chunks (slots) one after another.
+template <typename K, bool HASV>
+__global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_mwm_merge(MwmArgs<K> a) {
+    __shared__ MergeSmem<K> S;
+    const u32 nslot = min(a.S, *a.slot_count);
+    for (;;) {
+        if (threadIdx.x == 0) S.slot = atomicAdd(a.work, 1u);
+        __syncthreads();
+        const u32 slot = S.slot;
+        __syncthreads();
+        if (slot >= nslot) break;
+        mwm_merge_chunk<K, HASV>(a, slot, S);
+        __syncthreads();
+    }
+}
+
+template <typename K, bool HASV>
+__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 slot, MergeSmem<K>& S) {
+    constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
+    auto& sm = S.sm;
+    u32* ppre = S.ppre;
+    u32* soff = S.soff;
+    K* exch = sm.template ex<K>();
+    u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x, R = a.R;
-    const u32 slot = blockIdx.x;
-    if (slot >= *a.slot_count || slot >= a.S) return;
+    PHASE_START;
     const u32 g = a.slot_group[slot];
     const u32 c = slot - a.grp_base[g];
     const u32 nb = a.grp_nb[g];
+    const u32* lorow = a.cuts + (i64)(slot - 1) * R;
+    const u32* hirow = a.cuts + (i64)slot * R;
+    const u32* rl = a.run_len + (i64)g * R;
+    const u32* rsp = a.run_start + (i64)g * R;
     // piece lengths and their prefix (runs in order)
     const int RPT = (R + NT - 1) / NT;
     u32 mysum = 0, mylo = 0;
     for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
-        const u32 lo = c == 0 ? 0u : a.cuts[(i64)(slot - 1) * R + r];
-        const u32 hi = c == nb ? a.run_len[(i64)g * R + r] : a.cuts[(i64)slot * R + r];
+        const u32 lo = c == 0 ? 0u : lorow[r];
+        const u32 hi = c == nb ? rl[r] : hirow[r];
         mysum += hi - lo;
         mylo += lo;
     }
     u32 N;
     u32 ex = block_excl_scan<NT>(mysum, N, sm.wsum);
     for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
-        const u32 lo = c == 0 ? 0u : a.cuts[(i64)(slot - 1) * R + r];
-        const u32 hi = c == nb ? a.run_len[(i64)g * R + r] : a.cuts[(i64)slot * R + r];
+        const u32 lo = c == 0 ? 0u : lorow[r];
+        const u32 hi = c == nb ? rl[r] : hirow[r];
         ppre[r] = ex;
+        soff[r] = rsp[r] + lo;
         ex += hi - lo;
     }
     if (t == 0) ppre[R] = N;
-    u32 LO;
     __syncthreads();
+    u32 LO;
     (void)block_excl_scan<NT>(mylo, LO, sm.wsum);
     const u32 out = a.out_base[g] + LO;
     if (N == 0) return;
+    PHASE(0);
     if (N > a.cap) {
         if (t == 0) atomicAdd(a.oversize, 1u);
         mwm_oversize<K, HASV>(a, g, slot, c, nb, ppre, N, out, sm, exch);
         return;
     }
-    // gather pieces into LDS in run order (one wave per piece)
-    const int lane = t & 63, w = t >> 6, NW = NT / 64;
+    PHASE(1);
+    // blocked gather: thread t loads chunk positions t*IT .. t*IT+IT-1, walking
+    // the pieces from the one that holds its first position
+    const u32 i0 = (u32)(t * IT);
+    K kr[IT];
+    u32 v[IT], rank[IT];
     K mn = KeyMax<K>::v, mx = 0;
-    for (int r = w; r < R; r += NW) {
-        const u32 lo = c == 0 ? 0u : a.cuts[(i64)(slot - 1) * R + r];
-        const u32 len = ppre[r + 1] - ppre[r];
-        const K* s = a.src + a.run_start[(i64)g * R + r] + lo;
-        const u32 o = ppre[r];
-        for (u32 i = lane; i < len; i += 64) {
-            K u = s[i];
-            exch[padi((int)(o + i))] = u;
-            mn = u < mn ? u : mn;
-            mx = u > mx ? u : mx;
+    if (i0 < N) {
+        u32 lo = 0, hi = (u32)R - 1;  // largest piece r with ppre[r] <= i0 (a nonempty one)
+        while (lo < hi) {
+            const u32 mid = (lo + hi + 1) >> 1;
+            if (ppre[mid] <= i0) lo = mid; else hi = mid - 1;
         }
+        u32 r = lo, nxt = ppre[lo + 1], sb = soff[lo] - ppre[lo];
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            const u32 i = i0 + j;
+            kr[j] = 0;
+            v[j] = 0;
+            if (i < N) {
+                while (i >= nxt) {
+                    r++;
+                    nxt = ppre[r + 1];
+                    sb = soff[r] - ppre[r];
+                }
+                kr[j] = a.src[sb + i];
+                if (HASV) v[j] = a.srcv[sb + i];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            if (i0 + j < N) {
+                mn = kr[j] < mn ? kr[j] : mn;
+                mx = kr[j] > mx ? kr[j] : mx;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < IT; j++) { kr[j] = 0; v[j] = 0; }
     }
     block_minmax<NT, K>(mn, mx, sm.red64);
+    PHASE(2);
     const int nbits = bitwidth64((u64)(mx - mn));
-    u32 v[IT], rank[IT];
-    u32* vex = reinterpret_cast<u32*>(exch);
     const u32 gstart = a.out_base[g];
-    auto load_vals = [&]() {
-        for (int r = w; r < R; r += NW) {
-            const u32 lo = c == 0 ? 0u : a.cuts[(i64)(slot - 1) * R + r];
-            const u32 len = ppre[r + 1] - ppre[r];
-            const u32* s = a.srcv + a.run_start[(i64)g * R + r] + lo;
-            const u32 o = ppre[r];
-            for (u32 i = lane; i < len; i += 64) vex[padi((int)(o + i))] = s[i];
+    const u32 osh = a.oys ? (u32)(__ffs(a.oys) - 1) : 0u;
+    const u32 om = (1u << osh) - 1;
+    K* dst = a.dst + out;
+    auto emit = [&](u32 i, K u) {
+        if (a.osmp) {
+            const u32 rel = out + i - gstart + 1;
+            if ((rel & om) == 0) a.osmp[(i64)g * a.ospb + (rel >> osh) - 1] = u;
         }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < IT; j++) v[j] = vex[padi(t * IT + j)];
-        __syncthreads();
     };
     if (sizeof(K) == 8 && nbits > 32) {
         u64 sk[IT];
 #pragma unroll
+        for (int j = 0; j < IT; j++) sk[j] = i0 + j < N ? (u64)(kr[j] - mn) : (u64)(mx - mn);
+        wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
+        const u64* e = sm.template ex<u64>();
+#pragma unroll
         for (int j = 0; j < IT; j++) {
-            const u32 i = (u32)(t * IT + j);
-            sk[j] = i < N ? (u64)(exch[padi((int)i)] - mn) : (u64)(mx - mn);
-        }
-        __syncthreads();
-        if (HASV) load_vals();
-        wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, nbits, reinterpret_cast<u64*>(exch), sm);
-        u64* e = reinterpret_cast<u64*>(exch);
-        for (u32 i = t; i < N; i += NT) {
-            K u = (K)(e[padi((int)i)] + (u64)mn);
-            a.dst[out + i] = rawkey<K>(u, a.out_dt);
-            mwm_emit<K, HASV>(a, g, out + i, u, gstart);
+            const u32 i = (u32)(j * NT + t);
+            if (i < N) {
+                const K u = (K)(e[padi((int)i)] + (u64)mn);
+                dst[i] = rawkey<K>(u, a.out_dt);
+                emit(i, u);
+            }
         }
     } else {
         u32 sk[IT];
 #pragma unroll
+        for (int j = 0; j < IT; j++) sk[j] = i0 + j < N ? (u32)(kr[j] - mn) : (u32)(mx - mn);
+        wg_sort_regs<NT, IT, u32, HASV>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
+        PHASE(3);
+#pragma unroll
         for (int j = 0; j < IT; j++) {
-            const u32 i = (u32)(t * IT + j);
-            sk[j] = i < N ? (u32)(exch[padi((int)i)] - mn) : (u32)(mx - mn);
+            const u32 i = (u32)(j * NT + t);
+            if (i < N) {
+                const K u = (K)vex[padi((int)i)] + mn;
+                dst[i] = rawkey<K>(u, a.out_dt);
+                emit(i, u);
+            }
         }
-        __syncthreads();
-        if (HASV) load_vals();
-        wg_sort_regs<NT, IT, u32, HASV>(sk, v, rank, nbits, vex, sm);
-        for (u32 i = t; i < N; i += NT) {
-            K u = (K)vex[padi((int)i)] + mn;
-            a.dst[out + i] = rawkey<K>(u, a.out_dt);
-            mwm_emit<K, HASV>(a, g, out + i, u, gstart);
-        }
+        PHASE(4);
     }
     if (HASV) {
         wg_scatter_vals<NT, IT>(v, rank, vex);
-        for (u32 i = t; i < N; i += NT) a.dstv[out + i] = vex[padi((int)i)];
+        u32* dv = a.dstv + out;
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            const u32 i = (u32)(j * NT + t);
+            if (i < N) dv[i] = vex[padi((int)i)];
+        }
     }
 }
 

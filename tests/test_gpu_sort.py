@@ -94,7 +94,7 @@ def test_ragged_random(ora, dev, dtype, variant):
 @pytest.mark.parametrize("n", [2, 3, 17, 1000, 16383, 16384, 16385, 50001])
 def test_edges(ora, dev, n):
     keys = W.random_keys(n, "int32", seed=n, distinct=max(1, n // 4))
-    for p in sorted({1, 2, min(n, 7), min(n, 4096)}):
+    for p in sorted({1, 2, min(n, 7), min(n, 1024)}):
         _check(ora, dev, keys, p, 3, ora.DET)
 
 
@@ -103,7 +103,7 @@ def test_p_limit(dev):
     import paper_1408_6729_amd as bsps
     t = torch.zeros(5000, dtype=torch.int32, device=dev)
     with pytest.raises(bsps.BspsError) as e:
-        bsps.sort_(t, 4097, 1, bsps.DET)
+        bsps.sort_(t, 1025, 1, bsps.DET)
     assert e.value.code == bsps.EUNSUPPORTED
 
 
