@@ -189,11 +189,12 @@ size_t bsps_fit_workspace_bytes(int64_t N, int32_t leaves);
  * parameters, writes out_leaf[t] (device, N int32), out_grad (device, 2L
  * float: dLoss/dc, dLoss/dd per leaf) and out_gram (device, 3L float:
  * sum (x-mu)^2, sum (x-mu), count, all times 2/N), and the loss to *out_loss
- * (device, 1 float). Loss = (1/N) sum_t (f(x_t) - y_t)^2.
+ * (device, 1 float). Loss = (1/N) sum_t (f(x_t) - y_t)^2. ws: device,
+ * bsps_fit_workspace_bytes(N, leaves) bytes.
  */
 bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int32_t p, int32_t s,
                             int32_t leaves, const void* model, int32_t* out_leaf, float* out_grad,
-                            float* out_gram, float* out_loss, void* stream);
+                            float* out_gram, float* out_loss, void* ws, size_t ws_bytes, void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* bsps_status_string(int32_t status);
@@ -201,6 +202,20 @@ const char* bsps_status_string(int32_t status);
 const char* bsps_tuning_format(void);
 /* Frees the library's cached graph executables (its only owned state). */
 void bsps_release_cache(void);
+
+/*
+ * Diagnostics: per-stage timing with HIP events recorded on the caller's
+ * stream around every stage of the following calls. Stages (index):
+ *   0 tile sorts, 1 block merge, 2 sample + sample sort + splitters,
+ *   3 bucket ranking, 4 prefix sums / routing, 5 bucket merge,
+ *   6 merge kernel of the block merge, 7 merge kernel of the bucket merge,
+ *   8 per-key ranking kernel.
+ * bsps_timing_read waits for the recorded events and returns, for the first
+ * nstage stages, the summed milliseconds (ms, HOST) and launch counts
+ * (launches, HOST); reset != 0 clears the record. Not thread safe.
+ */
+int bsps_timing(int enable);
+int bsps_timing_read(double* ms, int64_t* launches, int nstage, int reset);
 
 #ifdef __cplusplus
 }

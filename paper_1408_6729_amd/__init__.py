@@ -60,6 +60,20 @@ def _load():
     L.bsps_sort_kv.argtypes = [vp, vp, i64, i32, PP, vp, sz, vp, SP]
     L.bsps_status_string.restype = ct.c_char_p
     L.bsps_status_string.argtypes = [i32]
+    L.bsps_rank.restype = i32
+    L.bsps_rank.argtypes = [vp, i64, i32, i32, vp, vp, i32, vp, vp, vp, vp, sz, vp, SP]
+    L.bsps_rank_workspace_bytes.restype = sz
+    L.bsps_rank_workspace_bytes.argtypes = [i64, i32]
+    L.bsps_model_bytes.restype = sz
+    L.bsps_model_bytes.argtypes = [i32]
+    L.bsps_fit_workspace_bytes.restype = sz
+    L.bsps_fit_workspace_bytes.argtypes = [i64, i32]
+    L.bsps_fit_model.restype = i32
+    L.bsps_fit_model.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, sz, vp]
+    L.bsps_model_grad.restype = i32
+    L.bsps_model_grad.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.bsps_timing.argtypes = [ct.c_int]
+    L.bsps_timing_read.argtypes = [vp, vp, ct.c_int, ct.c_int]
     return L
 
 
@@ -165,3 +179,75 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
     out["mean_fix_dist"] = st.mean_fix_dist
     out["oversize_chunks"] = st.oversize_chunks
     return out
+
+
+def _ptr(t):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def rank(keys, p: int, spl_keys, spl_pos, bucketing: int = SPLITTER, model=None, buckets=None, counts=None,
+         stats: bool = False):
+    """Bucket of every key of a block-sorted array (dtype of `keys`) against the
+    p-1 splitter records (spl_keys same dtype, spl_pos uint32 as int32 tensor).
+    Fills `buckets` (n, int32 view of uint32) and `counts` (p*p) when given."""
+    import torch
+    n = keys.numel()
+    dt = _dtype_code(keys)
+    ws = torch.empty(_lib.bsps_rank_workspace_bytes(n, p), dtype=torch.uint8, device=keys.device)
+    st = Stats() if stats else None
+    code = _lib.bsps_rank(_ptr(keys), n, dt, p, _ptr(spl_keys), _ptr(spl_pos), bucketing, _ptr(model),
+                          _ptr(buckets), _ptr(counts), _ptr(ws), ws.numel(), ct.c_void_p(_stream(keys)),
+                          ct.byref(st) if st is not None else None)
+    if code != OK:
+        raise BspsError(code, "bsps_rank")
+    if stats:
+        return {"mispredict_rate": st.mispredict_rate, "mean_fix_dist": st.mean_fix_dist}
+    return None
+
+
+def model_bytes(leaves: int) -> int:
+    return int(_lib.bsps_model_bytes(leaves))
+
+
+def fit_model(sample_keys, p: int, s: int, leaves: int = 4096, iters: int = 2):
+    """Trains the learned bucketing model on a sorted sample (dtype of the
+    tensor) with the library's forward / backward / Newton-update kernels.
+    Returns the device model buffer (uint8 tensor)."""
+    import torch
+    N = sample_keys.numel()
+    model = torch.zeros(model_bytes(leaves), dtype=torch.uint8, device=sample_keys.device)
+    ws = torch.empty(_lib.bsps_fit_workspace_bytes(N, leaves), dtype=torch.uint8, device=sample_keys.device)
+    code = _lib.bsps_fit_model(_ptr(sample_keys), N, _dtype_code(sample_keys), p, s, leaves, iters, _ptr(model),
+                               _ptr(ws), ws.numel(), ct.c_void_p(_stream(sample_keys)))
+    if code != OK:
+        raise BspsError(code, "bsps_fit_model")
+    return model
+
+
+def model_grad(sample_keys, p: int, s: int, leaves: int, model):
+    """Forward + backward of the leaf stage at the model's parameters:
+    returns (leaf ids, gradient [2L], Gram sums [3L], loss) as tensors."""
+    import torch
+    N = sample_keys.numel()
+    d = sample_keys.device
+    leaf = torch.empty(N, dtype=torch.int32, device=d)
+    grad = torch.empty(2 * leaves, dtype=torch.float32, device=d)
+    gram = torch.empty(3 * leaves, dtype=torch.float32, device=d)
+    loss = torch.empty(1, dtype=torch.float32, device=d)
+    ws = torch.empty(_lib.bsps_fit_workspace_bytes(N, leaves), dtype=torch.uint8, device=d)
+    code = _lib.bsps_model_grad(_ptr(sample_keys), N, _dtype_code(sample_keys), p, s, leaves, _ptr(model),
+                                _ptr(leaf), _ptr(grad), _ptr(gram), _ptr(loss), _ptr(ws), ws.numel(),
+                                ct.c_void_p(_stream(sample_keys)))
+    if code != OK:
+        raise BspsError(code, "bsps_model_grad")
+    return leaf, grad, gram, loss
+
+
+def model_fields(model):
+    """Host view of a model buffer: header dict and (L, 3) float32 leaf table."""
+    raw = model.cpu().numpy()
+    lo, hi = np.frombuffer(raw[:16].tobytes(), dtype=np.float64)
+    a, b, mur, inv = np.frombuffer(raw[16:32].tobytes(), dtype=np.float32)
+    L, p, s, _ = np.frombuffer(raw[32:48].tobytes(), dtype=np.int32)
+    leaf = np.frombuffer(raw[48:48 + 12 * int(L)].tobytes(), dtype=np.float32).reshape(int(L), 3)
+    return {"lo": lo, "hi": hi, "a": a, "b": b, "mur": mur, "inv": inv, "L": int(L), "p": int(p), "s": int(s)}, leaf

@@ -55,6 +55,51 @@ struct Carver {
 
 int key_bytes(int dt) { return dt == BSPS_I64 ? 8 : 4; }
 
+// Optional per-stage timing with HIP events recorded on the caller's stream
+// around each stage (diagnostics and benchmarks only).
+enum Stage {
+    ST_TILE = 0,       // A1: tile sorts
+    ST_BLOCK_MERGE,    // A1: block merge (pick + cuts + merge)
+    ST_SAMPLE,         // A2 + A3: sample, sample sort, splitters
+    ST_COUNT,          // A4: splitter search into blocks (or per-key ranking)
+    ST_TABLES,         // A5: prefix sums / bucket tables (and scatter)
+    ST_BUCKET_MERGE,   // A6: bucket merge (pick + cuts + merge)
+    ST_BLOCK_MERGE_K,  // k_mwm_merge alone, block merge
+    ST_BUCKET_MERGE_K, // k_mwm_merge alone, bucket merge
+    ST_RANK_K,         // per-key rank kernel alone
+    ST_N
+};
+struct StageTimer {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ST_N];
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+};
+StageTimer g_timer;
+struct StageScope {
+    int stage;
+    hipStream_t st;
+    hipEvent_t e0 = nullptr;
+    StageScope(int s_, hipStream_t st_) : stage(s_), st(st_) {
+        if (stage < ST_N && g_timer.on && (e0 = g_timer.get()) && hipEventRecord(e0, st) != hipSuccess) e0 = nullptr;
+    }
+    ~StageScope() {
+        if (!e0) return;
+        hipEvent_t e1 = g_timer.get();
+        if (!e1 || hipEventRecord(e1, st) != hipSuccess) return;
+        g_timer.ev[stage].push_back({e0, e1});
+    }
+};
+
 template <typename K> constexpr u32 tileT() { return (u32)(Shape<K>::NT * Shape<K>::IT); }
 
 // Device buffers of one multiway merge.
@@ -111,7 +156,7 @@ int device_cus() {
 }
 
 template <typename K, bool HASV>
-bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st) {
+bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     constexpr int NT = Shape<K>::NT;
     const int cus = device_cus();
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.slot_count, 4);
@@ -126,7 +171,10 @@ bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st) {
 #define BSPS_MERGE_WGS_PER_CU 2
 #endif
     const u32 gmerge = BSPS_MERGE_WGS_PER_CU > 0 ? (u32)std::min<u64>(a.S, (u64)cus * BSPS_MERGE_WGS_PER_CU) : a.S;
-    hipLaunchKernelGGL((k_mwm_merge<K, HASV>), dim3(gmerge), dim3(NT), 0, st, a);
+    {
+        StageScope sc(kstage, st);
+        hipLaunchKernelGGL((k_mwm_merge<K, HASV>), dim3(gmerge), dim3(NT), 0, st, a);
+    }
     LAUNCH_OK();
     return BSPS_OK;
 }
@@ -171,26 +219,91 @@ void carve_block_sort(Carver& c, BlockSortBufs<K>& b, u64 n, int p, bool hasv, u
 template <typename K, bool HASV>
 bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, int in_dt, K* out, u32* outv,
                        int out_dt, K* scr, u32* scrv, i64 n, int p, u32 cap, u32 tavg, K* osmp, u32 yb, u32 spb,
-                       hipStream_t st) {
+                       hipStream_t st, int tstage = ST_N, int mstage = ST_N, int mkstage = ST_N) {
     constexpr int NT = Shape<K>::NT;
     const u32 T = tileT<K>();
     TileArgs<K> ta;
     ta.in = in; ta.inv = inv; ta.n = n; ta.p = p; ta.tpb = b.tpb; ta.in_dt = in_dt;
     if (b.tpb == 1) {
         ta.out = out; ta.outv = outv; ta.out_dt = out_dt; ta.smp = osmp; ta.ys = yb; ta.spt = spb;
+        StageScope sc(tstage, st);
         hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3(p), dim3(NT), 0, st, ta);
         LAUNCH_OK();
         return BSPS_OK;
     }
     ta.out = b.A; ta.outv = b.Av; ta.out_dt = BSPS_DT_NONE; ta.smp = b.tsmp; ta.ys = kSampleStride; ta.spt = b.spt;
-    hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3((u32)(p * b.tpb)), dim3(NT), 0, st, ta);
+    {
+        StageScope sc(tstage, st);
+        hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3((u32)(p * b.tpb)), dim3(NT), 0, st, ta);
+    }
     LAUNCH_OK();
+    StageScope sc(mstage, st);
     const u64 nrun = (u64)p * b.tpb;
     hipLaunchKernelGGL((k_block_tables<K>), dim3((u32)cdiv(nrun, 256)), dim3(256), 0, st, n, p, b.tpb, T,
                        kSampleStride, b.spt, b.mwm.run_start, b.mwm.run_len, b.mwm.out_base, b.mwm.sdesc);
     LAUNCH_OK();
     MwmArgs<K> a = mwm_args<K>(b.mwm, b.A, b.Av, out, outv, scr, scrv, b.tsmp, cap, tavg, out_dt, osmp, yb, spb);
-    return mwm_run<K, HASV>(a, st);
+    return mwm_run<K, HASV>(a, st, mkstage);
+}
+
+// ------------------------------------------------------------------ learned model
+
+struct FitWs {
+    float* x;
+    int32_t* leafid;
+    float* r;
+    int32_t* lo;
+    float *g, *hs, *lossp, *loss;
+};
+
+FitWs carve_fit(Carver& c, i64 N, int L) {
+    FitWs f;
+    const i64 N1 = std::max<i64>(1, N);
+    f.x = c.take<float>(N1);
+    f.leafid = c.take<int32_t>(N1);
+    f.r = c.take<float>(N1);
+    f.lo = c.take<int32_t>((u64)L + 2);
+    f.g = c.take<float>(2 * (u64)L);
+    f.hs = c.take<float>(3 * (u64)L);
+    f.lossp = c.take<float>(L);
+    f.loss = c.take<float>(4);
+    return f;
+}
+
+// Trains the two-stage model on the sorted sample (root, then leaves):
+// forward (residuals), backward (gradient + Gram sums), Newton update, `iters`
+// times per stage.
+template <typename K>
+bsps_status fit_model(const K* smp, i64 N, int dt, int p, int s, int L, int iters, void* model, void* ws,
+                      hipStream_t st) {
+    Carver c(ws);
+    FitWs f = carve_fit(c, N, L);
+    const u32 gN = (u32)std::max<u64>(1, cdiv((u64)N, 256));
+    hipLaunchKernelGGL((k_model_init<K>), dim3(1), dim3(64), 0, st, smp, N, dt, p, s, L, model);
+    LAUNCH_OK();
+    for (int stage = 0; stage < 2; stage++) {
+        const int nmod = stage == 0 ? 1 : L;
+        const u32 gM = (u32)cdiv((u64)nmod + 1, 256);
+        hipLaunchKernelGGL((k_model_x<K>), dim3(gN), dim3(256), 0, st, smp, N, dt, (const void*)model, stage, f.x,
+                           f.leafid);
+        LAUNCH_OK();
+        hipLaunchKernelGGL(k_model_ranges, dim3(gM), dim3(256), 0, st, f.leafid, N, nmod, f.lo);
+        LAUNCH_OK();
+        hipLaunchKernelGGL(k_model_centres, dim3(gM), dim3(256), 0, st, f.x, f.lo, nmod, model, stage);
+        LAUNCH_OK();
+        for (int it = 0; it < iters; it++) {
+            hipLaunchKernelGGL(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, f.leafid, N, p, s,
+                               (const void*)model, stage, f.r);
+            LAUNCH_OK();
+            hipLaunchKernelGGL(k_model_backward, dim3(gM), dim3(256), 0, st, f.x, f.r, f.lo, nmod, N,
+                               (const void*)model, stage, f.g, f.hs, f.lossp);
+            LAUNCH_OK();
+            hipLaunchKernelGGL(k_model_update, dim3(gM), dim3(256), 0, st, f.g, f.hs, f.lo, nmod, p, s, model,
+                               stage);
+            LAUNCH_OK();
+        }
+    }
+    return BSPS_OK;
 }
 
 // ------------------------------------------------------------------ plan
@@ -280,12 +393,12 @@ size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* pr
     P.fitws_bytes = 0;
     if (scatter) {
         P.bucket = c.take<u32>(n);
-        P.C = c.take<u32>((u64)p * p);
+        P.C = c.take<u32>((u64)p * p + 4);
         P.off = c.take<u32>((u64)p * p);
         if (prm->bucketing == BSPS_LEARNED) {
             const int L = prm->leaves > 0 ? prm->leaves : 4096;
             P.model = c.take<char>(bsps_model_bytes(L));
-            P.fitws_bytes = bsps_fit_workspace_bytes(P.ns, L);
+            P.fitws_bytes = bsps_fit_workspace_bytes(P.ns, L);  // carve_fit layout
             P.fitws = c.take<char>(P.fitws_bytes);
         }
     }
@@ -361,7 +474,8 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
     bsps_status rc;
     // A1: every virtual processor sorts its block (stable).
     rc = block_sort<K, HASV>(P.bs, io, vals, dt, P.B, P.Bv, BSPS_DT_NONE, io, vals, n, p, o.cap, o.tavg, P.bsmp,
-                             kSampleStride, std::max<u32>(1, P.spb), st);
+                             kSampleStride, std::max<u32>(1, P.spb), st, ST_TILE, ST_BLOCK_MERGE,
+                             ST_BLOCK_MERGE_K);
     if (rc) return rc;
     if (stats && stats->block_sorted) {
         rc = copy_keys_out<K>(stats->block_sorted, P.B, n, dt, st);
@@ -383,42 +497,113 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         }
         return BSPS_OK;
     }
-    // A2: sample records (key, position in B), in position order.
     const i64 ns = P.ns;
-    if (prm->variant == BSPS_DET) {
-        hipLaunchKernelGGL((k_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, n, p, s, P.skey,
-                           P.spos);
-        LAUNCH_OK();
-    } else {
-        hipLaunchKernelGGL(k_ran_positions, dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, (u64)prm->seed, n, ns,
-                           P.rpos);
-        LAUNCH_OK();
-        const Opts ou = opts_for<u32>(prm);
-        rc = block_sort<u32, false>(P.rs, P.rpos, nullptr, BSPS_DT_NONE, P.spos, nullptr, BSPS_DT_NONE, P.rpos_scr,
-                                    nullptr, ns, 1, ou.cap, ou.tavg, nullptr, 1, 1, st);
+    {
+        StageScope sc(ST_SAMPLE, st);
+        // A2: sample records (key, position in B), in position order.
+        if (prm->variant == BSPS_DET) {
+            hipLaunchKernelGGL((k_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, n, p, s, P.skey,
+                               P.spos);
+            LAUNCH_OK();
+        } else {
+            hipLaunchKernelGGL(k_ran_positions, dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, (u64)prm->seed, n, ns,
+                               P.rpos);
+            LAUNCH_OK();
+            const Opts ou = opts_for<u32>(prm);
+            rc = block_sort<u32, false>(P.rs, P.rpos, nullptr, BSPS_DT_NONE, P.spos, nullptr, BSPS_DT_NONE, P.rpos_scr,
+                                        nullptr, ns, 1, ou.cap, ou.tavg, nullptr, 1, 1, st);
+            if (rc) return rc;
+            hipLaunchKernelGGL((k_gather_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, P.spos, ns,
+                               P.skey);
+            LAUNCH_OK();
+        }
+        // A3: sort the sample by (key, position): stable by key, input in position order.
+        rc = block_sort<K, true>(P.ss, P.skey, P.spos, BSPS_DT_NONE, P.ssk, P.ssp, BSPS_DT_NONE, P.sscr, P.sscrv, ns, 1,
+                                 o.cap, o.tavg, nullptr, 1, 1, st);
         if (rc) return rc;
-        hipLaunchKernelGGL((k_gather_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, P.spos, ns,
-                           P.skey);
+        hipLaunchKernelGGL((k_splitters<K>), dim3((u32)cdiv(p, 256)), dim3(256), 0, st, P.ssk, P.ssp, p, s, P.pk, P.pp);
         LAUNCH_OK();
     }
-    // A3: sort the sample by (key, position): stable by key, input in position order.
-    rc = block_sort<K, true>(P.ss, P.skey, P.spos, BSPS_DT_NONE, P.ssk, P.ssp, BSPS_DT_NONE, P.sscr, P.sscrv, ns, 1,
-                             o.cap, o.tavg, nullptr, 1, 1, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL((k_splitters<K>), dim3((u32)cdiv(p, 256)), dim3(256), 0, st, P.ssk, P.ssp, p, s, P.pk, P.pp);
-    LAUNCH_OK();
-    // A4: bucket boundaries inside every sorted block.
-    const u64 ncnt = (u64)(p + 1) * p;
-    hipLaunchKernelGGL((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pp, P.cntT);
-    LAUNCH_OK();
-    // A5: prefix sums -> runs of every bucket. A6: merge them (routing fused).
-    hipLaunchKernelGGL(k_bucket_tables, dim3(p), dim3(256), 0, st, n, p, P.cntT, kSampleStride,
-                       std::max<u32>(1, P.spb), (const u32*)nullptr, P.bm.run_start, P.bm.run_len, P.bm.out_base,
-                       P.bm.sdesc);
-    LAUNCH_OK();
-    MwmArgs<K> a = mwm_args<K>(P.bm, P.B, P.Bv, io, vals, P.bs.A, P.bs.Av, P.bsmp, o.cap, o.tavg, dt, nullptr, 1, 1);
-    rc = mwm_run<K, HASV>(a, st);
-    if (rc) return rc;
+    if (prm->route == BSPS_ROUTE_FUSED) {
+        // A4: bucket boundaries inside every sorted block (splitters searched into it).
+        {
+            StageScope sc(ST_COUNT, st);
+            const u64 ncnt = (u64)(p + 1) * p;
+            hipLaunchKernelGGL((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pp,
+                               P.cntT);
+            LAUNCH_OK();
+        }
+        // A5: prefix sums -> runs of every bucket. A6: merge them (routing fused).
+        {
+            StageScope sc(ST_TABLES, st);
+            hipLaunchKernelGGL(k_bucket_tables, dim3(p), dim3(256), 0, st, n, p, P.cntT, kSampleStride,
+                               std::max<u32>(1, P.spb), (const u32*)nullptr, P.bm.run_start, P.bm.run_len,
+                               P.bm.out_base, P.bm.sdesc);
+            LAUNCH_OK();
+        }
+        {
+            StageScope sc(ST_BUCKET_MERGE, st);
+            MwmArgs<K> a =
+                mwm_args<K>(P.bm, P.B, P.Bv, io, vals, P.bs.A, P.bs.Av, P.bsmp, o.cap, o.tavg, dt, nullptr, 1, 1);
+            rc = mwm_run<K, HASV>(a, st, ST_BUCKET_MERGE_K);
+            if (rc) return rc;
+        }
+    } else {
+        // A4: every key ranked on its own (splitter search or learned model).
+        const int tpbr = (int)cdiv(cdiv((u64)n, (u64)p), RANK_TILE);
+        {
+            StageScope sc(ST_COUNT, st);
+            if (prm->bucketing == BSPS_LEARNED) {
+                const int L = prm->leaves > 0 ? prm->leaves : 4096;
+                rc = fit_model<K>(P.ssk, ns, BSPS_DT_NONE, p, s, L, 2, P.model, P.fitws, st);
+                if (rc) return rc;
+            }
+            hipLaunchKernelGGL(k_zero_u32, dim3((u32)cdiv((u64)p * p + 4, 256)), dim3(256), 0, st, P.C, p * p + 4);
+            LAUNCH_OK();
+            StageScope sk(ST_RANK_K, st);
+            if (prm->bucketing == BSPS_LEARNED)
+                hipLaunchKernelGGL((k_rank<K, true>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, st, P.B, n, p, tpbr,
+                                   P.pk, P.pp, BSPS_DT_NONE, (const void*)P.model, P.bucket, P.C,
+                                   (unsigned long long*)(P.C + (size_t)p * p));
+            else
+                hipLaunchKernelGGL((k_rank<K, false>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, st, P.B, n, p, tpbr,
+                                   P.pk, P.pp, BSPS_DT_NONE, (const void*)nullptr, P.bucket, P.C,
+                                   (unsigned long long*)nullptr);
+            LAUNCH_OK();
+        }
+        // A5: the p independent prefix computations, then routing into Z (= A).
+        {
+            StageScope sc(ST_TABLES, st);
+            hipLaunchKernelGGL(k_counts_to_cntT, dim3(p), dim3(256), 0, st, P.C, p, P.cntT);
+            LAUNCH_OK();
+            hipLaunchKernelGGL(k_route_offsets, dim3(p), dim3(256), 0, st, P.C, P.cntT, p, P.off);
+            LAUNCH_OK();
+            const int tpbs = (int)cdiv(cdiv((u64)n, (u64)p), 4096);
+            hipLaunchKernelGGL((k_scatter<K, HASV>), dim3((u32)(p * tpbs)), dim3(256), 0, st, P.B, P.Bv, P.bucket, n, p,
+                               tpbs, P.cntT, P.off, P.bs.A, P.bs.Av);
+            LAUNCH_OK();
+            hipLaunchKernelGGL(k_bucket_tables, dim3(p), dim3(256), 0, st, n, p, P.cntT, kSampleStride,
+                               std::max<u32>(1, P.spb), (const u32*)P.off, P.bm.run_start, P.bm.run_len,
+                               P.bm.out_base, P.bm.sdesc);
+            LAUNCH_OK();
+        }
+        if (stats && stats->routed) {
+            rc = copy_keys_out<K>(stats->routed, P.bs.A, n, dt, st);
+            if (rc) return rc;
+        }
+        if (stats && stats->buckets) {
+            HIP_OK(hipMemcpyAsync(stats->buckets, P.bucket, 4 * n, hipMemcpyDeviceToHost, st));
+            HIP_OK(hipStreamSynchronize(st));
+        }
+        // A6: per-bucket merge of the routed runs (B is free: oversize scratch).
+        {
+            StageScope sc(ST_BUCKET_MERGE, st);
+            MwmArgs<K> a = mwm_args<K>(P.bm, P.bs.A, P.bs.Av, io, vals, P.B, P.Bv, P.bsmp, o.cap, o.tavg, dt,
+                                       nullptr, 1, 1);
+            rc = mwm_run<K, HASV>(a, st, ST_BUCKET_MERGE_K);
+            if (rc) return rc;
+        }
+    }
     if (stats) {
         HIP_OK(hipStreamSynchronize(st));
         rc = copy_keys_out<K>(stats->splitter_keys, P.pk, p - 1, dt, st);
@@ -449,6 +634,12 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         }
         stats->max_bucket_ratio = mx / ((double)n / p);
         stats->oversize_chunks = (i64)ctr[1] + (i64)ctr2[1];
+        if (prm->route == BSPS_ROUTE_SCATTER && prm->bucketing == BSPS_LEARNED) {
+            unsigned long long ls[2];
+            HIP_OK(hipMemcpy(ls, P.C + (size_t)p * p, 16, hipMemcpyDeviceToHost));
+            stats->mispredict_rate = (double)ls[0] / (double)n;
+            stats->mean_fix_dist = (double)ls[1] / (double)n;
+        }
     }
     return BSPS_OK;
 }
@@ -499,6 +690,113 @@ bsps_status bsps_sort_kv(void* keys, uint32_t* values, int64_t n, int32_t dtype,
     return dispatch_sort<true>(keys, values, n, dtype, prm, ws, ws_bytes, stream, st);
 }
 
+size_t bsps_fit_workspace_bytes(int64_t N, int32_t leaves) {
+    Carver c(nullptr);
+    (void)carve_fit(c, N, leaves > 0 ? leaves : 4096);
+    return c.off + 256;
+}
+
+size_t bsps_rank_workspace_bytes(int64_t n, int32_t p) {
+    (void)n;
+    (void)p;
+    return 256;
+}
+
+bsps_status bsps_rank(const void* keys, int64_t n, int32_t dtype, int32_t p, const void* spl_keys,
+                      const uint32_t* spl_pos, int32_t bucketing, const void* model, uint32_t* out_bucket,
+                      uint32_t* out_counts, void* ws, size_t ws_bytes, void* stream, bsps_stats* st) {
+    if (n < 0 || p < 1 || (i64)p > std::max<i64>(n, 1) || dtype < 0 || dtype > 2) return BSPS_EINVAL;
+    if (bucketing != BSPS_SPLITTER && bucketing != BSPS_LEARNED) return BSPS_EINVAL;
+    if (bucketing == BSPS_LEARNED && !model) return BSPS_EINVAL;
+    if (p > kMaxP || n >= (i64)0xFFFFFFFFll) return BSPS_EUNSUPPORTED;
+    if (n > 0 && (!keys || (p > 1 && (!spl_keys || !spl_pos)))) return BSPS_EINVAL;
+    if (!ws || ws_bytes < bsps_rank_workspace_bytes(n, p)) return BSPS_EWORKSPACE;
+    if (n == 0) return BSPS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* lst = (unsigned long long*)ws;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (u32*)ws, 4);
+    LAUNCH_OK();
+    if (out_counts) {
+        hipLaunchKernelGGL(k_zero_u32, dim3((u32)cdiv((u64)p * p, 256)), dim3(256), 0, s, out_counts, p * p);
+        LAUNCH_OK();
+    }
+    const int tpbr = (int)cdiv(cdiv((u64)n, (u64)p), RANK_TILE);
+    {
+        StageScope sc(ST_RANK_K, s);
+        // keys and splitters arrive in dtype form; the kernel maps both to order keys
+        if (dtype == BSPS_I64) {
+            if (bucketing == BSPS_LEARNED)
+                hipLaunchKernelGGL((k_rank<u64, true>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, s,
+                                   (const u64*)keys, n, p, tpbr, (const u64*)spl_keys, spl_pos, dtype, model,
+                                   out_bucket, out_counts, lst);
+            else
+                hipLaunchKernelGGL((k_rank<u64, false>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, s,
+                                   (const u64*)keys, n, p, tpbr, (const u64*)spl_keys, spl_pos, dtype, model,
+                                   out_bucket, out_counts, lst);
+        } else {
+            if (bucketing == BSPS_LEARNED)
+                hipLaunchKernelGGL((k_rank<u32, true>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, s,
+                                   (const u32*)keys, n, p, tpbr, (const u32*)spl_keys, spl_pos, dtype, model,
+                                   out_bucket, out_counts, lst);
+            else
+                hipLaunchKernelGGL((k_rank<u32, false>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, s,
+                                   (const u32*)keys, n, p, tpbr, (const u32*)spl_keys, spl_pos, dtype, model,
+                                   out_bucket, out_counts, lst);
+        }
+    }
+    LAUNCH_OK();
+    if (st) {
+        unsigned long long h[2];
+        HIP_OK(hipMemcpyAsync(h, lst, 16, hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+        st->mispredict_rate = (double)h[0] / (double)n;
+        st->mean_fix_dist = (double)h[1] / (double)n;
+    }
+    return BSPS_OK;
+}
+
+bsps_status bsps_fit_model(const void* smp_keys, int64_t N, int32_t dtype, int32_t p, int32_t s, int32_t leaves,
+                           int32_t iters, void* model, void* ws, size_t ws_bytes, void* stream) {
+    if (N < 1 || p < 1 || s < 1 || leaves < 1 || leaves > 4096 || iters < 1 || dtype < 0 || dtype > 2 ||
+        !smp_keys || !model)
+        return BSPS_EINVAL;
+    if (!ws || ws_bytes < bsps_fit_workspace_bytes(N, leaves)) return BSPS_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == BSPS_I64) return fit_model<u64>((const u64*)smp_keys, N, dtype, p, s, leaves, iters, model, ws, st);
+    return fit_model<u32>((const u32*)smp_keys, N, dtype, p, s, leaves, iters, model, ws, st);
+}
+
+bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int32_t p, int32_t s, int32_t leaves,
+                            const void* model, int32_t* out_leaf, float* out_grad, float* out_gram, float* out_loss,
+                            void* ws, size_t ws_bytes, void* stream) {
+    if (N < 1 || p < 1 || s < 1 || leaves < 1 || leaves > 4096 || dtype < 0 || dtype > 2 || !smp_keys || !model ||
+        !out_leaf || !out_grad || !out_gram || !out_loss)
+        return BSPS_EINVAL;
+    if (!ws || ws_bytes < bsps_fit_workspace_bytes(N, leaves)) return BSPS_EWORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    Carver c(ws);
+    FitWs f = carve_fit(c, N, leaves);
+    const u32 gN = (u32)std::max<u64>(1, cdiv((u64)N, 256));
+    const u32 gM = (u32)cdiv((u64)leaves + 1, 256);
+    if (dtype == BSPS_I64)
+        hipLaunchKernelGGL((k_model_x<u64>), dim3(gN), dim3(256), 0, st, (const u64*)smp_keys, N, dtype, model, 1,
+                           f.x, out_leaf);
+    else
+        hipLaunchKernelGGL((k_model_x<u32>), dim3(gN), dim3(256), 0, st, (const u32*)smp_keys, N, dtype, model, 1,
+                           f.x, out_leaf);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_model_ranges, dim3(gM), dim3(256), 0, st, out_leaf, N, leaves, f.lo);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, out_leaf, N, p, s, model, 1, f.r);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_model_backward, dim3(gM), dim3(256), 0, st, f.x, f.r, f.lo, leaves, N, model, 1, out_grad,
+                       out_gram, f.lossp);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(64), 0, st, f.lossp, leaves, N, out_loss);
+    LAUNCH_OK();
+    return BSPS_OK;
+}
+
 const char* bsps_status_string(int32_t status) {
     switch (status) {
         case BSPS_OK: return "ok";
@@ -511,6 +809,35 @@ const char* bsps_status_string(int32_t status) {
 }
 
 void bsps_release_cache(void) {}
+
+int bsps_timing(int enable) {
+    g_timer.on = enable != 0;
+    return BSPS_OK;
+}
+
+int bsps_timing_read(double* ms, int64_t* launches, int nstage, int reset) {
+    for (int sg = 0; sg < ST_N; sg++) {
+        double acc = 0;
+        for (auto& pr : g_timer.ev[sg]) {
+            float t = 0;
+            if (hipEventSynchronize(pr.second) != hipSuccess) return BSPS_EDEVICE;
+            if (hipEventElapsedTime(&t, pr.first, pr.second) != hipSuccess) return BSPS_EDEVICE;
+            acc += t;
+        }
+        if (sg < nstage) {
+            if (ms) ms[sg] = acc;
+            if (launches) launches[sg] = (int64_t)g_timer.ev[sg].size();
+        }
+        if (reset) {
+            for (auto& pr : g_timer.ev[sg]) {
+                g_timer.pool.push_back(pr.first);
+                g_timer.pool.push_back(pr.second);
+            }
+            g_timer.ev[sg].clear();
+        }
+    }
+    return BSPS_OK;
+}
 
 #ifdef BSPS_TIMING
 int bsps_debug_phases(unsigned long long* out, int reset) {

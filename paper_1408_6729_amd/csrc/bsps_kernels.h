@@ -765,3 +765,65 @@ __global__ void k_copy_out(const K* src, const u32* srcv, K* dst, u32* dstv, i64
     dst[i] = rawkey<K>(src[i], out_dt);
     if (srcv) dstv[i] = srcv[i];
 }
+
+// ======================================================================= scatter routing
+
+// From the count matrix C (row = block k, column = bucket i) to the
+// boundaries used by the merge tables: cntT[i*p + k] = keys of block k in
+// buckets below i (row p = block size). One workgroup per block.
+__global__ __launch_bounds__(256) void k_counts_to_cntT(const u32* C, int p, u32* cntT) {
+    __shared__ u32 wsum[8];
+    const int k = blockIdx.x, t = threadIdx.x;
+    const int per = (p + 255) / 256;
+    u32 loc = 0;
+    for (int i = t * per; i < (t + 1) * per && i < p; i++) loc += C[(i64)k * p + i];
+    u32 tot;
+    u32 ex = block_excl_scan<256>(loc, tot, wsum);
+    for (int i = t * per; i < (t + 1) * per && i < p; i++) {
+        cntT[(i64)i * p + k] = ex;
+        ex += C[(i64)k * p + i];
+    }
+    if (t == 0) cntT[(i64)p * p + k] = tot;
+}
+
+// Routing offsets (the p independent prefix computations): bucket i starts
+// after all smaller buckets, and within it the keys of block k follow those of
+// blocks 0..k-1: off[k*p + i]. One workgroup per bucket.
+__global__ __launch_bounds__(256) void k_route_offsets(const u32* C, const u32* cntT, int p, u32* off) {
+    __shared__ u32 wsum[8];
+    const int i = blockIdx.x, t = threadIdx.x;
+    const int per = (p + 255) / 256;
+    u32 loc = 0, lb = 0;
+    for (int k = t * per; k < (t + 1) * per && k < p; k++) {
+        loc += C[(i64)k * p + i];
+        lb += cntT[(i64)i * p + k];
+    }
+    u32 tot, base;
+    u32 ex = block_excl_scan<256>(loc, tot, wsum);
+    __syncthreads();
+    (void)block_excl_scan<256>(lb, base, wsum);
+    for (int k = t * per; k < (t + 1) * per && k < p; k++) {
+        off[(i64)k * p + i] = base + ex;
+        ex += C[(i64)k * p + i];
+    }
+}
+
+// Routing (Figure SortD steps 10-11): key g of block k in bucket b moves to
+// off[k][b] + its position within run (k, b); order within runs is kept.
+template <typename K, bool HASV>
+__global__ __launch_bounds__(256) void k_scatter(const K* B, const u32* Bv, const u32* bucket, i64 n, int p, int tpb,
+                                                 const u32* cntT, const u32* off, K* Z, u32* Zv) {
+    constexpr int TILE = 256 * 16;
+    const int k = blockIdx.x / tpb, tt = blockIdx.x % tpb;
+    const i64 st = (i64)(((u64)k * (u64)n) / (u64)p), en = (i64)(((u64)(k + 1) * (u64)n) / (u64)p);
+    const i64 base = st + (i64)tt * TILE;
+#pragma unroll 4
+    for (int j = 0; j < 16; j++) {
+        const i64 g = base + j * 256 + threadIdx.x;
+        if (g >= en) break;
+        const u32 b = bucket[g];
+        const u32 dst = off[(i64)k * p + b] + (u32)(g - st) - cntT[(i64)b * p + k];
+        Z[dst] = B[g];
+        if (HASV) Zv[dst] = Bv[g];
+    }
+}

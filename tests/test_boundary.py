@@ -1,0 +1,88 @@
+"""CPU tests of the C ABI boundary: the library loads, exports every symbol the
+header declares, and rejects bad arguments before any HIP call (so these run
+without a GPU)."""
+import ctypes as ct
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bsps.h")
+
+
+@pytest.fixture(scope="module")
+def bsps():
+    import paper_1408_6729_amd as m
+    return m
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bsps_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(bsps):
+    names = _declared()
+    assert "bsps_sort" in names and "bsps_sort_kv" in names and "bsps_sort_segmented" in names
+    missing = [n for n in names if not hasattr(bsps.lib, n)]
+    assert not missing, f"declared in bsps.h but not exported: {missing}"
+
+
+def test_status_strings(bsps):
+    assert bsps.status_string(0) == "ok"
+    assert "workspace" in bsps.status_string(2)
+    assert bsps.status_string(99) == "unknown status"
+
+
+def _call(bsps, n, dtype, prm, ws=None, ws_bytes=0, keys=1):
+    return bsps.lib.bsps_sort(ct.c_void_p(keys) if keys else None, n, dtype, ct.byref(prm), ws, ws_bytes, None,
+                              None)
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=-1, p=1, s=1), dict(n=10, p=0, s=1), dict(n=10, p=11, s=1), dict(n=10, p=2, s=0),
+    dict(n=10, p=2, s=6, variant=1), dict(n=10, p=2, s=1, variant=7), dict(n=10, p=2, s=1, route=5),
+    dict(n=10, p=2, s=1, bucketing=3), dict(n=10, p=2, s=1, leaves=-1), dict(n=10, p=2, s=1, dtype=9),
+])
+def test_invalid_arguments_rejected_on_host(bsps, case):
+    case = dict(case)
+    dtype = case.pop("dtype", 0)
+    n = case.pop("n")
+    prm = bsps.make_params(case.pop("p"), case.pop("s"), **case)
+    assert bsps.workspace_bytes(n, dtype, False, prm) == 0
+    assert _call(bsps, n, dtype, prm) == bsps.EINVAL
+
+
+def test_reserved_fields_must_be_zero(bsps):
+    prm = bsps.make_params(2, 2)
+    prm.reserved[3] = 1
+    assert _call(bsps, 100, 0, prm) == bsps.EINVAL
+
+
+def test_limits(bsps):
+    assert _call(bsps, 5000, 0, bsps.make_params(1025, 1)) == bsps.EUNSUPPORTED
+    assert _call(bsps, 1 << 32, 0, bsps.make_params(4, 1)) == bsps.EUNSUPPORTED
+    # a block of more than 1024 tiles of 16K keys
+    assert _call(bsps, (1 << 24) * 2 + 10, 0, bsps.make_params(1, 1)) == bsps.EUNSUPPORTED
+
+
+def test_workspace_checked_before_device(bsps):
+    prm = bsps.make_params(16, 8)
+    need = bsps.workspace_bytes(1 << 20, 0, False, prm)
+    assert need > 2 * 4 * (1 << 20)
+    assert _call(bsps, 1 << 20, 0, prm, ws=None, ws_bytes=0) == bsps.EWORKSPACE
+    assert _call(bsps, 1 << 20, 0, prm, ws=ct.c_void_p(4096), ws_bytes=need - 1) == bsps.EWORKSPACE
+    kv = bsps.workspace_bytes(1 << 20, 0, True, prm)
+    assert kv > need
+    assert bsps.workspace_bytes(1 << 20, 1, False, prm) > need  # int64 keys
+
+
+def test_trivial_sizes_are_noops(bsps):
+    assert _call(bsps, 0, 0, bsps.make_params(1, 1), keys=0) == bsps.OK
+    assert _call(bsps, 1, 2, bsps.make_params(1, 3)) == bsps.OK
+
+
+def test_null_keys_rejected(bsps):
+    assert _call(bsps, 100, 0, bsps.make_params(2, 2), keys=0) == bsps.EINVAL

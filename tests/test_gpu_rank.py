@@ -1,0 +1,144 @@
+"""GPU parity of per-key bucket ranking (splitter search and learned model),
+the scatter routing, and the learned model's gradient against the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1408_6729_amd  # noqa: F401
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _bits(a):
+    return a.view(np.uint32) if a.dtype == np.float32 else a
+
+
+@pytest.mark.parametrize("bucketing", [0, 1])
+@pytest.mark.parametrize("dtype,variant", [("int32", 0), ("float32", 1), ("int64", 0)])
+def test_scatter_route_parity(ora, dev, bucketing, dtype, variant):
+    """Route by per-key ranking: buckets, count matrix, routed array and the
+    sorted output all equal the oracle's (Figure SortD steps 9-12)."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    n, p, s = 300001, 64, 24
+    keys = W.lognormal_f32(n, zeros=64) if dtype == "float32" else W.random_keys(n, dtype, seed=3, distinct=5000)
+    vals = np.arange(n, dtype=np.uint32)
+    ref = ora.sort(keys, p, s, variant, 5, vals)
+    t = _t(keys, dev)
+    v = _t(vals.view(np.int32), dev)
+    st = bsps.sort_(t, p, s, variant, seed=5, values=v, bucketing=bucketing, route=bsps.ROUTE_SCATTER,
+                    leaves=256, stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(_bits(t.cpu().numpy()), _bits(ref["keys"]))
+    assert np.array_equal(v.cpu().numpy().view(np.uint32), ref["values"])
+    assert np.array_equal(st["count_matrix"], ref["C"])
+    assert np.array_equal(_bits(st["routed"]), _bits(ref["Z_keys"]))
+    truth = ora.rank(ref["B_keys"], ref["spl_key"], ref["spl_pos"])
+    assert np.array_equal(st["buckets"].astype(np.int64), truth)
+    if bucketing == 1:
+        assert 0.0 <= st["mispredict_rate"] < 0.5
+
+
+@pytest.mark.parametrize("p", [2, 100, 1024])
+@pytest.mark.parametrize("bucketing", [0, 1])
+def test_rank_entry_point(ora, dev, p, bucketing):
+    """bsps_rank on the oracle's block-sorted array and splitters."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    n, s = 1 << 19, 32
+    keys = W.lognormal_f32(n, zeros=16)
+    ref = ora.sort(keys, p, s, ora.RAN, 11)
+    B = _t(ref["B_keys"], dev)
+    sk = _t(ref["B_keys"][ref["spl_pos"]], dev)
+    sp = _t(ref["spl_pos"].astype(np.int32), dev)
+    buckets = torch.empty(n, dtype=torch.int32, device=dev)
+    counts = torch.empty(p * p, dtype=torch.int32, device=dev)
+    model = None
+    if bucketing == 1:
+        sorted_sample = _t(ref["B_keys"][ref["sample_pos"]], dev)
+        model = bsps.fit_model(sorted_sample, p, s, leaves=1024)
+    st = bsps.rank(B, p, sk, sp, bucketing, model, buckets, counts, stats=True)
+    torch.cuda.synchronize()
+    truth = ora.rank(ref["B_keys"], ref["spl_key"], ref["spl_pos"])
+    assert np.array_equal(buckets.cpu().numpy().astype(np.int64), truth)
+    assert np.array_equal(counts.cpu().numpy().reshape(p, p), ref["C"])
+    if bucketing == 1:
+        assert st["mispredict_rate"] < 0.3, st
+
+
+def test_model_gradient_matches_fp64(ora, dev):
+    """Backward kernel: FP32 gradient and Gram sums equal the FP64 oracle's at
+    the same parameters and leaf assignment."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    n, p, s, L = 1 << 20, 256, 64, 512
+    keys = W.lognormal_f32(n, zeros=32)
+    ref = ora.sort(keys, p, s, ora.DET)
+    smp = ref["B_keys"][ref["sample_pos"]]
+    smp_t = _t(smp, dev)
+    model = bsps.fit_model(smp_t, p, s, leaves=L, iters=2)
+    # perturb the fitted leaves so the gradient is far from zero
+    hdr, leaf = bsps.model_fields(model)
+    rng = np.random.default_rng(1)
+    leaf = leaf.copy()
+    leaf[:, 0] *= 1 + 0.1 * rng.standard_normal(L).astype(np.float32)
+    leaf[:, 1] += 0.01 * rng.standard_normal(L).astype(np.float32)
+    raw = model.cpu().numpy().copy()
+    raw[48:48 + 12 * L] = np.frombuffer(leaf.astype(np.float32).tobytes(), dtype=np.uint8)
+    model = torch.from_numpy(raw).to(dev)
+    lid, grad, gram, loss = bsps.model_grad(smp_t, p, s, L, model)
+    torch.cuda.synchronize()
+    lid = lid.cpu().numpy()
+    u = ora.order_keys(smp).astype(np.float64)
+    x = ((u - hdr["lo"]) * np.float64(hdr["inv"])).astype(np.float32).astype(np.float64)
+    y = (np.arange(smp.size) + 0.5) / (p * s)
+    assert (np.diff(lid) >= 0).all()
+    l64, g64, h64 = ora.rmi_grad(x, y, lid, leaf[:, 0].astype(np.float64), leaf[:, 1].astype(np.float64),
+                                 leaf[:, 2].astype(np.float64))
+    g = grad.cpu().numpy().astype(np.float64)
+    h = gram.cpu().numpy().astype(np.float64)
+    scale = np.abs(g64).max()
+    assert np.abs(g - g64).max() <= 1e-4 * scale, (np.abs(g - g64).max(), scale)
+    assert np.allclose(h, h64, rtol=1e-4, atol=1e-6 * np.abs(h64).max())
+    assert abs(loss.item() - l64) <= 1e-4 * l64
+
+
+def test_model_training_reduces_loss_and_predicts_buckets(ora, dev):
+    """Forward/backward/update: after training, the loss is far below the
+    untrained one and most keys are predicted in their exact bucket."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    n, p, s, L = 1 << 20, 1024, 16, 4096
+    keys = W.lognormal_f32(n, zeros=64)
+    ref = ora.sort(keys, p, s, ora.DET)
+    smp_t = _t(ref["B_keys"][ref["sample_pos"]], dev)
+    m0 = bsps.fit_model(smp_t, p, s, leaves=L, iters=1)
+    m2 = bsps.fit_model(smp_t, p, s, leaves=L, iters=2)
+    zero = m2.clone()
+    zero[48:] = 0
+    _, _, _, loss0 = bsps.model_grad(smp_t, p, s, L, zero)
+    _, g1, _, loss1 = bsps.model_grad(smp_t, p, s, L, m0)
+    _, g2, _, loss2 = bsps.model_grad(smp_t, p, s, L, m2)
+    torch.cuda.synchronize()
+    assert loss1.item() < 1e-3 * loss0.item()
+    assert loss2.item() <= loss1.item() * 1.01
+    B = _t(ref["B_keys"], dev)
+    sk = _t(ref["B_keys"][ref["spl_pos"]], dev)
+    sp = _t(ref["spl_pos"].astype(np.int32), dev)
+    buckets = torch.empty(n, dtype=torch.int32, device=dev)
+    st = bsps.rank(B, p, sk, sp, 1, m2, buckets, None, stats=True)
+    truth = ora.rank(ref["B_keys"], ref["spl_key"], ref["spl_pos"])
+    assert np.array_equal(buckets.cpu().numpy().astype(np.int64), truth)
+    assert st["mispredict_rate"] < 0.25 and st["mean_fix_dist"] < 0.5, st
