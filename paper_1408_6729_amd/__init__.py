@@ -72,6 +72,14 @@ def _load():
     L.bsps_fit_model.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, sz, vp]
     L.bsps_model_grad.restype = i32
     L.bsps_model_grad.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.bsps_sort_segmented.restype = i32
+    L.bsps_sort_segmented.argtypes = [vp, vp, vp, i32, i32, ct.c_char_p, vp, sz, vp, SP]
+    L.bsps_segmented_workspace_bytes.restype = sz
+    L.bsps_segmented_workspace_bytes.argtypes = [vp, i32, i32, i32, ct.c_char_p]
+    L.bsps_tuning_format.restype = ct.c_char_p
+    L.bsps_tuning_format.argtypes = []
+    L.bsps_release_cache.restype = None
+    L.bsps_release_cache.argtypes = []
     L.bsps_timing.argtypes = [ct.c_int]
     L.bsps_timing_read.argtypes = [vp, vp, ct.c_int, ct.c_int]
     return L
@@ -251,3 +259,42 @@ def model_fields(model):
     L, p, s, _ = np.frombuffer(raw[32:48].tobytes(), dtype=np.int32)
     leaf = np.frombuffer(raw[48:48 + 12 * int(L)].tobytes(), dtype=np.float32).reshape(int(L), 3)
     return {"lo": lo, "hi": hi, "a": a, "b": b, "mur": mur, "inv": inv, "L": int(L), "p": int(p), "s": int(s)}, leaf
+
+
+def segmented_workspace_bytes(offsets, dtype: int, with_values: bool, tuning: str | None = None) -> int:
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    return int(_lib.bsps_segmented_workspace_bytes(off.ctypes.data, len(off) - 1, dtype, int(with_values),
+                                                   tuning.encode() if tuning else None))
+
+
+def sort_segmented_(keys, offsets, values=None, tuning: str | None = None, stats: bool = False, workspace=None):
+    """Sorts every segment [offsets[i], offsets[i+1]) of `keys` (and `values`)
+    in place, all segments in one captured graph launch. `offsets`: host array
+    of nseg + 1 non-decreasing int64 starting at 0."""
+    import torch
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    nseg = len(off) - 1
+    dt = _dtype_code(keys)
+    tj = tuning.encode() if tuning else None
+    need = _lib.bsps_segmented_workspace_bytes(off.ctypes.data, nseg, dt, int(values is not None), tj)
+    if need == 0 and nseg > 0 and off[-1] > 0:
+        code = _lib.bsps_sort_segmented(None, None, off.ctypes.data, nseg, dt, tj, None, 0, None, None)
+        raise BspsError(code if code else EINVAL, "bsps_segmented_workspace_bytes")
+    ws = workspace if workspace is not None else torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+    st = Stats() if stats else None
+    code = _lib.bsps_sort_segmented(_ptr(keys), _ptr(values), off.ctypes.data, nseg, dt, tj, _ptr(ws), ws.numel(),
+                                    ct.c_void_p(_stream(keys)), ct.byref(st) if st is not None else None)
+    if code != OK:
+        raise BspsError(code, "bsps_sort_segmented")
+    if stats:
+        return {"oversize_chunks": st.oversize_chunks, "blocks": st.reserved_i[0], "merged_segments": st.reserved_i[1],
+                "graph": bool(st.reserved_i[2])}
+    return None
+
+
+def tuning_format() -> str:
+    return _lib.bsps_tuning_format().decode()
+
+
+def release_cache() -> None:
+    _lib.bsps_release_cache()

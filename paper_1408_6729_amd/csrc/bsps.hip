@@ -20,6 +20,10 @@
 #include "../../include/bsps.h"
 #include "bsps_kernels.h"
 #include "bsps_learned.h"
+#include "bsps_segmented.h"
+
+#include <map>
+#include <string>
 
 namespace {
 
@@ -662,6 +666,367 @@ bsps_status dispatch_sort(void* keys, u32* vals, i64 n, int dt, const bsps_param
     return run_sort<u32, HASV>(keys, vals, n, dt, prm, ws, ws_bytes, s, st);
 }
 
+// ------------------------------------------------------------------ segmented sort (batch)
+
+// Tuning: per size class (segments with n <= 2^max_log2, classes ascending),
+// the block size (keys per virtual processor, at most one tile) and the
+// oversampling s. p = ceil(n / block); s is clipped so that the segment's
+// sample (p*s records) fits one tile.
+struct TuneClass {
+    int max_log2, block, s;
+};
+struct Tuning {
+    std::vector<TuneClass> cls;
+};
+
+const char* kTuningFormat =
+    "{\"classes\": [{\"max_log2\": L, \"block\": B, \"s\": S}, ...]} with classes in ascending L; a segment of n "
+    "keys uses the first class with n <= 2^L (the last class beyond). B: keys per virtual processor, "
+    "1 <= B <= tile (16384 for 4-byte keys, 8192 for int64); S >= 1 sample records per bucket.";
+
+// Built-in table (written by paper_1408_6729_amd/autotune.py on MI355X).
+Tuning default_tuning() {
+    Tuning t;
+    t.cls = {{14, 16384, 1}, {17, 16384, 32}, {20, 16384, 16}, {40, 16384, 8}};
+    return t;
+}
+
+// Minimal reader for the documented format (integers only).
+bool parse_tuning(const char* js, Tuning& t) {
+    t.cls.clear();
+    if (!js) {
+        t = default_tuning();
+        return true;
+    }
+    const std::string s(js);
+    size_t pos = s.find("\"classes\"");
+    if (pos == std::string::npos) return false;
+    pos = s.find('[', pos);
+    if (pos == std::string::npos) return false;
+    const size_t end = s.find(']', pos);
+    if (end == std::string::npos) return false;
+    while (true) {
+        const size_t ob = s.find('{', pos);
+        if (ob == std::string::npos || ob > end) break;
+        const size_t cb = s.find('}', ob);
+        if (cb == std::string::npos || cb > end) return false;
+        const std::string obj = s.substr(ob, cb - ob);
+        auto field = [&](const char* name, int& out) {
+            const size_t f = obj.find(std::string("\"") + name + "\"");
+            if (f == std::string::npos) return false;
+            const size_t colon = obj.find(':', f);
+            if (colon == std::string::npos) return false;
+            char* ep = nullptr;
+            const long v = strtol(obj.c_str() + colon + 1, &ep, 10);
+            if (ep == obj.c_str() + colon + 1) return false;
+            out = (int)v;
+            return true;
+        };
+        TuneClass c;
+        if (!field("max_log2", c.max_log2) || !field("block", c.block) || !field("s", c.s)) return false;
+        if (c.block < 1 || c.s < 1 || c.max_log2 < 0 || c.max_log2 > 40) return false;
+        if (!t.cls.empty() && c.max_log2 <= t.cls.back().max_log2) return false;
+        t.cls.push_back(c);
+        pos = cb + 1;
+    }
+    return !t.cls.empty();
+}
+
+struct SegPlan {
+    int nseg = 0, NB = 0, nmerged = 0, nblocks_s = 0;
+    i64 n = 0;
+    std::vector<u32> seg, soff, poff, coff, btab, dtab, btab_s;
+    std::vector<std::vector<u32>> gtab;  // per merge class
+    std::vector<int> cls_R;
+    std::vector<i64> cls_n;
+    u32 nbsmp = 0;
+};
+
+template <typename K>
+bsps_status make_seg_plan(const int64_t* off, int nseg, const Tuning& tu, SegPlan& P) {
+    const u32 T = tileT<K>();
+    P = SegPlan();
+    P.nseg = nseg;
+    P.n = nseg ? off[nseg] : 0;
+    P.seg.assign((size_t)SEGW * std::max(nseg, 1), 0);
+    P.soff.assign(nseg + 1, 0);
+    P.poff.assign(nseg + 1, 0);
+    P.coff.assign(nseg + 1, 0);
+    P.dtab.assign(std::max(nseg, 1), 0);
+    std::vector<int> rclass;
+    for (int i = 0; i < nseg; i++) {
+        const i64 n = off[i + 1] - off[i];
+        const TuneClass* c = &tu.cls.back();
+        for (auto& cc : tu.cls)
+            if (n <= ((i64)1 << cc.max_log2)) { c = &cc; break; }
+        const i64 block = std::min<i64>(c->block, T);
+        i64 p = std::max<i64>(1, (n + block - 1) / block);
+        if (p > MAXR) return BSPS_EUNSUPPORTED;
+        if (n <= 1) p = 1;
+        i64 s = std::max<i64>(1, std::min<i64>(c->s, T / p));
+        u32* d = &P.seg[(size_t)SEGW * i];
+        d[0] = (u32)off[i];
+        d[1] = (u32)n;
+        d[2] = (u32)p;
+        d[3] = (u32)s;
+        d[4] = (u32)P.NB;
+        for (i64 k = 0; k < p; k++) {
+            const i64 a = (i64)(((u64)k * (u64)n) / (u64)p), b = (i64)(((u64)(k + 1) * (u64)n) / (u64)p);
+            P.btab.push_back((u32)(off[i] + a));
+            P.btab.push_back((u32)(b - a));
+            P.btab.push_back((u32)i);
+            P.btab.push_back(P.nbsmp);
+            P.nbsmp += (u32)((b - a) / kSampleStride);
+            P.NB++;
+        }
+        const bool merged = p >= 2;
+        P.dtab[i] = merged ? 0u : 1u;
+        P.soff[i + 1] = P.soff[i] + (merged ? (u32)(p * s) : 0u);
+        P.poff[i + 1] = P.poff[i] + (merged ? (u32)(p - 1) : 0u);
+        P.coff[i + 1] = P.coff[i] + (merged ? (u32)((p + 1) * p) : 0u);
+        if (merged) {
+            P.nmerged++;
+            P.btab_s.push_back(P.soff[i]);
+            P.btab_s.push_back((u32)(p * s));
+            P.btab_s.push_back((u32)i);
+            P.btab_s.push_back(0);
+            int R = 2;
+            while (R < p) R <<= 1;
+            int ci = -1;
+            for (size_t q = 0; q < P.cls_R.size(); q++)
+                if (P.cls_R[q] == R) ci = (int)q;
+            if (ci < 0) {
+                ci = (int)P.cls_R.size();
+                P.cls_R.push_back(R);
+                P.cls_n.push_back(0);
+                P.gtab.emplace_back();
+            }
+            P.cls_n[ci] += n;
+            for (i64 b = 0; b < p; b++) {
+                P.gtab[ci].push_back((u32)i);
+                P.gtab[ci].push_back((u32)b);
+            }
+        }
+    }
+    if (P.btab.empty()) P.btab.assign(4, 0);
+    if (P.btab_s.empty()) P.btab_s.assign(4, 0);
+    return BSPS_OK;
+}
+
+template <typename K>
+struct SegBufs {
+    u32 *seg, *soff, *poff, *coff, *btab, *dtab, *btab_s;
+    std::vector<u32*> gtab;
+    K *B, *A, *bsmp, *skey, *ssk, *pk;
+    u32 *Bv, *Av, *spos, *ssp, *pp, *cntT;
+    std::vector<MwmBufs<K>> mw;
+    char* tables;
+    size_t tables_bytes;
+};
+
+template <typename K>
+size_t carve_seg(Carver& c, const SegPlan& P, bool hasv, SegBufs<K>& b, u32 tavg) {
+    const size_t t0 = (c.off + 255) & ~(size_t)255;
+    b.seg = c.take<u32>(P.seg.size());
+    b.soff = c.take<u32>(P.soff.size());
+    b.poff = c.take<u32>(P.poff.size());
+    b.coff = c.take<u32>(P.coff.size());
+    b.btab = c.take<u32>(P.btab.size());
+    b.dtab = c.take<u32>(P.dtab.size());
+    b.btab_s = c.take<u32>(P.btab_s.size());
+    b.gtab.clear();
+    for (auto& g : P.gtab) b.gtab.push_back(c.take<u32>(g.size()));
+    b.tables = c.base ? c.base + t0 : nullptr;
+    b.tables_bytes = c.off - t0;
+    const i64 n1 = std::max<i64>(1, P.n);
+    b.B = c.take<K>(n1);
+    b.Bv = hasv ? c.take<u32>(n1) : nullptr;
+    b.A = c.take<K>(n1);
+    b.Av = hasv ? c.take<u32>(n1) : nullptr;
+    b.bsmp = c.take<K>(std::max<u32>(1, P.nbsmp));
+    const u32 ns = std::max<u32>(1, P.soff.back());
+    b.skey = c.take<K>(ns);
+    b.spos = c.take<u32>(ns);
+    b.ssk = c.take<K>(ns);
+    b.ssp = c.take<u32>(ns);
+    b.pk = c.take<K>(std::max<u32>(1, P.poff.back()));
+    b.pp = c.take<u32>(std::max<u32>(1, P.poff.back()));
+    b.cntT = c.take<u32>(std::max<u32>(1, P.coff.back()));
+    b.mw.assign(P.cls_R.size(), MwmBufs<K>());
+    for (size_t q = 0; q < P.cls_R.size(); q++)
+        carve_mwm<K>(c, b.mw[q], (int)(P.gtab[q].size() / 2), P.cls_R[q], (u64)P.cls_n[q], tavg);
+    return c.off + 256;
+}
+
+template <typename K, bool HASV>
+bsps_status enqueue_segmented(const SegPlan& P, const SegBufs<K>& b, K* io, u32* vals, int dt, const Opts& o,
+                              hipStream_t st) {
+    constexpr int NT = Shape<K>::NT;
+    if (P.NB == 0) return BSPS_OK;
+    TileArgs<K> ta;
+    std::memset(&ta, 0, sizeof(ta));
+    ta.in = io; ta.inv = vals; ta.n = P.n; ta.p = 1; ta.tpb = 1; ta.in_dt = dt;
+    ta.out = b.B; ta.outv = b.Bv; ta.out_dt = BSPS_DT_NONE; ta.smp = b.bsmp; ta.ys = kSampleStride; ta.spt = 0;
+    ta.btab = b.btab; ta.dtab = b.dtab; ta.outd = io; ta.outdv = vals;
+    {
+        StageScope sc(ST_TILE, st);
+        hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3(P.NB), dim3(NT), 0, st, ta);
+        LAUNCH_OK();
+    }
+    if (P.nmerged == 0) return BSPS_OK;
+    const u32 ns = P.soff.back(), np = P.poff.back(), nc = P.coff.back();
+    {
+        StageScope sc(ST_SAMPLE, st);
+        hipLaunchKernelGGL((k_seg_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, b.B, b.seg, b.soff,
+                           P.nseg, b.skey, b.spos);
+        LAUNCH_OK();
+        TileArgs<K> tb;
+        std::memset(&tb, 0, sizeof(tb));
+        tb.in = b.skey; tb.inv = b.spos; tb.n = ns; tb.p = 1; tb.tpb = 1; tb.in_dt = BSPS_DT_NONE;
+        tb.out = b.ssk; tb.outv = b.ssp; tb.out_dt = BSPS_DT_NONE; tb.smp = nullptr; tb.ys = 1;
+        tb.btab = b.btab_s;
+        hipLaunchKernelGGL((k_tile_sort<K, true>), dim3(P.nmerged), dim3(NT), 0, st, tb);
+        LAUNCH_OK();
+        if (np) {
+            hipLaunchKernelGGL((k_seg_splitters<K>), dim3((u32)cdiv(np, 256)), dim3(256), 0, st, b.ssk, b.ssp, b.seg,
+                               b.soff, b.poff, P.nseg, b.pk, b.pp);
+            LAUNCH_OK();
+        }
+    }
+    {
+        StageScope sc(ST_COUNT, st);
+        hipLaunchKernelGGL((k_seg_count<K>), dim3((u32)cdiv(nc, 256)), dim3(256), 0, st, b.B, b.seg, b.poff, b.coff,
+                           P.nseg, b.pk, b.pp, b.cntT);
+        LAUNCH_OK();
+    }
+    for (size_t q = 0; q < P.cls_R.size(); q++) {
+        const int G = (int)(P.gtab[q].size() / 2);
+        {
+            StageScope sc(ST_TABLES, st);
+            hipLaunchKernelGGL(k_seg_bucket_tables, dim3(G), dim3(256), 0, st, b.gtab[q], P.cls_R[q], b.seg, b.coff,
+                               b.cntT, b.btab, kSampleStride, b.mw[q].run_start, b.mw[q].run_len, b.mw[q].out_base,
+                               b.mw[q].sdesc);
+            LAUNCH_OK();
+        }
+        StageScope sc(ST_BUCKET_MERGE, st);
+        MwmArgs<K> a = mwm_args<K>(b.mw[q], b.B, b.Bv, io, vals, b.A, b.Av, b.bsmp, o.cap, o.tavg, dt, nullptr, 1, 1);
+        const bsps_status rc = mwm_run<K, HASV>(a, st, ST_BUCKET_MERGE_K);
+        if (rc) return rc;
+    }
+    return BSPS_OK;
+}
+
+// Cached graph executables, keyed by everything the captured launches depend on.
+struct GraphCache {
+    std::map<std::string, hipGraphExec_t> execs;
+    hipStream_t cap = nullptr;
+};
+GraphCache g_graphs;
+
+std::string graph_key(const void* a, const void* b, const void* c, const int64_t* off, int nseg, int dt, bool hasv,
+                      const Tuning& tu) {
+    u64 h = 1469598103934665603ull;
+    auto mix = [&](u64 v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix((u64)(uintptr_t)a); mix((u64)(uintptr_t)b); mix((u64)(uintptr_t)c); mix((u64)nseg); mix((u64)dt);
+    mix((u64)hasv);
+    for (int i = 0; i <= nseg; i++) mix((u64)off[i]);
+    for (auto& cc : tu.cls) { mix((u64)cc.max_log2); mix((u64)cc.block); mix((u64)cc.s); }
+    char buf[64];
+    snprintf(buf, sizeof(buf), "%016llx-%d", (unsigned long long)h, nseg);
+    return std::string(buf);
+}
+
+template <typename K, bool HASV>
+bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, int dt, const Tuning& tu, void* ws,
+                          size_t ws_bytes, hipStream_t st, bsps_stats* stats) {
+    SegPlan P;
+    bsps_status rc = make_seg_plan<K>(off, nseg, tu, P);
+    if (rc) return rc;
+    bsps_params dp;
+    std::memset(&dp, 0, sizeof(dp));
+    const Opts o = opts_for<K>(&dp);
+    SegBufs<K> b;
+    Carver c(ws);
+    const size_t need = carve_seg<K>(c, P, HASV, b, o.tavg);
+    if (!ws || ws_bytes < need) return BSPS_EWORKSPACE;
+    if (P.NB == 0) return BSPS_OK;
+    // tables -> workspace (host staging in carve order)
+    {
+        std::vector<char> stage(b.tables_bytes, 0);
+        Carver hc(stage.data());
+        auto put = [&](const std::vector<u32>& v) {
+            u32* d = hc.take<u32>(v.size());
+            std::memcpy(d, v.data(), v.size() * sizeof(u32));
+        };
+        put(P.seg); put(P.soff); put(P.poff); put(P.coff); put(P.btab); put(P.dtab); put(P.btab_s);
+        for (auto& g : P.gtab) put(g);
+        HIP_OK(hipMemcpyAsync(b.tables, stage.data(), stage.size(), hipMemcpyHostToDevice, st));
+    }
+    // capture every launch into one graph (on a private stream), launch it once
+    const bool timed = g_timer.on;
+    bool launched = false;
+    if (!timed && getenv("BSPS_NO_GRAPH") == nullptr) {
+        const std::string key = graph_key(keys, vals, ws, off, nseg, dt, HASV, tu);
+        auto it = g_graphs.execs.find(key);
+        hipGraphExec_t exec = nullptr;
+        if (it != g_graphs.execs.end()) {
+            exec = it->second;
+        } else {
+            if (!g_graphs.cap && hipStreamCreateWithFlags(&g_graphs.cap, hipStreamNonBlocking) != hipSuccess)
+                g_graphs.cap = nullptr;
+            hipGraph_t graph = nullptr;
+            if (g_graphs.cap && hipStreamBeginCapture(g_graphs.cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                const bsps_status erc = enqueue_segmented<K, HASV>(P, b, (K*)keys, vals, dt, o, g_graphs.cap);
+                const hipError_t ec = hipStreamEndCapture(g_graphs.cap, &graph);
+                if (erc == BSPS_OK && ec == hipSuccess && graph &&
+                    hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+                    g_graphs.execs[key] = exec;
+                } else {
+                    exec = nullptr;
+                }
+                if (graph) (void)hipGraphDestroy(graph);
+                (void)hipGetLastError();
+            }
+        }
+        if (exec) {
+            HIP_OK(hipGraphLaunch(exec, st));
+            launched = true;
+        }
+    }
+    if (!launched) {
+        rc = enqueue_segmented<K, HASV>(P, b, (K*)keys, vals, dt, o, st);
+        if (rc) return rc;
+    }
+    if (stats) {
+        HIP_OK(hipStreamSynchronize(st));
+        i64 over = 0;
+        for (auto& m : b.mw) {
+            u32 ctr[2];
+            HIP_OK(hipMemcpy(ctr, m.counters, 8, hipMemcpyDeviceToHost));
+            over += ctr[1];
+        }
+        stats->oversize_chunks = over;
+        stats->reserved_i[0] = P.NB;
+        stats->reserved_i[1] = P.nmerged;
+        stats->reserved_i[2] = launched ? 1 : 0;
+    }
+    return BSPS_OK;
+}
+
+bsps_status validate_segments(const int64_t* off, int nseg, int dtype, const char* tuning_json, Tuning& tu) {
+    if (nseg < 0 || dtype < 0 || dtype > 2 || (nseg > 0 && !off)) return BSPS_EINVAL;
+    if (!parse_tuning(tuning_json, tu)) return BSPS_EINVAL;
+    if (nseg == 0) return BSPS_OK;
+    if (off[0] != 0) return BSPS_EINVAL;
+    for (int i = 0; i < nseg; i++)
+        if (off[i + 1] < off[i]) return BSPS_EINVAL;
+    if (off[nseg] >= (int64_t)0xFFFFFFFFll) return BSPS_EUNSUPPORTED;
+    return BSPS_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -797,6 +1162,41 @@ bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int3
     return BSPS_OK;
 }
 
+size_t bsps_segmented_workspace_bytes(const int64_t* h_offsets, int32_t nseg, int32_t dtype, int32_t with_values,
+                                      const char* tuning_json) {
+    Tuning tu;
+    if (validate_segments(h_offsets, nseg, dtype, tuning_json, tu) != BSPS_OK) return 0;
+    SegPlan P;
+    bsps_params dp;
+    std::memset(&dp, 0, sizeof(dp));
+    Carver c(nullptr);
+    if (dtype == BSPS_I64) {
+        if (make_seg_plan<u64>(h_offsets, nseg, tu, P) != BSPS_OK) return 0;
+        SegBufs<u64> b;
+        return carve_seg<u64>(c, P, with_values != 0, b, opts_for<u64>(&dp).tavg);
+    }
+    if (make_seg_plan<u32>(h_offsets, nseg, tu, P) != BSPS_OK) return 0;
+    SegBufs<u32> b;
+    return carve_seg<u32>(c, P, with_values != 0, b, opts_for<u32>(&dp).tavg);
+}
+
+bsps_status bsps_sort_segmented(void* keys, uint32_t* values, const int64_t* h_offsets, int32_t nseg, int32_t dtype,
+                                const char* tuning_json, void* ws, size_t ws_bytes, void* stream, bsps_stats* st) {
+    Tuning tu;
+    bsps_status rc = validate_segments(h_offsets, nseg, dtype, tuning_json, tu);
+    if (rc) return rc;
+    if (nseg == 0 || h_offsets[nseg] == 0) return BSPS_OK;
+    if (!keys) return BSPS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == BSPS_I64)
+        return values ? run_segmented<u64, true>(keys, values, h_offsets, nseg, dtype, tu, ws, ws_bytes, s, st)
+                      : run_segmented<u64, false>(keys, values, h_offsets, nseg, dtype, tu, ws, ws_bytes, s, st);
+    return values ? run_segmented<u32, true>(keys, values, h_offsets, nseg, dtype, tu, ws, ws_bytes, s, st)
+                  : run_segmented<u32, false>(keys, values, h_offsets, nseg, dtype, tu, ws, ws_bytes, s, st);
+}
+
+const char* bsps_tuning_format(void) { return kTuningFormat; }
+
 const char* bsps_status_string(int32_t status) {
     switch (status) {
         case BSPS_OK: return "ok";
@@ -808,7 +1208,12 @@ const char* bsps_status_string(int32_t status) {
     }
 }
 
-void bsps_release_cache(void) {}
+void bsps_release_cache(void) {
+    for (auto& kv : g_graphs.execs) (void)hipGraphExecDestroy(kv.second);
+    g_graphs.execs.clear();
+    if (g_graphs.cap) (void)hipStreamDestroy(g_graphs.cap);
+    g_graphs.cap = nullptr;
+}
 
 int bsps_timing(int enable) {
     g_timer.on = enable != 0;

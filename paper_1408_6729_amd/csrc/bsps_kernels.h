@@ -89,6 +89,14 @@ struct TileArgs {
     int in_dt, out_dt;
     K* smp;      // sample every ys-th key of each tile, tile slot stride spt
     u32 ys, spt;
+    // Optional explicit tiles (segmented sorts): tile b covers
+    // [btab[4b], btab[4b] + btab[4b+1]) of segment btab[4b+2]; its samples go to
+    // smp[btab[4b+3] ...]. With dtab != NULL, a tile whose segment has
+    // dtab[seg] != 0 is a whole segment: it is written as raw keys to outd.
+    const u32* btab;
+    const u32* dtab;
+    K* outd;
+    u32* outdv;
 };
 
 // Processor k owns [floor(k n / p), floor((k+1) n / p)): blocks differ in size by at most one.
@@ -166,10 +174,30 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
     __shared__ SortSmem<NT, (int)sizeof(K)> sm;
     u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x;
-    const int k = blockIdx.x / a.tpb, tt = blockIdx.x % a.tpb;
-    const i64 st = blk_start(a.n, a.p, k), en = blk_start(a.n, a.p, k + 1);
-    const i64 base = st + (i64)tt * T;
-    i64 cnt64 = en - base;
+    i64 base, cnt64, sbase = (i64)blockIdx.x * a.spt;
+    K* outk = a.out;
+    u32* outv = a.outv;
+    int odt = a.out_dt;
+    K* smp = a.smp;
+    if (a.btab) {
+        const u32* bt = a.btab + 4 * (i64)blockIdx.x;
+        base = bt[0];
+        cnt64 = bt[1];
+        sbase = bt[3];
+        if (a.dtab && a.dtab[bt[2]]) {
+            outk = a.outd;
+            outv = a.outdv;
+            odt = a.in_dt;
+            smp = nullptr;
+        } else {
+            odt = BSPS_DT_NONE;
+        }
+    } else {
+        const int k = blockIdx.x / a.tpb, tt = blockIdx.x % a.tpb;
+        const i64 st = blk_start(a.n, a.p, k), en = blk_start(a.n, a.p, k + 1);
+        base = st + (i64)tt * T;
+        cnt64 = en - base;
+    }
     const int cnt = cnt64 <= 0 ? 0 : (cnt64 > T ? T : (int)cnt64);
     if (cnt == 0) return;
     const int i0 = t * IT;
@@ -190,24 +218,23 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
     block_minmax<NT, K>(mn, mx, sm.red64);
     const int nbits = bitwidth64((u64)(mx - mn));
     const u32 ysh = a.ys ? (u32)(__ffs(a.ys) - 1) : 0u;
-    K* out = a.out + base;
-    const i64 sbase = (i64)blockIdx.x * a.spt;
+    K* out = outk + base;
     if (sizeof(K) == 8 && nbits > 32) {
         u64 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = j < valid ? (u64)(kr[j] - mn) : (u64)(mx - mn);
         wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
-        store_sorted<K, u64, NT, IT>(sm.template ex<u64>(), mn, cnt, out, a.out_dt, a.smp, sbase, ysh);
+        store_sorted<K, u64, NT, IT>(sm.template ex<u64>(), mn, cnt, out, odt, smp, sbase, ysh);
     } else {
         u32 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = j < valid ? (u32)(kr[j] - mn) : (u32)(mx - mn);
         wg_sort_regs<NT, IT, u32, HASV>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
-        store_sorted<K, u32, NT, IT>(vex, mn, cnt, out, a.out_dt, a.smp, sbase, ysh);
+        store_sorted<K, u32, NT, IT>(vex, mn, cnt, out, odt, smp, sbase, ysh);
     }
     if (HASV) {
         wg_scatter_vals<NT, IT>(v, rank, vex);
-        u32* ov = a.outv + base;
+        u32* ov = outv + base;
 #pragma unroll
         for (int j = 0; j < IT; j++) {
             const int i = j * NT + t;

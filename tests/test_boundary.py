@@ -86,3 +86,20 @@ def test_trivial_sizes_are_noops(bsps):
 
 def test_null_keys_rejected(bsps):
     assert _call(bsps, 100, 0, bsps.make_params(2, 2), keys=0) == bsps.EINVAL
+
+
+def test_segmented_validation(bsps):
+    import numpy as np
+    ok = np.array([0, 10, 10, 25], dtype=np.int64)
+    assert bsps.segmented_workspace_bytes(ok, 0, False) > 0
+    assert bsps.segmented_workspace_bytes(np.array([1, 10], dtype=np.int64), 0, False) == 0   # must start at 0
+    assert bsps.segmented_workspace_bytes(np.array([0, 10, 5], dtype=np.int64), 0, False) == 0  # decreasing
+    assert bsps.segmented_workspace_bytes(ok, 7, False) == 0  # dtype
+    assert bsps.segmented_workspace_bytes(ok, 0, False, tuning='{"classes": []}') == 0
+    assert bsps.segmented_workspace_bytes(ok, 0, False, tuning='{"classes": [{"max_log2": 8, "block": 0, "s": 1}]}') == 0
+    good = '{"classes": [{"max_log2": 8, "block": 64, "s": 2}, {"max_log2": 30, "block": 4096, "s": 8}]}'
+    assert bsps.segmented_workspace_bytes(ok, 0, True, tuning=good) > bsps.segmented_workspace_bytes(ok, 0, False, tuning=good)
+    assert "max_log2" in bsps.tuning_format()
+    # a segment that needs more than 1024 blocks of one tile
+    big = np.array([0, 16384 * 1024 + 1], dtype=np.int64)
+    assert bsps.segmented_workspace_bytes(big, 0, False) == 0

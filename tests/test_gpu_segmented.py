@@ -1,0 +1,132 @@
+"""GPU parity of the batched segmented sort (many independent arrays, one
+captured graph launch) against the oracle, segment by segment."""
+import json
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TILE = {"int32": 16384, "float32": 16384, "int64": 8192}
+DEFAULT = [(14, 16384, 1), (17, 16384, 32), (20, 16384, 16), (40, 16384, 8)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1408_6729_amd  # noqa: F401
+    return torch.device("cuda:0")
+
+
+def _params(dtype, table=DEFAULT):
+    """The per-segment (p, s) rule of the library's tuning table."""
+    T = TILE[dtype]
+
+    def f(i, n):
+        c = next((c for c in table if n <= (1 << c[0])), table[-1])
+        block = min(c[1], T)
+        p = max(1, -(-n // block)) if n > 1 else 1
+        s = max(1, min(c[2], T // p))
+        return p, s, 0, 1
+    return f
+
+
+def _check(ora, dev, keys, offs, values=None, tuning=None, table=DEFAULT, reps=1):
+    import torch
+    import paper_1408_6729_amd as bsps
+    dtype = str(keys.dtype)
+    ref = ora.sort_segmented(keys, offs, _params(dtype, table), values)
+    outs = []
+    for _ in range(reps):
+        t = torch.from_numpy(keys.copy()).to(dev)
+        v = None if values is None else torch.from_numpy(values.view(np.int32).copy()).to(dev)
+        st = bsps.sort_segmented_(t, offs, values=v, tuning=tuning, stats=True)
+        torch.cuda.synchronize()
+        out = t.cpu().numpy()
+        a = out.view(np.uint32) if out.dtype == np.float32 else out
+        b = ref["keys"].view(np.uint32) if out.dtype == np.float32 else ref["keys"]
+        assert np.array_equal(a, b), "segmented keys differ from the oracle"
+        if values is not None:
+            assert np.array_equal(v.cpu().numpy().view(np.uint32), ref["values"])
+        outs.append(out)
+    return st
+
+
+def test_mixed_batch_int32(ora, dev):
+    """Scaled-down batch: log-uniform sizes in [2^8, 2^17], uniform and
+    2^8-distinct segments alternating."""
+    sizes = W.segment_sizes(300, 8, 17, seed=4)
+    keys, offs = W.segmented_int32(sizes, seed=4)
+    st = _check(ora, dev, keys, offs)
+    assert st["merged_segments"] > 0 and st["graph"]
+
+
+def test_kv_and_dtypes(ora, dev):
+    rng = np.random.default_rng(2)
+    sizes = rng.integers(0, 70000, size=40)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(offs[-1])
+    vals = np.arange(n, dtype=np.uint32)
+    for dtype in ("int32", "int64", "float32"):
+        keys = W.random_keys(n, dtype, seed=7, distinct=3000)
+        _check(ora, dev, keys, offs, values=vals)
+
+
+def test_edge_segments(ora, dev):
+    sizes = np.array([0, 1, 2, 0, 16383, 16384, 16385, 3, 0, 40000, 1], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(offs[-1])
+    keys = W.random_keys(n, "int32", seed=9, distinct=7)
+    keys[offs[9]:offs[10]] = 5  # an all-equal segment
+    _check(ora, dev, keys, offs, values=np.arange(n, dtype=np.uint32))
+
+
+def test_graph_replays_match_eager(ora, dev, monkeypatch):
+    """The cached graph is replayed several times, with eager work and syncs in
+    between; every replay equals the eager (no-graph) result and the oracle."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    sizes = W.segment_sizes(120, 8, 16, seed=11)
+    keys, offs = W.segmented_int32(sizes, seed=11)
+    n = keys.size
+    base = torch.from_numpy(keys).to(dev)
+    ws = torch.empty(bsps.segmented_workspace_bytes(offs, bsps.I32, False), dtype=torch.uint8, device=dev)
+    ref = ora.sort_segmented(keys, offs, _params("int32"))["keys"]
+    work = torch.empty_like(base)
+    for rep in range(4):
+        work.copy_(base)
+        torch.cuda.synchronize()
+        st = bsps.sort_segmented_(work, offs, workspace=ws, stats=True)
+        assert st["graph"]
+        eager_noise = torch.randn(1000, device=dev).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert np.array_equal(work.cpu().numpy(), ref), f"replay {rep} differs"
+        del eager_noise
+    monkeypatch.setenv("BSPS_NO_GRAPH", "1")
+    work.copy_(base)
+    st = bsps.sort_segmented_(work, offs, workspace=ws, stats=True)
+    torch.cuda.synchronize()
+    assert not st["graph"]
+    assert np.array_equal(work.cpu().numpy(), ref)
+    bsps.release_cache()
+    assert n == offs[-1]
+
+
+def test_custom_tuning_table(ora, dev):
+    table = [(12, 4096, 8), (40, 8192, 4)]
+    tj = json.dumps({"classes": [{"max_log2": a, "block": b, "s": c} for a, b, c in table]})
+    sizes = W.segment_sizes(60, 6, 16, seed=13)
+    keys, offs = W.segmented_int32(sizes, seed=13)
+    _check(ora, dev, keys, offs, tuning=tj, table=table)
+
+
+def test_bad_tuning_rejected(dev):
+    import torch
+    import paper_1408_6729_amd as bsps
+    t = torch.zeros(100, dtype=torch.int32, device=dev)
+    with pytest.raises(bsps.BspsError) as e:
+        bsps.sort_segmented_(t, np.array([0, 50, 100]), tuning='{"classes": [{"max_log2": 10}]}')
+    assert e.value.code == bsps.EINVAL
