@@ -87,7 +87,9 @@ typedef struct bsps_params {
 
 /*
  * Diagnostic statistics, HOST memory. Every pointer member may be NULL (not
- * filled). Passing a non-NULL bsps_stats* makes the call synchronous.
+ * filled). Passing a non-NULL bsps_stats* makes the call synchronous; the
+ * arrays are copied out through a pinned staging buffer (hipHostMalloc,
+ * freed before the call returns), 8 MiB at a time.
  */
 typedef struct bsps_stats {
     void* splitter_keys;       /* p-1 keys of the call's dtype */
@@ -132,7 +134,11 @@ bsps_status bsps_sort_kv(void* keys, uint32_t* values, int64_t n, int32_t dtype,
  * Sort nseg independent segments [h_offsets[i], h_offsets[i+1]) of one key
  * array (and payload array if values != NULL), each with its own (p, s)
  * chosen per size class by the built-in tuning table or by tuning_json. All
- * segments go through one captured graph launch.
+ * segments go through one captured graph launch, cached by the exact call
+ * signature (pointers, dtype, offsets, table) until bsps_release_cache().
+ * The per-call segment tables are uploaded into the workspace from a pinned
+ * host buffer the library owns; a call waits for the previous call's upload
+ * before refilling it. Not thread safe (shared cache and staging buffer).
  *  h_offsets   HOST, nseg + 1 non-decreasing entries, h_offsets[0] = 0
  *  tuning_json HOST, NULL for the built-in table (format: bsps_tuning_format())
  * Errors: EINVAL for nseg < 0, offsets not non-decreasing or not starting at 0,
@@ -200,7 +206,8 @@ bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int3
 const char* bsps_status_string(int32_t status);
 /* Format of the tuning table accepted by bsps_sort_segmented (static storage). */
 const char* bsps_tuning_format(void);
-/* Frees the library's cached graph executables (its only owned state). */
+/* Frees the library's owned state: the cached graph executables of the
+ * segmented sort, their capture stream and the pinned table-staging buffer. */
 void bsps_release_cache(void);
 
 /*

@@ -127,11 +127,14 @@ def _stream(t) -> int:
 
 
 def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, bucketing: int = SPLITTER,
-          route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0, stats: bool = False, workspace=None):
+          route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0, stats: bool = False, workspace=None,
+          stats_arrays: bool = False):
     """Sorts `keys` (a contiguous int32/int64/float32 CUDA tensor) in place; with
     `values` (uint32 payload as an int32 tensor of the same length) a key-value
     sort. With stats=True the call synchronizes and returns the diagnostic
-    statistics (splitters, sample, counts, block-sorted array ...)."""
+    statistics (splitters, sample, counts, bucket sizes ...); stats_arrays=True
+    adds the n-element arrays (block-sorted keys and payloads, and for the
+    scatter route the routed keys and bucket ids)."""
     import torch
     assert keys.is_cuda and keys.is_contiguous() and keys.dim() == 1
     n = keys.numel()
@@ -155,11 +158,12 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
             "splitter_keys": np.zeros(max(p - 1, 1), kd), "splitter_pos": np.zeros(max(p - 1, 1), np.int64),
             "sample_keys": np.zeros(max(ns, 1), kd), "sample_pos": np.zeros(max(ns, 1), np.int64),
             "bucket_sizes": np.zeros(p, np.int64), "count_matrix": np.zeros(p * p, np.int64),
-            "block_sorted": np.zeros(max(n, 1), kd),
         }
-        if hasv:
+        if stats_arrays:
+            host["block_sorted"] = np.zeros(max(n, 1), kd)
+        if hasv and stats_arrays:
             host["block_sorted_values"] = np.zeros(max(n, 1), np.uint32)
-        if route == ROUTE_SCATTER:
+        if route == ROUTE_SCATTER and stats_arrays:
             host["routed"] = np.zeros(max(n, 1), kd)
             host["buckets"] = np.zeros(max(n, 1), np.uint32)
         for k, arr in host.items():
@@ -181,7 +185,8 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
     out["sample_keys"] = out["sample_keys"][:ns]
     out["sample_pos"] = out["sample_pos"][:ns]
     out["count_matrix"] = out["count_matrix"].reshape(p, p)
-    out["block_sorted"] = out["block_sorted"][:n]
+    if stats_arrays:
+        out["block_sorted"] = out["block_sorted"][:n]
     out["max_bucket_ratio"] = st.max_bucket_ratio
     out["mispredict_rate"] = st.mispredict_rate
     out["mean_fix_dist"] = st.mean_fix_dist
@@ -261,21 +266,44 @@ def model_fields(model):
     return {"lo": lo, "hi": hi, "a": a, "b": b, "mur": mur, "inv": inv, "L": int(L), "p": int(p), "s": int(s)}, leaf
 
 
+TUNING_PATH = os.path.join(_HERE, "tuning_mi355x.json")
+_tuning_cache: list = []
+
+
+def default_tuning() -> str | None:
+    """The size-class table the segmented sort uses when none is given: the
+    autotuner's output beside this file if present (else the library's
+    built-in table, returned here as None)."""
+    if not _tuning_cache:
+        txt = None
+        if os.path.exists(TUNING_PATH):
+            with open(TUNING_PATH) as f:
+                txt = f.read()
+        _tuning_cache.append(txt)
+    return _tuning_cache[0]
+
+
+def _tuning_arg(tuning):
+    t = tuning if tuning is not None else default_tuning()
+    return t.encode() if t else None
+
+
 def segmented_workspace_bytes(offsets, dtype: int, with_values: bool, tuning: str | None = None) -> int:
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     return int(_lib.bsps_segmented_workspace_bytes(off.ctypes.data, len(off) - 1, dtype, int(with_values),
-                                                   tuning.encode() if tuning else None))
+                                                   _tuning_arg(tuning)))
 
 
 def sort_segmented_(keys, offsets, values=None, tuning: str | None = None, stats: bool = False, workspace=None):
     """Sorts every segment [offsets[i], offsets[i+1]) of `keys` (and `values`)
     in place, all segments in one captured graph launch. `offsets`: host array
-    of nseg + 1 non-decreasing int64 starting at 0."""
+    of nseg + 1 non-decreasing int64 starting at 0. `tuning`: a size-class
+    table (JSON, `tuning_format()`); default `default_tuning()`."""
     import torch
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     nseg = len(off) - 1
     dt = _dtype_code(keys)
-    tj = tuning.encode() if tuning else None
+    tj = _tuning_arg(tuning)
     need = _lib.bsps_segmented_workspace_bytes(off.ctypes.data, nseg, dt, int(values is not None), tj)
     if need == 0 and nseg > 0 and off[-1] > 0:
         code = _lib.bsps_sort_segmented(None, None, off.ctypes.data, nseg, dt, tj, None, 0, None, None)

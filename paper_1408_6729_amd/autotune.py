@@ -1,0 +1,143 @@
+"""Autotuner of the batched segmented sort's size-class table.
+
+The segmented sort gives every segment of n keys p = ceil(n / block) virtual
+processors (each block at most one tile) and oversampling s; segments are
+grouped by size class (n <= 2^max_log2) and every class has its own (block, s).
+This tool measures, on the GPU, each candidate (block, s) of a class on a
+synthetic batch made only of segments of that class (sizes log-uniform inside
+the class, uniform and 2^8-distinct segments alternating), timing the whole
+captured graph launch with HIP events on the launching stream, and writes
+the fastest table as JSON in the library's tuning format:
+
+    python -m paper_1408_6729_amd.autotune [--out tuning.json] [--keys-per-class 2^25]
+
+A table written here is used by `sort_segmented_` when passed as `tuning`,
+and the package loads `tuning_mi355x.json` beside this file by default.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+CLASSES = (14, 16, 18, 20, 30)
+BLOCKS = (2048, 4096, 8192, 16384)
+OVERSAMPLING = (1, 2, 4, 8, 16, 32, 64)
+
+
+def _log(msg):
+    print(f"[autotune] {msg}", file=sys.stderr, flush=True)
+
+
+def _batch(lo_log2: float, hi_log2: float, total: int, seed: int):
+    import numpy as np
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import workloads as W
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = []
+    while sum(sizes) < total:
+        sizes.append(int(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * rng.random())))
+    return W.segmented_int32(np.array(sizes, dtype=np.int64), seed=seed)
+
+
+def _table(classes):
+    return json.dumps({"classes": [{"max_log2": c, "block": b, "s": s} for c, (b, s) in classes]})
+
+
+def _time(bsps, torch, base, offs, tuning: str, reps: int) -> float:
+    """Median milliseconds of one graph launch over `reps` staged copies."""
+    n = base.numel()
+    ws = torch.empty(max(1, bsps.segmented_workspace_bytes(offs, bsps.I32, False, tuning)), dtype=torch.uint8,
+                     device=base.device)
+    copies = torch.empty((reps + 1, n), dtype=torch.int32, device=base.device)
+    for i in range(reps + 1):
+        copies[i].copy_(base)
+    bsps.sort_segmented_(copies[0], offs, tuning=tuning, workspace=ws)  # capture + warm-up
+    torch.cuda.synchronize()
+    times = []
+    for i in range(1, reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        bsps.sort_segmented_(copies[i], offs, tuning=tuning, workspace=ws)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    out = copies[reps]
+    desc = out[1:] < out[:-1]
+    inner = torch.as_tensor(offs[1:-1], dtype=torch.int64, device=base.device)
+    inner = inner[(inner > 0) & (inner < n)]
+    desc[inner - 1] = False  # a descent across a segment boundary is allowed
+    if bool(desc.any()):
+        raise RuntimeError(f"segmented sort produced an unsorted segment with tuning {tuning}")
+    bsps.release_cache()
+    return sorted(times)[len(times) // 2]
+
+
+def tune(classes=CLASSES, blocks=BLOCKS, oversampling=OVERSAMPLING, keys_per_class=1 << 25, reps=5):
+    import torch
+    import paper_1408_6729_amd as bsps
+    dev = torch.device("cuda:0")
+    tile = 16384
+    best = []
+    lo = 8.0
+    report = []
+    for ci, c in enumerate(classes):
+        hi = float(min(c, 20))
+        if hi <= lo:  # beyond the largest measured size: keep the last winner
+            best.append((c, best[-1][1] if best else (tile, 8)))
+            continue
+        keys, offs = _batch(lo, hi, keys_per_class, seed=100 + ci)
+        pin = torch.empty(keys.shape, dtype=torch.int32, pin_memory=True)
+        pin.copy_(torch.from_numpy(keys))
+        base = pin.to(dev)
+        del pin
+        n = keys.size
+        cands = []
+        for b in blocks:
+            if b > tile:
+                continue
+            pmax = -(-(1 << int(hi)) // b)
+            for s in oversampling:
+                if pmax == 1 and s > 1:
+                    continue  # one block per segment: no sample at all
+                if pmax * s > tile:
+                    continue
+                cands.append((b, s))
+        results = []
+        for b, s in cands:
+            tb = [(cc, bs) for cc, bs in best] + [(c, (b, s))] + [(cc, (tile, 8)) for cc in classes[ci + 1:]]
+            ms = _time(bsps, torch, base, offs, _table(tb), reps)
+            results.append((ms, b, s))
+            _log(f"class <=2^{c}: block {b:5d} s {s:2d}: {ms:8.3f} ms  {n / ms / 1e6:7.2f} Gkeys/s")
+        ms, b, s = min(results)
+        best.append((c, (b, s)))
+        report.append({"max_log2": c, "block": b, "s": s, "ms": ms, "keys": n, "keys_per_s": n / (ms / 1e3),
+                       "candidates": [{"block": bb, "s": ss, "ms": mm} for mm, bb, ss in results]})
+        lo = hi
+        del base
+        torch.cuda.empty_cache()
+    return json.loads(_table(best)), report
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_mi355x.json"))
+    ap.add_argument("--report", default=None, help="also write every candidate's timing here")
+    ap.add_argument("--keys-per-class", type=int, default=1 << 25)
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
+    t0 = time.time()
+    table, report = tune(keys_per_class=args.keys_per_class, reps=args.reps)
+    with open(args.out, "w") as f:
+        json.dump(table, f, indent=1)
+        f.write("\n")
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(report, f, indent=1)
+    _log(f"wrote {args.out} in {time.time() - t0:.0f} s: {json.dumps(table)}")
+
+
+if __name__ == "__main__":
+    main()

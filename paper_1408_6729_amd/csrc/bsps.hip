@@ -443,12 +443,34 @@ u32 raw_of<u32>(u32 u, int dt) {
 template <>
 u64 raw_of<u64>(u64 u, int dt) { (void)dt; return u ^ 0x8000000000000000ull; }
 
+// Device-to-host copy for the diagnostic paths. It goes through a small
+// pinned buffer from hipHostMalloc, chunk by chunk, and never hands a large
+// pageable host range to the runtime.
+bsps_status d2h(void* host, const void* dev, size_t bytes, hipStream_t st) {
+    if (!host || bytes == 0) return BSPS_OK;
+    constexpr size_t CH = (size_t)8 << 20;
+    void* pin = nullptr;
+    if (hipHostMalloc(&pin, std::min(bytes, CH), hipHostMallocDefault) != hipSuccess) return BSPS_EDEVICE;
+    bsps_status rc = BSPS_OK;
+    for (size_t off = 0; off < bytes; off += CH) {
+        const size_t b = std::min(CH, bytes - off);
+        if (hipMemcpyAsync(pin, (const char*)dev + off, b, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = BSPS_EDEVICE;
+            break;
+        }
+        std::memcpy((char*)host + off, pin, b);
+    }
+    if (hipHostFree(pin) != hipSuccess && rc == BSPS_OK) rc = BSPS_EDEVICE;
+    return rc;
+}
+
 template <typename K>
 bsps_status copy_keys_out(void* host, const K* dev, i64 count, int dt, hipStream_t st) {
     if (!host || count <= 0) return BSPS_OK;
     std::vector<K> tmp((size_t)count);
-    HIP_OK(hipMemcpyAsync(tmp.data(), dev, sizeof(K) * count, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    const bsps_status rc = d2h(tmp.data(), dev, sizeof(K) * (size_t)count, st);
+    if (rc) return rc;
     K* h = (K*)host;
     for (i64 i = 0; i < count; i++) h[i] = raw_of<K>(tmp[i], dt);
     return BSPS_OK;
@@ -457,8 +479,8 @@ bsps_status copy_keys_out(void* host, const K* dev, i64 count, int dt, hipStream
 bsps_status copy_u32_to_i64(int64_t* host, const u32* dev, i64 count, hipStream_t st) {
     if (!host || count <= 0) return BSPS_OK;
     std::vector<u32> tmp((size_t)count);
-    HIP_OK(hipMemcpyAsync(tmp.data(), dev, sizeof(u32) * count, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    const bsps_status rc = d2h(tmp.data(), dev, sizeof(u32) * (size_t)count, st);
+    if (rc) return rc;
     for (i64 i = 0; i < count; i++) host[i] = tmp[i];
     return BSPS_OK;
 }
@@ -486,8 +508,8 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         if (rc) return rc;
     }
     if (stats && stats->block_sorted_values && HASV) {
-        HIP_OK(hipMemcpyAsync(stats->block_sorted_values, P.Bv, 4 * n, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
+        rc = d2h(stats->block_sorted_values, P.Bv, 4 * (size_t)n, st);
+        if (rc) return rc;
     }
     if (p == 1) {
         hipLaunchKernelGGL((k_copy_out<K>), dim3((u32)cdiv(n, 256)), dim3(256), 0, st, P.B, HASV ? P.Bv : nullptr, io,
@@ -596,8 +618,8 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
             if (rc) return rc;
         }
         if (stats && stats->buckets) {
-            HIP_OK(hipMemcpyAsync(stats->buckets, P.bucket, 4 * n, hipMemcpyDeviceToHost, st));
-            HIP_OK(hipStreamSynchronize(st));
+            rc = d2h(stats->buckets, P.bucket, 4 * (size_t)n, st);
+            if (rc) return rc;
         }
         // A6: per-bucket merge of the routed runs (B is free: oversize scratch).
         {
@@ -619,12 +641,16 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         rc = copy_u32_to_i64(stats->sample_pos, P.ssp, ns, st);
         if (rc) return rc;
         std::vector<u32> ct((size_t)(p + 1) * p);
-        HIP_OK(hipMemcpyAsync(ct.data(), P.cntT, 4 * ct.size(), hipMemcpyDeviceToHost, st));
+        rc = d2h(ct.data(), P.cntT, 4 * ct.size(), st);
+        if (rc) return rc;
         u32 ctr[2];
-        HIP_OK(hipMemcpyAsync(ctr, P.bm.counters, 8, hipMemcpyDeviceToHost, st));
+        rc = d2h(ctr, P.bm.counters, 8, st);
+        if (rc) return rc;
         u32 ctr2[2] = {0, 0};
-        if (P.bs.tpb > 1) HIP_OK(hipMemcpyAsync(ctr2, P.bs.mwm.counters, 8, hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
+        if (P.bs.tpb > 1) {
+            rc = d2h(ctr2, P.bs.mwm.counters, 8, st);
+            if (rc) return rc;
+        }
         double mx = 0;
         for (int i = 0; i < p; i++) {
             i64 bsz = 0;
@@ -640,7 +666,8 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         stats->oversize_chunks = (i64)ctr[1] + (i64)ctr2[1];
         if (prm->route == BSPS_ROUTE_SCATTER && prm->bucketing == BSPS_LEARNED) {
             unsigned long long ls[2];
-            HIP_OK(hipMemcpy(ls, P.C + (size_t)p * p, 16, hipMemcpyDeviceToHost));
+            rc = d2h(ls, P.C + (size_t)p * p, 16, st);
+            if (rc) return rc;
             stats->mispredict_rate = (double)ls[0] / (double)n;
             stats->mean_fix_dist = (double)ls[1] / (double)n;
         }
@@ -917,6 +944,36 @@ bsps_status enqueue_segmented(const SegPlan& P, const SegBufs<K>& b, K* io, u32*
 }
 
 // Cached graph executables, keyed by everything the captured launches depend on.
+// Pinned host buffer the segmented sort's tables are uploaded from. The
+// upload is asynchronous on the caller's stream; the next call waits for the
+// previous upload (event `done`) before it refills the buffer.
+struct TableStage {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+TableStage g_tstage;
+
+bsps_status table_stage(size_t bytes, char** out) {
+    if (g_tstage.done && hipEventSynchronize(g_tstage.done) != hipSuccess) return BSPS_EDEVICE;
+    if (!g_tstage.done && hipEventCreateWithFlags(&g_tstage.done, hipEventDisableTiming) != hipSuccess) {
+        g_tstage.done = nullptr;
+        return BSPS_EDEVICE;
+    }
+    if (g_tstage.cap < bytes) {
+        if (g_tstage.p && hipHostFree(g_tstage.p) != hipSuccess) return BSPS_EDEVICE;
+        g_tstage.p = nullptr;
+        g_tstage.cap = 0;
+        if (hipHostMalloc(&g_tstage.p, bytes, hipHostMallocDefault) != hipSuccess) {
+            g_tstage.p = nullptr;
+            return BSPS_EDEVICE;
+        }
+        g_tstage.cap = bytes;
+    }
+    *out = (char*)g_tstage.p;
+    return BSPS_OK;
+}
+
 struct GraphCache {
     std::map<std::string, hipGraphExec_t> execs;
     hipStream_t cap = nullptr;
@@ -925,18 +982,16 @@ GraphCache g_graphs;
 
 std::string graph_key(const void* a, const void* b, const void* c, const int64_t* off, int nseg, int dt, bool hasv,
                       const Tuning& tu) {
-    u64 h = 1469598103934665603ull;
-    auto mix = [&](u64 v) {
-        h ^= v;
-        h *= 1099511628211ull;
-    };
-    mix((u64)(uintptr_t)a); mix((u64)(uintptr_t)b); mix((u64)(uintptr_t)c); mix((u64)nseg); mix((u64)dt);
-    mix((u64)hasv);
-    for (int i = 0; i <= nseg; i++) mix((u64)off[i]);
-    for (auto& cc : tu.cls) { mix((u64)cc.max_log2); mix((u64)cc.block); mix((u64)cc.s); }
-    char buf[64];
-    snprintf(buf, sizeof(buf), "%016llx-%d", (unsigned long long)h, nseg);
-    return std::string(buf);
+    // The whole call signature, byte for byte (no hash: a collision would
+    // replay another call's graph).
+    std::string k;
+    auto put = [&](u64 v) { k.append((const char*)&v, sizeof(v)); };
+    put((u64)(uintptr_t)a); put((u64)(uintptr_t)b); put((u64)(uintptr_t)c); put((u64)nseg); put((u64)dt);
+    put((u64)hasv);
+    put((u64)tu.cls.size());
+    for (auto& cc : tu.cls) { put((u64)cc.max_log2); put((u64)cc.block); put((u64)cc.s); }
+    k.append((const char*)off, sizeof(int64_t) * ((size_t)nseg + 1));
+    return k;
 }
 
 template <typename K, bool HASV>
@@ -953,17 +1008,21 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
     const size_t need = carve_seg<K>(c, P, HASV, b, o.tavg);
     if (!ws || ws_bytes < need) return BSPS_EWORKSPACE;
     if (P.NB == 0) return BSPS_OK;
-    // tables -> workspace (host staging in carve order)
+    // tables -> workspace (pinned host staging in carve order, asynchronous)
     {
-        std::vector<char> stage(b.tables_bytes, 0);
-        Carver hc(stage.data());
+        char* stage = nullptr;
+        rc = table_stage(b.tables_bytes, &stage);
+        if (rc) return rc;
+        std::memset(stage, 0, b.tables_bytes);
+        Carver hc(stage);
         auto put = [&](const std::vector<u32>& v) {
             u32* d = hc.take<u32>(v.size());
             std::memcpy(d, v.data(), v.size() * sizeof(u32));
         };
         put(P.seg); put(P.soff); put(P.poff); put(P.coff); put(P.btab); put(P.dtab); put(P.btab_s);
         for (auto& g : P.gtab) put(g);
-        HIP_OK(hipMemcpyAsync(b.tables, stage.data(), stage.size(), hipMemcpyHostToDevice, st));
+        HIP_OK(hipMemcpyAsync(b.tables, stage, b.tables_bytes, hipMemcpyHostToDevice, st));
+        HIP_OK(hipEventRecord(g_tstage.done, st));
     }
     // capture every launch into one graph (on a private stream), launch it once
     const bool timed = g_timer.on;
@@ -1005,7 +1064,8 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
         i64 over = 0;
         for (auto& m : b.mw) {
             u32 ctr[2];
-            HIP_OK(hipMemcpy(ctr, m.counters, 8, hipMemcpyDeviceToHost));
+            rc = d2h(ctr, m.counters, 8, st);
+            if (rc) return rc;
             over += ctr[1];
         }
         stats->oversize_chunks = over;
@@ -1112,8 +1172,8 @@ bsps_status bsps_rank(const void* keys, int64_t n, int32_t dtype, int32_t p, con
     LAUNCH_OK();
     if (st) {
         unsigned long long h[2];
-        HIP_OK(hipMemcpyAsync(h, lst, 16, hipMemcpyDeviceToHost, s));
-        HIP_OK(hipStreamSynchronize(s));
+        const bsps_status rc = d2h(h, lst, 16, s);
+        if (rc) return rc;
         st->mispredict_rate = (double)h[0] / (double)n;
         st->mean_fix_dist = (double)h[1] / (double)n;
     }
@@ -1213,6 +1273,12 @@ void bsps_release_cache(void) {
     g_graphs.execs.clear();
     if (g_graphs.cap) (void)hipStreamDestroy(g_graphs.cap);
     g_graphs.cap = nullptr;
+    if (g_tstage.done) {
+        (void)hipEventSynchronize(g_tstage.done);
+        (void)hipEventDestroy(g_tstage.done);
+    }
+    if (g_tstage.p) (void)hipHostFree(g_tstage.p);
+    g_tstage = TableStage();
 }
 
 int bsps_timing(int enable) {
@@ -1246,11 +1312,11 @@ int bsps_timing_read(double* ms, int64_t* launches, int nstage, int reset) {
 
 #ifdef BSPS_TIMING
 int bsps_debug_phases(unsigned long long* out, int reset) {
-    unsigned long long h[8];
+    unsigned long long h[16];
     if (hipMemcpyFromSymbol(h, HIP_SYMBOL(g_phase), sizeof(h)) != hipSuccess) return 1;
-    for (int i = 0; i < 8; i++) out[i] = h[i];
+    for (int i = 0; i < 16; i++) out[i] = h[i];
     if (reset) {
-        unsigned long long z[8] = {0};
+        unsigned long long z[16] = {0};
         if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase), z, sizeof(z)) != hipSuccess) return 1;
     }
     return 0;

@@ -27,13 +27,15 @@
 constexpr int MAXR = 1024;  // runs per merge group (tiles per block, or p)
 
 #ifdef BSPS_TIMING
-__device__ unsigned long long g_phase[8];
+// Per-phase cycle sums of the merge kernel: [0, 8) merges that emit output
+// samples (block merges), [8, 16) the others (bucket merges).
+__device__ unsigned long long g_phase[16];
 #define PHASE(k)                                                               \
     do {                                                                       \
         __syncthreads();                                                       \
         if (threadIdx.x == 0) {                                                \
             const unsigned long long now = __builtin_amdgcn_s_memtime();       \
-            atomicAdd(&g_phase[k], now - t_last);                              \
+            atomicAdd(&g_phase[(k) + (a.osmp ? 0 : 8)], now - t_last);         \
             t_last = now;                                                      \
         }                                                                      \
     } while (0)

@@ -39,7 +39,7 @@ def test_scatter_route_parity(ora, dev, bucketing, dtype, variant):
     t = _t(keys, dev)
     v = _t(vals.view(np.int32), dev)
     st = bsps.sort_(t, p, s, variant, seed=5, values=v, bucketing=bucketing, route=bsps.ROUTE_SCATTER,
-                    leaves=256, stats=True)
+                    leaves=256, stats=True, stats_arrays=True)
     torch.cuda.synchronize()
     assert np.array_equal(_bits(t.cpu().numpy()), _bits(ref["keys"]))
     assert np.array_equal(v.cpu().numpy().view(np.uint32), ref["values"])

@@ -10,7 +10,17 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 TILE = {"int32": 16384, "float32": 16384, "int64": 8192}
-DEFAULT = [(14, 16384, 1), (17, 16384, 32), (20, 16384, 16), (40, 16384, 8)]
+BUILTIN = [(14, 16384, 1), (17, 16384, 32), (20, 16384, 16), (40, 16384, 8)]
+
+
+def _default_table():
+    """The table the library uses when the call names none: the autotuned
+    file if the package ships one, else the built-in table."""
+    import paper_1408_6729_amd as bsps
+    txt = bsps.default_tuning()
+    if not txt:
+        return BUILTIN
+    return [(c["max_log2"], c["block"], c["s"]) for c in json.loads(txt)["classes"]]
 
 
 @pytest.fixture(scope="module")
@@ -21,9 +31,10 @@ def dev():
     return torch.device("cuda:0")
 
 
-def _params(dtype, table=DEFAULT):
+def _params(dtype, table=None):
     """The per-segment (p, s) rule of the library's tuning table."""
     T = TILE[dtype]
+    table = table or _default_table()
 
     def f(i, n):
         c = next((c for c in table if n <= (1 << c[0])), table[-1])
@@ -34,7 +45,7 @@ def _params(dtype, table=DEFAULT):
     return f
 
 
-def _check(ora, dev, keys, offs, values=None, tuning=None, table=DEFAULT, reps=1):
+def _check(ora, dev, keys, offs, values=None, tuning=None, table=None, reps=1):
     import torch
     import paper_1408_6729_amd as bsps
     dtype = str(keys.dtype)

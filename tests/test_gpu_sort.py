@@ -31,7 +31,7 @@ def _run(dev, keys, p, s, variant, seed=1, values=None, chunk_cap=0):
     import paper_1408_6729_amd as bsps
     t = _torch_keys(keys, dev)
     v = None if values is None else torch.from_numpy(values.view(np.int32)).to(dev)
-    st = bsps.sort_(t, p, s, variant, seed, values=v, chunk_cap=chunk_cap, stats=True)
+    st = bsps.sort_(t, p, s, variant, seed, values=v, chunk_cap=chunk_cap, stats=True, stats_arrays=True)
     torch.cuda.synchronize()
     out = t.cpu().numpy()
     outv = None if v is None else v.cpu().numpy().view(np.uint32)
