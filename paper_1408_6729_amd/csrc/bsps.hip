@@ -136,7 +136,7 @@ void carve_mwm(Carver& c, MwmBufs<K>& m, int G, int R, u64 n, u32 tavg) {
 template <typename K>
 MwmArgs<K> mwm_args(const MwmBufs<K>& m, const K* src, const u32* srcv, K* dst, u32* dstv, K* scr, u32* scrv,
                     const K* smp, u32 cap, u32 tavg, int out_dt, K* osmp, u32 oys, u32 ospb) {
-    MwmArgs<K> a;
+    MwmArgs<K> a{};
     a.src = src; a.srcv = srcv; a.dst = dst; a.dstv = dstv; a.scr = scr; a.scrv = scrv;
     a.G = m.G; a.R = m.R;
     a.run_start = m.run_start; a.run_len = m.run_len; a.out_base = m.out_base; a.sdesc = m.sdesc;
@@ -226,7 +226,7 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
                        hipStream_t st, int tstage = ST_N, int mstage = ST_N, int mkstage = ST_N) {
     constexpr int NT = Shape<K>::NT;
     const u32 T = tileT<K>();
-    TileArgs<K> ta;
+    TileArgs<K> ta{};
     ta.in = in; ta.inv = inv; ta.n = n; ta.p = p; ta.tpb = b.tpb; ta.in_dt = in_dt;
     if (b.tpb == 1) {
         ta.out = out; ta.outv = outv; ta.out_dt = out_dt; ta.smp = osmp; ta.ys = yb; ta.spt = spb;
@@ -261,7 +261,7 @@ struct FitWs {
 };
 
 FitWs carve_fit(Carver& c, i64 N, int L) {
-    FitWs f;
+    FitWs f{};
     const i64 N1 = std::max<i64>(1, N);
     f.x = c.take<float>(N1);
     f.leafid = c.take<int32_t>(N1);
@@ -319,7 +319,7 @@ struct Opts {
 template <typename K>
 Opts opts_for(const bsps_params* prm) {
     const u32 T = tileT<K>();
-    Opts o;
+    Opts o{};
     o.cap = (prm && prm->chunk_cap > 0) ? std::min<u32>((u32)prm->chunk_cap, T) : T;
     o.tavg = std::max<u32>(1, o.cap / 4);  // floor of the adaptive chunk target
     return o;
@@ -492,7 +492,7 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
                      hipStream_t st, bsps_stats* stats) {
     const int p = prm->p, s = prm->s;
     Carver c(ws);
-    Plan<K> P;
+    Plan<K> P{};
     const size_t need = carve_plan<K>(c, P, n, HASV, prm);
     if (!ws || ws_bytes < need) return BSPS_EWORKSPACE;
     const Opts o = opts_for<K>(prm);
@@ -890,7 +890,7 @@ bsps_status enqueue_segmented(const SegPlan& P, const SegBufs<K>& b, K* io, u32*
                               hipStream_t st) {
     constexpr int NT = Shape<K>::NT;
     if (P.NB == 0) return BSPS_OK;
-    TileArgs<K> ta;
+    TileArgs<K> ta{};
     std::memset(&ta, 0, sizeof(ta));
     ta.in = io; ta.inv = vals; ta.n = P.n; ta.p = 1; ta.tpb = 1; ta.in_dt = dt;
     ta.out = b.B; ta.outv = b.Bv; ta.out_dt = BSPS_DT_NONE; ta.smp = b.bsmp; ta.ys = kSampleStride; ta.spt = 0;
@@ -907,7 +907,7 @@ bsps_status enqueue_segmented(const SegPlan& P, const SegBufs<K>& b, K* io, u32*
         hipLaunchKernelGGL((k_seg_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, b.B, b.seg, b.soff,
                            P.nseg, b.skey, b.spos);
         LAUNCH_OK();
-        TileArgs<K> tb;
+        TileArgs<K> tb{};
         std::memset(&tb, 0, sizeof(tb));
         tb.in = b.skey; tb.inv = b.spos; tb.n = ns; tb.p = 1; tb.tpb = 1; tb.in_dt = BSPS_DT_NONE;
         tb.out = b.ssk; tb.outv = b.ssp; tb.out_dt = BSPS_DT_NONE; tb.smp = nullptr; tb.ys = 1;
@@ -997,13 +997,13 @@ std::string graph_key(const void* a, const void* b, const void* c, const int64_t
 template <typename K, bool HASV>
 bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, int dt, const Tuning& tu, void* ws,
                           size_t ws_bytes, hipStream_t st, bsps_stats* stats) {
-    SegPlan P;
+    SegPlan P{};
     bsps_status rc = make_seg_plan<K>(off, nseg, tu, P);
     if (rc) return rc;
     bsps_params dp;
     std::memset(&dp, 0, sizeof(dp));
     const Opts o = opts_for<K>(&dp);
-    SegBufs<K> b;
+    SegBufs<K> b{};
     Carver c(ws);
     const size_t need = carve_seg<K>(c, P, HASV, b, o.tavg);
     if (!ws || ws_bytes < need) return BSPS_EWORKSPACE;
@@ -1226,7 +1226,7 @@ size_t bsps_segmented_workspace_bytes(const int64_t* h_offsets, int32_t nseg, in
                                       const char* tuning_json) {
     Tuning tu;
     if (validate_segments(h_offsets, nseg, dtype, tuning_json, tu) != BSPS_OK) return 0;
-    SegPlan P;
+    SegPlan P{};
     bsps_params dp;
     std::memset(&dp, 0, sizeof(dp));
     Carver c(nullptr);

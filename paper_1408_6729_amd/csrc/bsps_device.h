@@ -67,7 +67,13 @@ __device__ __forceinline__ int bitwidth64(u64 v) { return v ? 64 - __clzll((long
 // Workgroup sort shapes: 4-byte keys use 512 threads x 32 items (16K keys),
 // 8-byte keys use 256 threads x 32 items (8K keys).
 template <typename K> struct Shape;
-template <> struct Shape<u32> { static constexpr int NT = 512, IT = 32; };
+#ifndef BSPS_NT32
+#define BSPS_NT32 512
+#endif
+#ifndef BSPS_IT32
+#define BSPS_IT32 32
+#endif
+template <> struct Shape<u32> { static constexpr int NT = BSPS_NT32, IT = BSPS_IT32; };
 template <> struct Shape<u64> { static constexpr int NT = 256, IT = 32; };
 
 #ifndef BSPS_DIG_RECOMPUTE
@@ -90,7 +96,7 @@ __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }  // one pad 
 template <int NT, int KB> struct SortSmem {
     static constexpr int CNT = HALF * NT;
     static constexpr int CNTW = CNT + CNT / 32;
-    static constexpr int EXW = (NT * 32 + NT) * KB / 4;  // IT = 32 items of KB bytes
+    static constexpr int EXW = (NT * 32 + NT) * KB / 4;  // up to 32 items of KB bytes per thread
     static constexpr int UW = CNTW > EXW ? CNTW : EXW;
     u32 u[UW];
     u32 wsum[NT / 64 + 2];
