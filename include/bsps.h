@@ -77,7 +77,7 @@ typedef struct bsps_params {
     int32_t variant;    /* bsps_variant */
     int32_t bucketing;  /* bsps_bucketing; applies to route = BSPS_ROUTE_SCATTER */
     int32_t route;      /* bsps_route */
-    int32_t leaves;     /* learned model: leaf models (0 = 4096) */
+    int32_t leaves;     /* learned model: leaf models, 1..4096 (0 = 4096) */
     uint64_t seed;      /* RAN: key of the sample permutation */
     int32_t chunk_cap;  /* 0 = default. Largest merge chunk sorted in LDS; a smaller
                            value routes more chunks through the global-memory path
@@ -106,7 +106,9 @@ typedef struct bsps_stats {
     double mispredict_rate;    /* learned bucketing: fraction of keys corrected */
     double mean_fix_dist;      /* learned bucketing: mean |predicted - true| */
     int64_t oversize_chunks;   /* merge chunks sorted by the global-memory path */
-    int64_t reserved_i[4];
+    int64_t reserved_i[4];     /* bsps_sort: [0] oversize chunks of the block merge, [1] of the
+                                  bucket merge, [2] keys in the largest one. bsps_sort_segmented:
+                                  [0] blocks, [1] merged segments, [2] 1 if the graph was used */
 } bsps_stats;
 
 /* Bytes of device workspace a sort of n keys needs (values: 0 or 1). Returns
@@ -118,7 +120,7 @@ size_t bsps_workspace_bytes(int64_t n, int32_t dtype, int32_t with_values, const
  *  keys      device, n keys of `dtype`; replaced by the sorted keys
  *  ws        device workspace of ws_bytes >= bsps_workspace_bytes(n, dtype, 0, prm)
  * Errors: EINVAL for n < 0, p < 1, p > max(n, 1), s < 1, RAN with s*p - 1 > n,
- * unknown dtype/variant/route/bucketing, leaves < 0, nonzero reserved fields;
+ * unknown dtype/variant/route/bucketing, leaves < 0 or > 4096, nonzero reserved fields;
  * EWORKSPACE; EUNSUPPORTED beyond the limits above. n = 0 and n = 1 are
  * valid no-ops.
  */

@@ -13,6 +13,9 @@ import ctypes as ct
 import os
 
 import numpy as np
+# torch first: the library must bind to the HIP runtime torch has loaded
+# (loading it before torch can leave the process with two runtimes).
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("BSPS_LIB") or os.path.join(_HERE, "libbsps.so")
@@ -191,6 +194,7 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
     out["mispredict_rate"] = st.mispredict_rate
     out["mean_fix_dist"] = st.mean_fix_dist
     out["oversize_chunks"] = st.oversize_chunks
+    out["oversize_block"], out["oversize_bucket"], out["oversize_max"] = (int(x) for x in st.reserved_i[:3])
     return out
 
 

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -30,13 +31,26 @@ namespace {
 constexpr u32 kSampleStride = 32;  // tile and block samples for the merges: every 32nd key
 constexpr int kMaxP = MAXR;  // p <= 1024
 
-#define HIP_OK(x)                                              \
-    do {                                                       \
-        if ((x) != hipSuccess) return BSPS_EDEVICE;            \
+// A failed HIP call maps to BSPS_EDEVICE; with BSPS_DEBUG set in the
+// environment the call, the source line and HIP's message go to stderr.
+bool debug_on() {
+    static int v = -1;
+    if (v < 0) v = std::getenv("BSPS_DEBUG") ? 1 : 0;
+    return v == 1;
+}
+bsps_status hip_fail(hipError_t e, const char* what, int line) {
+    if (debug_on()) std::fprintf(stderr, "[bsps] %s failed (bsps.hip:%d): %s\n", what, line, hipGetErrorString(e));
+    return BSPS_EDEVICE;
+}
+#define HIP_OK(x)                                                      \
+    do {                                                               \
+        const hipError_t e_ = (x);                                     \
+        if (e_ != hipSuccess) return hip_fail(e_, #x, __LINE__);       \
     } while (0)
-#define LAUNCH_OK()                                            \
-    do {                                                       \
-        if (hipGetLastError() != hipSuccess) return BSPS_EDEVICE; \
+#define LAUNCH_OK()                                                    \
+    do {                                                               \
+        const hipError_t e_ = hipGetLastError();                       \
+        if (e_ != hipSuccess) return hip_fail(e_, "launch", __LINE__); \
     } while (0)
 
 inline u64 cdiv(u64 a, u64 b) { return (a + b - 1) / b; }
@@ -119,7 +133,8 @@ template <typename K>
 void carve_mwm(Carver& c, MwmBufs<K>& m, int G, int R, u64 n, u32 tavg) {
     m.G = G;
     m.R = R;
-    m.S = (u32)(n / tavg + (u64)G + 1);
+    // chunks of a group of N > cap keys: at most N / tavg + 2 (k_mwm_pick)
+    m.S = (u32)(n / tavg + 2 * (u64)G + 1);
     m.run_start = c.take<u32>((u64)G * R);
     m.run_len = c.take<u32>((u64)G * R);
     m.out_base = c.take<u32>(G);
@@ -157,6 +172,20 @@ int device_cus() {
             cus = 256;
     }
     return cus;
+}
+
+// Per-key rank launch: every tile once, with at most as many workgroups as
+// are resident at the same time (the kernel walks tiles with a stride).
+template <typename K, bool LEARNED>
+bsps_status launch_rank(const K* B, i64 n, int p, const K* spk, const u32* spp, int dt, const void* model,
+                        u32* bucket, u32* counts, unsigned long long* lstats, hipStream_t st) {
+    typedef RankShape<LEARNED> RS;
+    const int tpb = (int)cdiv(cdiv((u64)n, (u64)p), (u64)rank_tile<LEARNED>());
+    const u32 grid = (u32)std::max<i64>(1, std::min<i64>((i64)p * tpb, (i64)device_cus() * RS::WG_PER_CU));
+    hipLaunchKernelGGL((k_rank<K, LEARNED>), dim3(grid), dim3(RS::NT), 0, st, B, n, p, tpb, spk, spp, dt, model,
+                       bucket, counts, lstats);
+    LAUNCH_OK();
+    return BSPS_OK;
 }
 
 template <typename K, bool HASV>
@@ -293,14 +322,21 @@ bsps_status fit_model(const K* smp, i64 N, int dt, int p, int s, int L, int iter
         LAUNCH_OK();
         hipLaunchKernelGGL(k_model_ranges, dim3(gM), dim3(256), 0, st, f.leafid, N, nmod, f.lo);
         LAUNCH_OK();
-        hipLaunchKernelGGL(k_model_centres, dim3(gM), dim3(256), 0, st, f.x, f.lo, nmod, model, stage);
+        if (stage == 0)
+            hipLaunchKernelGGL(k_model_centres<1024>, dim3(1), dim3(1024), 0, st, f.x, f.lo, nmod, model, stage);
+        else
+            hipLaunchKernelGGL(k_model_centres<64>, dim3(nmod), dim3(64), 0, st, f.x, f.lo, nmod, model, stage);
         LAUNCH_OK();
         for (int it = 0; it < iters; it++) {
             hipLaunchKernelGGL(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, f.leafid, N, p, s,
                                (const void*)model, stage, f.r);
             LAUNCH_OK();
-            hipLaunchKernelGGL(k_model_backward, dim3(gM), dim3(256), 0, st, f.x, f.r, f.lo, nmod, N,
-                               (const void*)model, stage, f.g, f.hs, f.lossp);
+            if (stage == 0)
+                hipLaunchKernelGGL(k_model_backward<1024>, dim3(1), dim3(1024), 0, st, f.x, f.r, f.lo, nmod, N,
+                                   (const void*)model, stage, f.g, f.hs, f.lossp);
+            else
+                hipLaunchKernelGGL(k_model_backward<64>, dim3(nmod), dim3(64), 0, st, f.x, f.r, f.lo, nmod, N,
+                                   (const void*)model, stage, f.g, f.hs, f.lossp);
             LAUNCH_OK();
             hipLaunchKernelGGL(k_model_update, dim3(gM), dim3(256), 0, st, f.g, f.hs, f.lo, nmod, p, s, model,
                                stage);
@@ -417,7 +453,7 @@ bsps_status validate(i64 n, int dtype, const bsps_params* prm) {
     if (prm->variant != BSPS_DET && prm->variant != BSPS_RAN) return BSPS_EINVAL;
     if (prm->route != BSPS_ROUTE_FUSED && prm->route != BSPS_ROUTE_SCATTER) return BSPS_EINVAL;
     if (prm->bucketing != BSPS_SPLITTER && prm->bucketing != BSPS_LEARNED) return BSPS_EINVAL;
-    if (prm->leaves < 0 || prm->chunk_cap < 0) return BSPS_EINVAL;
+    if (prm->leaves < 0 || prm->leaves > MAX_LEAVES || prm->chunk_cap < 0) return BSPS_EINVAL;
     for (int i = 0; i < 7; i++)
         if (prm->reserved[i]) return BSPS_EINVAL;
     if (prm->variant == BSPS_RAN && (i64)prm->s * prm->p - 1 > n) return BSPS_EINVAL;
@@ -450,7 +486,7 @@ bsps_status d2h(void* host, const void* dev, size_t bytes, hipStream_t st) {
     if (!host || bytes == 0) return BSPS_OK;
     constexpr size_t CH = (size_t)8 << 20;
     void* pin = nullptr;
-    if (hipHostMalloc(&pin, std::min(bytes, CH), hipHostMallocDefault) != hipSuccess) return BSPS_EDEVICE;
+    HIP_OK(hipHostMalloc(&pin, std::min(bytes, CH), hipHostMallocDefault));
     bsps_status rc = BSPS_OK;
     for (size_t off = 0; off < bytes; off += CH) {
         const size_t b = std::min(CH, bytes - off);
@@ -576,26 +612,23 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         }
     } else {
         // A4: every key ranked on its own (splitter search or learned model).
-        const int tpbr = (int)cdiv(cdiv((u64)n, (u64)p), RANK_TILE);
         {
             StageScope sc(ST_COUNT, st);
             if (prm->bucketing == BSPS_LEARNED) {
                 const int L = prm->leaves > 0 ? prm->leaves : 4096;
-                rc = fit_model<K>(P.ssk, ns, BSPS_DT_NONE, p, s, L, 2, P.model, P.fitws, st);
+                // one Newton step per stage: the loss of each linear model is quadratic
+                rc = fit_model<K>(P.ssk, ns, BSPS_DT_NONE, p, s, L, 1, P.model, P.fitws, st);
                 if (rc) return rc;
             }
             hipLaunchKernelGGL(k_zero_u32, dim3((u32)cdiv((u64)p * p + 4, 256)), dim3(256), 0, st, P.C, p * p + 4);
             LAUNCH_OK();
             StageScope sk(ST_RANK_K, st);
             if (prm->bucketing == BSPS_LEARNED)
-                hipLaunchKernelGGL((k_rank<K, true>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, st, P.B, n, p, tpbr,
-                                   P.pk, P.pp, BSPS_DT_NONE, (const void*)P.model, P.bucket, P.C,
-                                   (unsigned long long*)(P.C + (size_t)p * p));
+                rc = launch_rank<K, true>(P.B, n, p, P.pk, P.pp, BSPS_DT_NONE, P.model, P.bucket, P.C,
+                                          (unsigned long long*)(P.C + (size_t)p * p), st);
             else
-                hipLaunchKernelGGL((k_rank<K, false>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, st, P.B, n, p, tpbr,
-                                   P.pk, P.pp, BSPS_DT_NONE, (const void*)nullptr, P.bucket, P.C,
-                                   (unsigned long long*)nullptr);
-            LAUNCH_OK();
+                rc = launch_rank<K, false>(P.B, n, p, P.pk, P.pp, BSPS_DT_NONE, nullptr, P.bucket, P.C, nullptr, st);
+            if (rc) return rc;
         }
         // A5: the p independent prefix computations, then routing into Z (= A).
         {
@@ -643,12 +676,12 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         std::vector<u32> ct((size_t)(p + 1) * p);
         rc = d2h(ct.data(), P.cntT, 4 * ct.size(), st);
         if (rc) return rc;
-        u32 ctr[2];
-        rc = d2h(ctr, P.bm.counters, 8, st);
+        u32 ctr[4];
+        rc = d2h(ctr, P.bm.counters, 16, st);
         if (rc) return rc;
-        u32 ctr2[2] = {0, 0};
+        u32 ctr2[4] = {0, 0, 0, 0};
         if (P.bs.tpb > 1) {
-            rc = d2h(ctr2, P.bs.mwm.counters, 8, st);
+            rc = d2h(ctr2, P.bs.mwm.counters, 16, st);
             if (rc) return rc;
         }
         double mx = 0;
@@ -664,6 +697,9 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         }
         stats->max_bucket_ratio = mx / ((double)n / p);
         stats->oversize_chunks = (i64)ctr[1] + (i64)ctr2[1];
+        stats->reserved_i[0] = ctr2[1];                            // block merge
+        stats->reserved_i[1] = ctr[1];                             // bucket merge
+        stats->reserved_i[2] = (i64)std::max(ctr[3], ctr2[3]);     // largest oversize chunk
         if (prm->route == BSPS_ROUTE_SCATTER && prm->bucketing == BSPS_LEARNED) {
             unsigned long long ls[2];
             rc = d2h(ls, P.C + (size_t)p * p, 16, st);
@@ -955,18 +991,22 @@ struct TableStage {
 TableStage g_tstage;
 
 bsps_status table_stage(size_t bytes, char** out) {
-    if (g_tstage.done && hipEventSynchronize(g_tstage.done) != hipSuccess) return BSPS_EDEVICE;
-    if (!g_tstage.done && hipEventCreateWithFlags(&g_tstage.done, hipEventDisableTiming) != hipSuccess) {
-        g_tstage.done = nullptr;
-        return BSPS_EDEVICE;
+    if (g_tstage.done) HIP_OK(hipEventSynchronize(g_tstage.done));
+    if (!g_tstage.done) {
+        const hipError_t e = hipEventCreateWithFlags(&g_tstage.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            g_tstage.done = nullptr;
+            return hip_fail(e, "hipEventCreateWithFlags", __LINE__);
+        }
     }
     if (g_tstage.cap < bytes) {
-        if (g_tstage.p && hipHostFree(g_tstage.p) != hipSuccess) return BSPS_EDEVICE;
+        if (g_tstage.p) HIP_OK(hipHostFree(g_tstage.p));
         g_tstage.p = nullptr;
         g_tstage.cap = 0;
-        if (hipHostMalloc(&g_tstage.p, bytes, hipHostMallocDefault) != hipSuccess) {
+        const hipError_t e = hipHostMalloc(&g_tstage.p, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
             g_tstage.p = nullptr;
-            return BSPS_EDEVICE;
+            return hip_fail(e, "hipHostMalloc", __LINE__);
         }
         g_tstage.cap = bytes;
     }
@@ -1025,6 +1065,7 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
         HIP_OK(hipEventRecord(g_tstage.done, st));
     }
     // capture every launch into one graph (on a private stream), launch it once
+    (void)device_cus();  // device queries stay outside the graph capture
     const bool timed = g_timer.on;
     bool launched = false;
     if (!timed && getenv("BSPS_NO_GRAPH") == nullptr) {
@@ -1040,10 +1081,15 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
             if (g_graphs.cap && hipStreamBeginCapture(g_graphs.cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
                 const bsps_status erc = enqueue_segmented<K, HASV>(P, b, (K*)keys, vals, dt, o, g_graphs.cap);
                 const hipError_t ec = hipStreamEndCapture(g_graphs.cap, &graph);
+                hipError_t ei = hipErrorUnknown;
                 if (erc == BSPS_OK && ec == hipSuccess && graph &&
-                    hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+                    (ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) == hipSuccess) {
                     g_graphs.execs[key] = exec;
                 } else {
+                    if (debug_on())
+                        std::fprintf(stderr, "[bsps] graph capture not used (enqueue %d, end capture %s, "
+                                     "instantiate %s); running eagerly\n", (int)erc, hipGetErrorString(ec),
+                                     hipGetErrorString(ei));
                     exec = nullptr;
                 }
                 if (graph) (void)hipGraphDestroy(graph);
@@ -1145,31 +1191,27 @@ bsps_status bsps_rank(const void* keys, int64_t n, int32_t dtype, int32_t p, con
         hipLaunchKernelGGL(k_zero_u32, dim3((u32)cdiv((u64)p * p, 256)), dim3(256), 0, s, out_counts, p * p);
         LAUNCH_OK();
     }
-    const int tpbr = (int)cdiv(cdiv((u64)n, (u64)p), RANK_TILE);
     {
         StageScope sc(ST_RANK_K, s);
         // keys and splitters arrive in dtype form; the kernel maps both to order keys
+        bsps_status rc;
         if (dtype == BSPS_I64) {
             if (bucketing == BSPS_LEARNED)
-                hipLaunchKernelGGL((k_rank<u64, true>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, s,
-                                   (const u64*)keys, n, p, tpbr, (const u64*)spl_keys, spl_pos, dtype, model,
-                                   out_bucket, out_counts, lst);
+                rc = launch_rank<u64, true>((const u64*)keys, n, p, (const u64*)spl_keys, spl_pos, dtype, model,
+                                            out_bucket, out_counts, lst, s);
             else
-                hipLaunchKernelGGL((k_rank<u64, false>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, s,
-                                   (const u64*)keys, n, p, tpbr, (const u64*)spl_keys, spl_pos, dtype, model,
-                                   out_bucket, out_counts, lst);
+                rc = launch_rank<u64, false>((const u64*)keys, n, p, (const u64*)spl_keys, spl_pos, dtype, model,
+                                             out_bucket, out_counts, lst, s);
         } else {
             if (bucketing == BSPS_LEARNED)
-                hipLaunchKernelGGL((k_rank<u32, true>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, s,
-                                   (const u32*)keys, n, p, tpbr, (const u32*)spl_keys, spl_pos, dtype, model,
-                                   out_bucket, out_counts, lst);
+                rc = launch_rank<u32, true>((const u32*)keys, n, p, (const u32*)spl_keys, spl_pos, dtype, model,
+                                            out_bucket, out_counts, lst, s);
             else
-                hipLaunchKernelGGL((k_rank<u32, false>), dim3((u32)(p * tpbr)), dim3(RANK_NT), 0, s,
-                                   (const u32*)keys, n, p, tpbr, (const u32*)spl_keys, spl_pos, dtype, model,
-                                   out_bucket, out_counts, lst);
+                rc = launch_rank<u32, false>((const u32*)keys, n, p, (const u32*)spl_keys, spl_pos, dtype, model,
+                                             out_bucket, out_counts, lst, s);
         }
+        if (rc) return rc;
     }
-    LAUNCH_OK();
     if (st) {
         unsigned long long h[2];
         const bsps_status rc = d2h(h, lst, 16, s);
@@ -1182,7 +1224,7 @@ bsps_status bsps_rank(const void* keys, int64_t n, int32_t dtype, int32_t p, con
 
 bsps_status bsps_fit_model(const void* smp_keys, int64_t N, int32_t dtype, int32_t p, int32_t s, int32_t leaves,
                            int32_t iters, void* model, void* ws, size_t ws_bytes, void* stream) {
-    if (N < 1 || p < 1 || s < 1 || leaves < 1 || leaves > 4096 || iters < 1 || dtype < 0 || dtype > 2 ||
+    if (N < 1 || p < 1 || s < 1 || leaves < 1 || leaves > MAX_LEAVES || iters < 1 || dtype < 0 || dtype > 2 ||
         !smp_keys || !model)
         return BSPS_EINVAL;
     if (!ws || ws_bytes < bsps_fit_workspace_bytes(N, leaves)) return BSPS_EWORKSPACE;
@@ -1194,7 +1236,7 @@ bsps_status bsps_fit_model(const void* smp_keys, int64_t N, int32_t dtype, int32
 bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int32_t p, int32_t s, int32_t leaves,
                             const void* model, int32_t* out_leaf, float* out_grad, float* out_gram, float* out_loss,
                             void* ws, size_t ws_bytes, void* stream) {
-    if (N < 1 || p < 1 || s < 1 || leaves < 1 || leaves > 4096 || dtype < 0 || dtype > 2 || !smp_keys || !model ||
+    if (N < 1 || p < 1 || s < 1 || leaves < 1 || leaves > MAX_LEAVES || dtype < 0 || dtype > 2 || !smp_keys || !model ||
         !out_leaf || !out_grad || !out_gram || !out_loss)
         return BSPS_EINVAL;
     if (!ws || ws_bytes < bsps_fit_workspace_bytes(N, leaves)) return BSPS_EWORKSPACE;
@@ -1214,10 +1256,10 @@ bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int3
     LAUNCH_OK();
     hipLaunchKernelGGL(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, out_leaf, N, p, s, model, 1, f.r);
     LAUNCH_OK();
-    hipLaunchKernelGGL(k_model_backward, dim3(gM), dim3(256), 0, st, f.x, f.r, f.lo, leaves, N, model, 1, out_grad,
-                       out_gram, f.lossp);
+    hipLaunchKernelGGL(k_model_backward<64>, dim3(leaves), dim3(64), 0, st, f.x, f.r, f.lo, leaves, N, model, 1,
+                       out_grad, out_gram, f.lossp);
     LAUNCH_OK();
-    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(64), 0, st, f.lossp, leaves, N, out_loss);
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, f.lossp, leaves, N, out_loss);
     LAUNCH_OK();
     return BSPS_OK;
 }
@@ -1232,11 +1274,11 @@ size_t bsps_segmented_workspace_bytes(const int64_t* h_offsets, int32_t nseg, in
     Carver c(nullptr);
     if (dtype == BSPS_I64) {
         if (make_seg_plan<u64>(h_offsets, nseg, tu, P) != BSPS_OK) return 0;
-        SegBufs<u64> b;
+        SegBufs<u64> b{};
         return carve_seg<u64>(c, P, with_values != 0, b, opts_for<u64>(&dp).tavg);
     }
     if (make_seg_plan<u32>(h_offsets, nseg, tu, P) != BSPS_OK) return 0;
-    SegBufs<u32> b;
+    SegBufs<u32> b{};
     return carve_seg<u32>(c, P, with_values != 0, b, opts_for<u32>(&dp).tavg);
 }
 

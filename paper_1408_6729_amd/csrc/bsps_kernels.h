@@ -26,6 +26,10 @@
 
 constexpr int MAXR = 1024;  // runs per merge group (tiles per block, or p)
 
+#ifndef BSPS_GATHER_LDS
+#define BSPS_GATHER_LDS 1  // merge gather through LDS-staged, position-striped loads
+#endif
+
 #ifdef BSPS_TIMING
 // Per-phase cycle sums of the merge kernel: [0, 8) merges that emit output
 // samples (block merges), [8, 16) the others (bucket merges).
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     u32 totN;
     (void)block_excl_scan<NT>(myn, totN, sm.wsum);
     const u32 Sraw = totS, N = totN;
-    u32 nb = 0, f = 1, Sg = 0, q = 1;
+    u32 nb = 0, f = 1, Sg = 0, q = 1, dsh = 0;
     if (N > a.cap && Sraw > 0) {
         f = (Sraw + T - 1) / T;
         Sg = Sraw / f;
@@ -290,12 +294,23 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
         u32 tg = tgf < (float)a.tavg ? a.tavg : (u32)tgf;
         u64 qq = ((u64)tg * Sg + N - 1) / N;
         q = qq < 1 ? 1u : (u32)qq;
-        nb = Sg / q;
+        // The keys at or below a boundary include, in every run, the keys
+        // after its last subsample at or below it: about half a subsample
+        // spacing (f samples of stride ys) per run. That offset cancels
+        // between consecutive boundaries but not in the first chunk, so all
+        // boundaries move down by it (in subsample ranks, at most q - 1).
+        // Symmetrically every run ends with about half a spacing of keys
+        // after its last subsample, which the last chunk holds: the boundary
+        // count covers Sg + dsh ranks so that those keys are not left over.
+        const float ys = (float)(sd[3] ? sd[3] : 1u);
+        const float off = 0.5f * (float)R * (float)f * ys / yeff;
+        dsh = off >= (float)(q - 1) ? q - 1 : (u32)off;
+        nb = (Sg + dsh) / q;
     }
     if (t == 0) {
         u32 slots = N > 0 ? nb + 1 : 0;
         u32 b = slots ? atomicAdd(a.slot_count, slots) : 0u;
-        if (b + slots > a.S) { slots = 0; b = a.S; }  // cannot happen: capacity n/tavg + G
+        if (b + slots > a.S) { slots = 0; b = a.S; }  // cannot happen: capacity n/tavg + 2G + 1
         sh_base = b;
         sh_nb = slots ? nb : 0u;
         a.grp_base[g] = b;
@@ -348,12 +363,12 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
         for (int j = 0; j < IT; j++) key[j] = (K)vex[padi(t * IT + j)] + mn;
     }
     wg_scatter_vals<NT, IT>(v, rank, vex);
-    // boundary b (1..nb) = sorted element b*q - 1
+    // boundary b (1..nb) = sorted element b*q - 1 - dsh
 #pragma unroll
     for (int j = 0; j < IT; j++) {
         const u32 i = (u32)(t * IT + j);
-        if (i < Sg && (i + 1) % q == 0 && (i + 1) / q <= nb) {
-            const u32 b = (i + 1) / q;
+        if (i < Sg && (i + 1 + dsh) % q == 0 && (i + 1 + dsh) / q <= nb) {
+            const u32 b = (i + 1 + dsh) / q;
             const u32 c = vex[padi((int)i)];
             int lo = 0, hi = R;
             while (hi - lo > 1) {
@@ -586,17 +601,104 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     if (N == 0) return;
     PHASE(0);
     if (N > a.cap) {
-        if (t == 0) atomicAdd(a.oversize, 1u);
+        if (t == 0) {
+            atomicAdd(a.oversize, 1u);
+            atomicMax(a.oversize + 2, N);  // largest oversize chunk (counters[3])
+        }
         mwm_oversize<K, HASV>(a, g, slot, c, nb, ppre, N, out, sm, exch);
         return;
     }
     PHASE(1);
-    // blocked gather: thread t loads chunk positions t*IT .. t*IT+IT-1, walking
-    // the pieces from the one that holds its first position
+    // gather: thread t owns chunk positions t*IT .. t*IT+IT-1 (blocked order,
+    // which the stable sort needs), walking the pieces from the one that holds
+    // its first position
     const u32 i0 = (u32)(t * IT);
     K kr[IT];
     u32 v[IT], rank[IT];
     K mn = KeyMax<K>::v, mx = 0;
+#if BSPS_GATHER_LDS
+    // Every position's source index is written to LDS piece by piece; the
+    // loads are then issued position-striped (consecutive lanes read
+    // consecutive keys of a piece, coalesced) and the keys are turned back
+    // into blocked order through LDS.
+    {
+        u32* srcidx = sm.template ex<u32>();
+        if (N >= 64u * (u32)R) {
+            // long pieces: each wave fills the positions of its pieces
+            const int lane = t & 63, w = t >> 6;
+            for (int r = w; r < R; r += NT / 64) {
+                const u32 p0 = ppre[r], len = ppre[r + 1] - p0, s0 = soff[r];
+                for (u32 i = lane; i < len; i += 64) srcidx[padi((int)(p0 + i))] = s0 + i;
+            }
+        } else if (i0 < N) {
+            // short pieces: each thread walks its own positions from the piece
+            // that holds its first one
+            u32 lo = 0, hi = (u32)R - 1;
+            while (lo < hi) {
+                const u32 mid = (lo + hi + 1) >> 1;
+                if (ppre[mid] <= i0) lo = mid; else hi = mid - 1;
+            }
+            u32 r = lo, nxt = ppre[lo + 1], sb = soff[lo] - ppre[lo];
+#pragma unroll
+            for (int j = 0; j < IT; j++) {
+                const u32 i = i0 + j;
+                if (i < N) {
+                    while (i >= nxt) {
+                        r++;
+                        nxt = ppre[r + 1];
+                        sb = soff[r] - ppre[r];
+                    }
+                    srcidx[padi((int)i)] = sb + i;
+                }
+            }
+        }
+        __syncthreads();
+        K ks[IT];
+        u32 vs[IT];
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            const u32 i = (u32)(j * NT + t);
+            ks[j] = 0;
+            vs[j] = 0;
+            if (i < N) {
+                const u32 si = srcidx[padi((int)i)];
+                ks[j] = a.src[si];
+                if (HASV) vs[j] = a.srcv[si];
+            }
+        }
+        __syncthreads();
+        K* exk = sm.template ex<K>();
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            const u32 i = (u32)(j * NT + t);
+            if (i < N) exk[padi((int)i)] = ks[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            kr[j] = i0 + j < N ? exk[padi((int)(i0 + j))] : (K)0;
+            if (i0 + j < N) {
+                mn = kr[j] < mn ? kr[j] : mn;
+                mx = kr[j] > mx ? kr[j] : mx;
+            }
+        }
+        if (HASV) {
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < IT; j++) {
+                const u32 i = (u32)(j * NT + t);
+                if (i < N) srcidx[padi((int)i)] = vs[j];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < IT; j++) v[j] = i0 + j < N ? srcidx[padi((int)(i0 + j))] : 0u;
+        } else {
+#pragma unroll
+            for (int j = 0; j < IT; j++) v[j] = 0;
+        }
+        __syncthreads();
+    }
+#else
     if (i0 < N) {
         u32 lo = 0, hi = (u32)R - 1;  // largest piece r with ppre[r] <= i0 (a nonempty one)
         while (lo < hi) {
@@ -630,6 +732,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
 #pragma unroll
         for (int j = 0; j < IT; j++) { kr[j] = 0; v[j] = 0; }
     }
+#endif
     block_minmax<NT, K>(mn, mx, sm.red64);
     PHASE(2);
     const int nbits = bitwidth64((u64)(mx - mn));

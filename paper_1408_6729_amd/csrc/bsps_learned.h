@@ -39,24 +39,36 @@ __device__ __forceinline__ float model_x(K u, const ModelHdr& h) {
     return d * h.inv;
 }
 
+// 4-byte keys: the offset from lo in 32-bit integer arithmetic (exact), then
+// one conversion; training and inference use the same function.
+template <>
+__device__ __forceinline__ float model_x<u32>(u32 u, const ModelHdr& h) {
+    const u32 lo = (u32)h.lo;
+    const float d = u >= lo ? (float)(u - lo) : -(float)(lo - u);
+    return d * h.inv;
+}
+
 __device__ __forceinline__ int model_leaf(float x, const ModelHdr& h) {
     float r = (h.a * (x - h.mur) + h.b) * (float)h.L;
     r = fminf(fmaxf(r, 0.0f), (float)(h.L - 1));
     return (int)r;
 }
 
-__device__ __forceinline__ int model_bucket(float x, int l, const float* leaf, int p) {
-    float f = leaf[3 * l] * (x - leaf[3 * l + 2]) + leaf[3 * l + 1];
-    f = fminf(fmaxf(f * (float)p, 0.0f), (float)(p - 1));
-    return (int)f;
-}
 
 // ---------------------------------------------------------------- per-key rank
 
 // One workgroup per RANK_TILE keys of one block: bucket of every key, the
 // block's row of the count matrix (atomics), and for the learned model the
 // number of corrected predictions and their total distance.
-constexpr int RANK_NT = 256, RANK_IT = 16, RANK_TILE = RANK_NT * RANK_IT;
+// Splitter search: 256-thread workgroups (12 KB of LDS, 8 per CU). Learned:
+// 1024-thread workgroups that also hold the leaf table (32 KB), 2 per CU.
+// A tile is 32 keys per thread of one block.
+constexpr int RANK_IT = 32;
+constexpr int MAX_LEAVES = 4096;
+template <bool LEARNED> struct RankShape;
+template <> struct RankShape<false> { static constexpr int NT = 256, WG_PER_CU = 8; };
+template <> struct RankShape<true> { static constexpr int NT = 1024, WG_PER_CU = 2; };
+template <bool LEARNED> constexpr int rank_tile() { return RankShape<LEARNED>::NT * RANK_IT; }
 
 // ---------------------------------------------------------------- training
 
@@ -109,15 +121,37 @@ __device__ __forceinline__ float* stage_params(void* model, int stage) {
     return stage == 0 ? &h->a : (float*)(h + 1);
 }
 
+// Sum over the workgroup (NTR threads, a multiple of 64); every thread gets
+// the total. red: NTR/64 floats of LDS.
+template <int NTR>
+__device__ __forceinline__ float wg_sum(float v, float* red) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (NTR == 64) return v;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    float acc = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NTR / 64; i++) acc += red[i];
+    return acc;
+}
+
 // Leaf centres mu = mean x over each leaf's samples (0 for an empty leaf);
-// parameters start at zero.
-__global__ void k_model_centres(const float* x, const int32_t* lo, int nmod, void* model, int stage) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+// parameters start at zero. One workgroup of NTR threads per model.
+template <int NTR>
+__global__ __launch_bounds__(NTR) void k_model_centres(const float* x, const int32_t* lo, int nmod, void* model,
+                                                         int stage) {
+    __shared__ float red[NTR / 64];
+    const int l = blockIdx.x;
     if (l >= nmod) return;
     float* q = stage_params(model, stage);
     const int32_t a = lo[l], b = lo[l + 1];
     float sx = 0.0f;
-    for (int32_t t = a; t < b; t++) sx += x[t];
+    for (int32_t t = a + (int32_t)threadIdx.x; t < b; t += NTR) sx += x[t];
+    sx = wg_sum<NTR>(sx, red);
+    if (threadIdx.x != 0) return;
     const float mu = b > a ? sx / (float)(b - a) : 0.0f;
     if (stage == 0) {
         q[0] = 0.0f; q[1] = 0.0f; q[2] = mu;   // a, b, mu_r
@@ -143,19 +177,23 @@ __global__ void k_model_forward(const float* x, const int32_t* leafid, i64 N, in
     r[t] = c * (x[t] - mu) + d - y;
 }
 
-// Backward: per model, gradient of the loss and the Gram sums (all times 2/N),
-// summed in sample order: g = (sum r dx, sum r), h = (sum dx^2, sum dx, count),
-// dx = x - mu; also the model's share of the loss sum r^2.
-__global__ void k_model_backward(const float* x, const float* r, const int32_t* lo, int nmod, i64 N,
-                                 const void* model, int stage, float* g, float* hs, float* lossp) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+// Backward: per model, gradient of the loss and the Gram sums (all times 2/N):
+// g = (sum r dx, sum r), h = (sum dx^2, sum dx, count), dx = x - mu; also the
+// model's share of the loss sum r^2. One workgroup of NTR threads per model,
+// partial sums per thread then a tree over the workgroup.
+template <int NTR>
+__global__ __launch_bounds__(NTR) void k_model_backward(const float* x, const float* r, const int32_t* lo, int nmod,
+                                                          i64 N, const void* model, int stage, float* g, float* hs,
+                                                          float* lossp) {
+    __shared__ float red[NTR / 64];
+    const int l = blockIdx.x;
     if (l >= nmod) return;
     const float* q = stage_params(const_cast<void*>(model), stage);
     float c, d, mu;
     stage_get(q, stage, l, c, d, mu);
     float s_rx = 0, s_r = 0, s_xx = 0, s_x = 0, s_rr = 0;
     const int32_t a = lo[l], b = lo[l + 1];
-    for (int32_t t = a; t < b; t++) {
+    for (int32_t t = a + (int32_t)threadIdx.x; t < b; t += NTR) {
         const float dx = x[t] - mu, rv = r[t];
         s_rx += rv * dx;
         s_r += rv;
@@ -163,6 +201,12 @@ __global__ void k_model_backward(const float* x, const float* r, const int32_t* 
         s_x += dx;
         s_rr += rv * rv;
     }
+    s_rx = wg_sum<NTR>(s_rx, red);
+    s_r = wg_sum<NTR>(s_r, red);
+    s_xx = wg_sum<NTR>(s_xx, red);
+    s_x = wg_sum<NTR>(s_x, red);
+    s_rr = wg_sum<NTR>(s_rr, red);
+    if (threadIdx.x != 0) return;
     const float sc = N > 0 ? 2.0f / (float)N : 0.0f;
     g[2 * l] = s_rx * sc;
     g[2 * l + 1] = s_r * sc;
@@ -198,90 +242,139 @@ __global__ void k_model_update(const float* g, const float* hs, const int32_t* l
 }
 
 // Root fitted: copy (a, b, mu_r) stays in the header; nothing else to do.
-__global__ void k_sum_loss(const float* lossp, int nmod, i64 N, float* out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    float acc = 0;
-    for (int l = 0; l < nmod; l++) acc += lossp[l];
-    *out = N > 0 ? acc / (float)N : 0.0f;
+// Loss = (sum of the models' r^2 shares) / N; one workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_sum_loss(const float* lossp, int nmod, i64 N, float* out) {
+    __shared__ float red[4];
+    float acc = 0.0f;
+    for (int l = threadIdx.x; l < nmod; l += 256) acc += lossp[l];
+    acc = wg_sum<256>(acc, red);
+    if (threadIdx.x == 0) *out = N > 0 ? acc / (float)N : 0.0f;
 }
 
-// Keys and splitters of dtype dt (BSPS_DT_NONE: already order keys).
+// Splitter records in LDS, compared with a record (key, pos) by the tie rule.
+// 4-byte keys pack (key, pos) into one u64, so a comparison is one 64-bit
+// compare and one LDS read; 8-byte keys keep key and tag apart.
+template <typename K> struct SplitLds;
+template <>
+struct SplitLds<u32> {
+    u64 kp[MAXR];
+    typedef u64 Q;
+    __device__ __forceinline__ void set(int i, u32 k, u32 pos) { kp[i] = ((u64)k << 32) | pos; }
+    __device__ __forceinline__ void set_inf(int i) { kp[i] = ~0ull; }
+    __device__ __forceinline__ static Q query(u32 key, u32 pos) { return ((u64)key << 32) | pos; }
+    __device__ __forceinline__ bool lt(int i, Q q) const { return kp[i] < q; }  // S_i <_rec (key, pos)
+};
+template <>
+struct SplitLds<u64> {
+    u64 k[MAXR];
+    u32 ps[MAXR];
+    struct Q { u64 key; u32 pos; };
+    __device__ __forceinline__ void set(int i, u64 kk, u32 pos) { k[i] = kk; ps[i] = pos; }
+    __device__ __forceinline__ void set_inf(int i) { k[i] = ~0ull; ps[i] = 0xffffffffu; }
+    __device__ __forceinline__ static Q query(u64 key, u32 pos) { return Q{key, pos}; }
+    __device__ __forceinline__ bool lt(int i, Q q) const { return rec_lt<u64>(k[i], ps[i], q.key, q.pos); }
+};
+
+// Bucket of every key of the block-sorted array B and the count matrix.
+// Keys and splitters of dtype dt (BSPS_DT_NONE: already order keys). Tiles of
+// rank_tile() keys of one block; each workgroup loads the splitters (and the
+// learned model) once and walks tiles with a grid stride. Splitter
+// bucketing: branch-free binary search over the p - 1 records padded to a
+// power of two. Learned bucketing: root, then the leaf line held in LDS as
+// (c, d - c mu) so that f(x) = c x + (d - c mu), then the exact check against
+// the two neighbouring splitters, walking to the true bucket when the
+// prediction is off. Counts: lanes holding a run of equal buckets add its
+// length once.
 template <typename K, bool LEARNED>
-__global__ __launch_bounds__(RANK_NT) void k_rank(const K* B, i64 n, int p, int tpb, const K* spk,
-                                                      const u32* spp, int dt, const void* model, u32* bucket,
-                                                      u32* counts, unsigned long long* lstats) {
-    __shared__ K sk[MAXR];
-    __shared__ u32 sp[MAXR];
+__global__ __launch_bounds__(RankShape<LEARNED>::NT) void k_rank(const K* B, i64 n, int p, int tpb, const K* spk,
+                                                                     const u32* spp, int dt, const void* model,
+                                                                     u32* bucket, u32* counts,
+                                                                     unsigned long long* lstats) {
+    constexpr int NT = RankShape<LEARNED>::NT, TILE = NT * RANK_IT;
+    __shared__ SplitLds<K> S;
     __shared__ u32 hist[MAXR];
-    __shared__ float leaf[LEARNED ? 3 * 4096 : 1];
-    __shared__ ModelHdr mh;
+    __shared__ float2 lf2[LEARNED ? MAX_LEAVES : 1];
     __shared__ unsigned long long wst[2];
-    const int t = threadIdx.x;
-    const int k = blockIdx.x / tpb, tt = blockIdx.x % tpb;
-    const i64 st = (i64)(((u64)k * (u64)n) / (u64)p), en = (i64)(((u64)(k + 1) * (u64)n) / (u64)p);
-    const i64 base = st + (i64)tt * RANK_TILE;
-    const i64 cnt64 = en - base;
-    if (cnt64 <= 0) return;
-    const int cnt = cnt64 > RANK_TILE ? RANK_TILE : (int)cnt64;
+    const int t = threadIdx.x, lane = t & 63;
     int P2 = 1;
     while (P2 < p) P2 <<= 1;
-    for (int i = t; i < P2; i += RANK_NT) {
-        if (i < p - 1) {
-            sk[i] = okey<K>(spk[i], dt);
-            sp[i] = spp[i];
-        } else {
-            sk[i] = KeyMax<K>::v;
-            sp[i] = 0xffffffffu;
-        }
+    for (int i = t; i < P2; i += NT) {
+        if (i < p - 1) S.set(i, okey<K>(spk[i], dt), spp[i]);
+        else S.set_inf(i);
         if (i < p) hist[i] = 0;
     }
+    if (t == 0) wst[0] = wst[1] = 0;
+    ModelHdr mh;
     if (LEARNED) {
-        const ModelHdr* h = (const ModelHdr*)model;
-        if (t == 0) {
-            mh = *h;
-            wst[0] = wst[1] = 0;
+        mh = *(const ModelHdr*)model;
+        mh.L = mh.L < 1 ? 1 : (mh.L > MAX_LEAVES ? MAX_LEAVES : mh.L);  // leaf ids stay inside the table
+        const float* lf = (const float*)((const ModelHdr*)model + 1);
+        for (int l = t; l < mh.L; l += NT) {
+            const float c = lf[3 * l], d = lf[3 * l + 1], mu = lf[3 * l + 2];
+            lf2[l] = make_float2(c, d - c * mu);
         }
-        const float* lf = (const float*)(h + 1);
-        for (int i = t; i < 3 * h->L; i += RANK_NT) leaf[i] = lf[i];
     }
     __syncthreads();
     unsigned long long miss = 0, dist = 0;
+    const int ntile = p * tpb;
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        const int k = tile / tpb, tt = tile % tpb;
+        const i64 st = (i64)(((u64)k * (u64)n) / (u64)p), en = (i64)(((u64)(k + 1) * (u64)n) / (u64)p);
+        const i64 base = st + (i64)tt * TILE;
+        const i64 cnt64 = en - base;
+        const int cnt = cnt64 <= 0 ? 0 : (cnt64 > TILE ? TILE : (int)cnt64);
 #pragma unroll 4
-    for (int j = 0; j < RANK_IT; j++) {
-        const int i = j * RANK_NT + t;
-        if (i >= cnt) break;
-        const i64 g = base + i;
-        const K key = okey<K>(B[g], dt);
-        const u32 pos = (u32)g;
-        int b;
-        if (!LEARNED) {
-            b = 0;
-            for (int hstep = P2 >> 1; hstep >= 1; hstep >>= 1) {
-                const int q = b + hstep - 1;
-                b += rec_lt<K>(sk[q], sp[q], key, pos) ? hstep : 0;
+        for (int j = 0; j < RANK_IT; j++) {
+            if (j * NT + (t & ~63) >= cnt) break;  // the whole wave is past the tile's end
+            const int i = j * NT + t;
+            const bool valid = i < cnt;
+            const i64 g = base + i;
+            int b = p;
+            if (valid) {
+                const K key = okey<K>(B[g], dt);
+                const typename SplitLds<K>::Q q = SplitLds<K>::query(key, (u32)g);
+                if (!LEARNED) {
+                    b = 0;
+                    for (int h = P2 >> 1; h >= 1; h >>= 1) b += S.lt(b + h - 1, q) ? h : 0;
+                } else {
+                    const float x = model_x<K>(key, mh);
+                    const float2 ce = lf2[model_leaf(x, mh)];
+                    const float f = fminf(fmaxf((ce.x * x + ce.y) * (float)p, 0.0f), (float)(p - 1));
+                    const int pred = (int)f;
+                    b = pred;
+                    while (b > 0 && !S.lt(b - 1, q)) b--;
+                    while (b < p - 1 && S.lt(b, q)) b++;
+                    miss += b != pred;
+                    dist += (unsigned long long)(b > pred ? b - pred : pred - b);
+                }
+                if (bucket) bucket[g] = (u32)b;
             }
-        } else {
-            const float x = model_x<K>(key, mh);
-            const int pred = model_bucket(x, model_leaf(x, mh), leaf, p);
-            b = pred;
-            while (b > 0 && !rec_lt<K>(sk[b - 1], sp[b - 1], key, pos)) b--;
-            while (b < p - 1 && rec_lt<K>(sk[b], sp[b], key, pos)) b++;
-            miss += b != pred;
-            dist += (unsigned long long)(b > pred ? b - pred : pred - b);
+            const int bprev = __shfl_up(b, 1, 64);
+            const bool head = valid && (lane == 0 || bprev != b);
+            const unsigned long long bound = __ballot(head || !valid);
+            if (head) {
+                const unsigned long long above = lane == 63 ? 0ull : (bound >> (lane + 1));
+                const int len = above ? __ffsll((long long)above) : 64 - lane;
+                atomicAdd(&hist[b], (u32)len);
+            }
         }
-        if (bucket) bucket[g] = (u32)b;
-        atomicAdd(&hist[b], 1u);
+        __syncthreads();
+        for (int i = t; i < p; i += NT) {
+            const u32 h = hist[i];
+            if (h) {
+                if (counts) atomicAdd(&counts[(i64)k * p + i], h);
+                hist[i] = 0;
+            }
+        }
+        __syncthreads();
     }
     if (LEARNED) {
         atomicAdd(&wst[0], miss);
         atomicAdd(&wst[1], dist);
-    }
-    __syncthreads();
-    if (counts)
-        for (int i = t; i < p; i += RANK_NT)
-            if (hist[i]) atomicAdd(&counts[(i64)k * p + i], hist[i]);
-    if (LEARNED && t == 0 && lstats) {
-        atomicAdd(&lstats[0], wst[0]);
-        atomicAdd(&lstats[1], wst[1]);
+        __syncthreads();
+        if (t == 0 && lstats) {
+            atomicAdd(&lstats[0], wst[0]);
+            atomicAdd(&lstats[1], wst[1]);
+        }
     }
 }
