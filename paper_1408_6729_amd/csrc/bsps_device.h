@@ -65,7 +65,8 @@ __device__ __forceinline__ int bitwidth64(u64 v) { return v ? 64 - __clzll((long
 // ---------------------------------------------------------------- tile geometry
 
 // Workgroup sort shapes: 4-byte keys use 512 threads x 32 items (16K keys),
-// 8-byte keys use 256 threads x 32 items (8K keys).
+// 8-byte keys 512 threads x 16 items (8K keys: half the items per thread keep
+// the 64-bit keys, ranks and payloads in registers without spilling).
 template <typename K> struct Shape;
 #ifndef BSPS_NT32
 #define BSPS_NT32 512
@@ -74,7 +75,13 @@ template <typename K> struct Shape;
 #define BSPS_IT32 32
 #endif
 template <> struct Shape<u32> { static constexpr int NT = BSPS_NT32, IT = BSPS_IT32; };
-template <> struct Shape<u64> { static constexpr int NT = 256, IT = 32; };
+#ifndef BSPS_NT64
+#define BSPS_NT64 512
+#endif
+#ifndef BSPS_IT64
+#define BSPS_IT64 16
+#endif
+template <> struct Shape<u64> { static constexpr int NT = BSPS_NT64, IT = BSPS_IT64; };
 
 #ifndef BSPS_DIG_RECOMPUTE
 #define BSPS_DIG_RECOMPUTE 1  // recompute digits instead of keeping them in registers
@@ -93,10 +100,10 @@ __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }  // one pad 
 // time (ranking ends with a barrier before keys are scattered), so they share
 // one LDS region: `u` holds HALF*NT counter words or NT*IT exchange slots of
 // 8 bytes, whichever is larger, each with one pad word per 32.
-template <int NT, int KB> struct SortSmem {
+template <int NT, int KB, int IT> struct SortSmem {
     static constexpr int CNT = HALF * NT;
     static constexpr int CNTW = CNT + CNT / 32;
-    static constexpr int EXW = (NT * 32 + NT) * KB / 4;  // up to 32 items of KB bytes per thread
+    static constexpr int EXW = (NT * IT + NT * IT / 32) * KB / 4;  // IT items of KB bytes per thread, padded
     static constexpr int UW = CNTW > EXW ? CNTW : EXW;
     u32 u[UW];
     u32 wsum[NT / 64 + 2];

@@ -177,7 +177,7 @@ __device__ __forceinline__ void load_blocked(const T* p, int valid, T (&r)[IT]) 
 template <typename K, bool HASV>
 __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(TileArgs<K> a) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
-    __shared__ SortSmem<NT, (int)sizeof(K)> sm;
+    __shared__ SortSmem<NT, (int)sizeof(K), IT> sm;
     u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x;
     i64 base, cnt64, sbase = (i64)blockIdx.x * a.spt;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
 template <typename K>
 __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
-    __shared__ SortSmem<NT, (int)sizeof(K)> sm;
+    __shared__ SortSmem<NT, (int)sizeof(K), IT> sm;
     __shared__ u32 spre[MAXR + 1];
     __shared__ u32 sh_nb, sh_base;
     u32* vex = sm.template ex<u32>();
@@ -436,7 +436,7 @@ __device__ void mwm_emit(const MwmArgs<K>& a, u32 g, u32 o, K u, u32 gstart) {
 // digit passes alternating scr <-> dst; the last step writes dst.
 template <typename K, bool HASV>
 __device__ void mwm_oversize(const MwmArgs<K>& a, u32 g, u32 slot, u32 c, u32 nb, const u32* ppre, u32 N,
-                             u32 out, SortSmem<Shape<K>::NT, (int)sizeof(K)>& sm, K* exch) {
+                             u32 out, SortSmem<Shape<K>::NT, (int)sizeof(K), Shape<K>::IT>& sm, K* exch) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
     const int t = threadIdx.x, R = a.R;
     const int lane = t & 63, w = t >> 6, NW = NT / 64;
@@ -533,7 +533,7 @@ __device__ void mwm_oversize(const MwmArgs<K>& a, u32 g, u32 slot, u32 c, u32 nb
 template <typename K>
 struct MergeSmem {
     static constexpr int NT = Shape<K>::NT, T = NT * Shape<K>::IT;
-    SortSmem<NT, (int)sizeof(K)> sm;
+    SortSmem<NT, (int)sizeof(K), Shape<K>::IT> sm;
     u32 ppre[MAXR + 1];   // chunk offset of each piece
     u32 soff[MAXR];       // source position of each piece
     u32 slot;
