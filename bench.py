@@ -232,6 +232,9 @@ def bench_int64_kv(bsps, torch, W, args, timer):
 
 
 def bench_segmented(bsps, torch, W, args):
+    """The batch with the package's size-class table, learned bucketing on the
+    segments above 2^16 keys (as the table says) and, for comparison, with
+    splitter search everywhere."""
     import numpy as np
     log("segmented: generating 4096 segments")
     sizes = W.segment_sizes(4096, 8, 20)
@@ -240,30 +243,40 @@ def bench_segmented(bsps, torch, W, args):
     base = to_dev(torch, keys)
     K, Wm = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
     copies = torch.empty((K + Wm, n), dtype=torch.int32, device="cuda:0")
-    for i in range(K + Wm):
-        copies[i].copy_(base)
-    ws = torch.empty(bsps.segmented_workspace_bytes(offs, bsps.I32, False), dtype=torch.uint8, device="cuda:0")
-    for i in range(Wm):
-        bsps.sort_segmented_(copies[i], offs, workspace=ws)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K):
-        bsps.sort_segmented_(copies[Wm + i], offs, workspace=ws)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / K
-    st = bsps.sort_segmented_(copies[0].copy_(base), offs, workspace=ws, stats=True)
-    out = copies[Wm + K - 1]
-    # every segment sorted: no descent inside a segment
-    d = out[1:] < out[:-1]
-    cut = torch.zeros(n, dtype=torch.bool, device="cuda:0")
+    table = json.loads(bsps.default_tuning() or json.dumps(
+        {"classes": [{"max_log2": 14, "block": 16384, "s": 1}, {"max_log2": 17, "block": 16384, "s": 32},
+                     {"max_log2": 20, "block": 16384, "s": 16}, {"max_log2": 40, "block": 16384, "s": 8}]}))
     inner = torch.from_numpy(np.asarray(offs[1:-1], dtype=np.int64)).to("cuda:0")
+    cut = torch.zeros(n, dtype=torch.bool, device="cuda:0")
     cut[inner[(inner > 0) & (inner < n)]] = True
-    ok = not bool((d & ~cut[1:]).any().item())
-    log(f"segmented: {ms:.3f} ms, {n / ms / 1e6:.2f} Gkeys/s, sorted={ok}")
-    return {"workload": f"4096 int32 segments, log-uniform sizes in [2^8, 2^20], {n} keys; even segments "
-                        "uniform, odd 2^8-distinct", "ms": ms, "keys_per_s": n / (ms / 1e3), "segments_sorted": ok,
-            "steps": K, "graph": st["graph"], "blocks": st["blocks"], "merged_segments": st["merged_segments"],
-            "floor_fraction_6w": 6 * 4 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    res = {"workload": f"4096 int32 segments, log-uniform sizes in [2^8, 2^20], {n} keys; even segments "
+                       "uniform, odd 2^8-distinct", "steps": K, "tuning": table}
+    for name, lg in (("learned", 16), ("splitter", 40)):
+        tj = json.dumps(dict(table, learned_above_log2=lg))
+        for i in range(K + Wm):
+            copies[i].copy_(base)
+        ws = torch.empty(bsps.segmented_workspace_bytes(offs, bsps.I32, False, tj), dtype=torch.uint8,
+                         device="cuda:0")
+        for i in range(Wm):
+            bsps.sort_segmented_(copies[i], offs, tuning=tj, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(K):
+            bsps.sort_segmented_(copies[Wm + i], offs, tuning=tj, workspace=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / K
+        out = copies[Wm + K - 1]
+        ok = not bool(((out[1:] < out[:-1]) & ~cut[1:]).any().item())
+        st = bsps.sort_segmented_(copies[0].copy_(base), offs, tuning=tj, workspace=ws, stats=True)
+        e = {"ms": ms, "keys_per_s": n / (ms / 1e3), "segments_sorted": ok, "graph": st["graph"],
+             "blocks": st["blocks"], "merged_segments": st["merged_segments"],
+             "learned_segments": st["learned_segments"], "mispredict_rate": st["mispredict_rate"],
+             "floor_fraction_6w": 6 * 4 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+        res[name] = e
+        log(f"segmented/{name}: {ms:.3f} ms, {n / ms / 1e6:.2f} Gkeys/s, sorted={ok}, "
+            f"learned segments {e['learned_segments']}, mispredict {e['mispredict_rate']:.4f}")
+        del ws
+    return res
 
 
 def main():

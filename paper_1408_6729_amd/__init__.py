@@ -320,7 +320,8 @@ def sort_segmented_(keys, offsets, values=None, tuning: str | None = None, stats
         raise BspsError(code, "bsps_sort_segmented")
     if stats:
         return {"oversize_chunks": st.oversize_chunks, "blocks": st.reserved_i[0], "merged_segments": st.reserved_i[1],
-                "graph": bool(st.reserved_i[2])}
+                "graph": bool(st.reserved_i[2]), "learned_segments": st.reserved_i[3],
+                "mispredict_rate": st.mispredict_rate, "mean_fix_dist": st.mean_fix_dist}
     return None
 
 

@@ -740,12 +740,15 @@ struct TuneClass {
 };
 struct Tuning {
     std::vector<TuneClass> cls;
+    int learned_log2 = 16;  // segments of more than 2^learned_log2 keys use learned bucketing (>= 32: none)
 };
 
 const char* kTuningFormat =
     "{\"classes\": [{\"max_log2\": L, \"block\": B, \"s\": S}, ...]} with classes in ascending L; a segment of n "
     "keys uses the first class with n <= 2^L (the last class beyond). B: keys per virtual processor, "
-    "1 <= B <= tile (16384 for 4-byte keys, 8192 for int64); S >= 1 sample records per bucket.";
+    "1 <= B <= tile (16384 for 4-byte keys, 8192 for int64); S >= 1 sample records per bucket. Optional "
+    "\"learned_above_log2\": G (default 16): segments of more than 2^G keys that are split into blocks get "
+    "their bucket counts from a learned model of their sample (G >= 32: never).";
 
 // Built-in table (written by paper_1408_6729_amd/autotune.py on MI355X).
 Tuning default_tuning() {
@@ -762,6 +765,17 @@ bool parse_tuning(const char* js, Tuning& t) {
         return true;
     }
     const std::string s(js);
+    {
+        const size_t f = s.find("\"learned_above_log2\"");
+        if (f != std::string::npos) {
+            const size_t colon = s.find(':', f);
+            if (colon == std::string::npos) return false;
+            char* ep = nullptr;
+            const long v = strtol(s.c_str() + colon + 1, &ep, 10);
+            if (ep == s.c_str() + colon + 1 || v < 0 || v > 40) return false;
+            t.learned_log2 = (int)v;
+        }
+    }
     size_t pos = s.find("\"classes\"");
     if (pos == std::string::npos) return false;
     pos = s.find('[', pos);
@@ -797,8 +811,11 @@ bool parse_tuning(const char* js, Tuning& t) {
 
 struct SegPlan {
     int nseg = 0, NB = 0, nmerged = 0, nblocks_s = 0;
+    int NL = 0;   // large segments (learned bucketing)
+    u32 nls = 0;  // their sample records
     i64 n = 0;
     std::vector<u32> seg, soff, poff, coff, btab, dtab, btab_s;
+    std::vector<u32> lseg, lcs, lblk;
     std::vector<std::vector<u32>> gtab;  // per merge class
     std::vector<int> cls_R;
     std::vector<i64> cls_n;
@@ -847,6 +864,15 @@ bsps_status make_seg_plan(const int64_t* off, int nseg, const Tuning& tu, SegPla
         P.soff[i + 1] = P.soff[i] + (merged ? (u32)(p * s) : 0u);
         P.poff[i + 1] = P.poff[i] + (merged ? (u32)(p - 1) : 0u);
         P.coff[i + 1] = P.coff[i] + (merged ? (u32)((p + 1) * p) : 0u);
+        if (merged && tu.learned_log2 < 32 && n > ((i64)1 << tu.learned_log2)) {
+            d[5] = 1;
+            for (i64 k = 0; k < p; k++) {
+                P.lblk.push_back(d[4] + (u32)k);
+                P.lblk.push_back((u32)P.NL);
+            }
+            P.lseg.push_back((u32)i);
+            P.NL++;
+        }
         if (merged) {
             P.nmerged++;
             P.btab_s.push_back(P.soff[i]);
@@ -873,12 +899,25 @@ bsps_status make_seg_plan(const int64_t* off, int nseg, const Tuning& tu, SegPla
     }
     if (P.btab.empty()) P.btab.assign(4, 0);
     if (P.btab_s.empty()) P.btab_s.assign(4, 0);
+    P.lcs.assign(P.NL + 1, 0);
+    for (int j = 0; j < P.NL; j++) {
+        const u32 sg = P.lseg[j];
+        P.lcs[j + 1] = P.lcs[j] + (P.soff[sg + 1] - P.soff[sg]);
+    }
+    P.nls = P.lcs[P.NL];
+    if (P.lseg.empty()) P.lseg.assign(1, 0);
+    if (P.lblk.empty()) P.lblk.assign(2, 0);
     return BSPS_OK;
 }
 
 template <typename K>
 struct SegBufs {
     u32 *seg, *soff, *poff, *coff, *btab, *dtab, *btab_s;
+    u32 *lseg, *lcs, *lblk;           // learned bucketing tables
+    void* models;                     // learned models of the large segments
+    float *fx, *fr, *fg, *fhs;        // their training buffers
+    int32_t *fmid, *flo;
+    unsigned long long* lst;          // mispredictions, total correction distance
     std::vector<u32*> gtab;
     K *B, *A, *bsmp, *skey, *ssk, *pk;
     u32 *Bv, *Av, *spos, *ssp, *pp, *cntT;
@@ -899,6 +938,9 @@ size_t carve_seg(Carver& c, const SegPlan& P, bool hasv, SegBufs<K>& b, u32 tavg
     b.btab_s = c.take<u32>(P.btab_s.size());
     b.gtab.clear();
     for (auto& g : P.gtab) b.gtab.push_back(c.take<u32>(g.size()));
+    b.lseg = c.take<u32>(P.lseg.size());
+    b.lcs = c.take<u32>(P.lcs.size());
+    b.lblk = c.take<u32>(P.lblk.size());
     b.tables = c.base ? c.base + t0 : nullptr;
     b.tables_bytes = c.off - t0;
     const i64 n1 = std::max<i64>(1, P.n);
@@ -915,6 +957,17 @@ size_t carve_seg(Carver& c, const SegPlan& P, bool hasv, SegBufs<K>& b, u32 tavg
     b.pk = c.take<K>(std::max<u32>(1, P.poff.back()));
     b.pp = c.take<u32>(std::max<u32>(1, P.poff.back()));
     b.cntT = c.take<u32>(std::max<u32>(1, P.coff.back()));
+    {
+        const u64 nl = std::max(P.NL, 1), nls = std::max<u32>(P.nls, 1), nm = nl * SEG_LEAVES;
+        b.models = c.take<char>(nl * SEG_MODEL_BYTES);
+        b.fx = c.take<float>(nls);
+        b.fr = c.take<float>(nls);
+        b.fmid = c.take<int32_t>(nls);
+        b.flo = c.take<int32_t>(nm + 2);
+        b.fg = c.take<float>(2 * nm);
+        b.fhs = c.take<float>(3 * nm);
+        b.lst = c.take<unsigned long long>(2);
+    }
     b.mw.assign(P.cls_R.size(), MwmBufs<K>());
     for (size_t q = 0; q < P.cls_R.size(); q++)
         carve_mwm<K>(c, b.mw[q], (int)(P.gtab[q].size() / 2), P.cls_R[q], (u64)P.cls_n[q], tavg);
@@ -961,6 +1014,39 @@ bsps_status enqueue_segmented(const SegPlan& P, const SegBufs<K>& b, K* io, u32*
         hipLaunchKernelGGL((k_seg_count<K>), dim3((u32)cdiv(nc, 256)), dim3(256), 0, st, b.B, b.seg, b.poff, b.coff,
                            P.nseg, b.pk, b.pp, b.cntT);
         LAUNCH_OK();
+        if (P.NL > 0) {
+            // large segments: train their models on their sorted samples, then
+            // rank every key (learned prediction + exact splitter check)
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (u32*)b.lst, 4);
+            LAUNCH_OK();
+            hipLaunchKernelGGL((k_sl_init<K>), dim3((u32)cdiv(P.NL, 64)), dim3(64), 0, st, b.ssk, b.seg, b.soff,
+                               b.lseg, P.NL, b.models);
+            LAUNCH_OK();
+            const u32 gq = (u32)std::max<u64>(1, cdiv(P.nls, 256));
+            for (int stage = 0; stage < 2; stage++) {
+                const int nmod = stage == 0 ? P.NL : P.NL * SEG_LEAVES;
+                hipLaunchKernelGGL((k_sl_x<K>), dim3(gq), dim3(256), 0, st, b.ssk, b.soff, b.lseg, b.lcs, P.NL,
+                                   b.models, stage, b.fx, b.fmid);
+                LAUNCH_OK();
+                hipLaunchKernelGGL(k_model_ranges, dim3((u32)cdiv((u64)nmod + 1, 256)), dim3(256), 0, st, b.fmid,
+                                   (i64)P.nls, nmod, b.flo);
+                LAUNCH_OK();
+                hipLaunchKernelGGL(k_sl_centres, dim3(nmod), dim3(64), 0, st, b.fx, b.flo, nmod, b.models, stage);
+                LAUNCH_OK();
+                hipLaunchKernelGGL(k_sl_forward, dim3(gq), dim3(256), 0, st, b.fx, b.fmid, b.lcs, P.NL, b.models,
+                                   stage, b.fr);
+                LAUNCH_OK();
+                hipLaunchKernelGGL(k_sl_backward, dim3(nmod), dim3(64), 0, st, b.fx, b.fr, b.flo, nmod, b.lcs,
+                                   b.models, stage, b.fg, b.fhs);
+                LAUNCH_OK();
+                hipLaunchKernelGGL(k_sl_update, dim3((u32)cdiv(nmod, 256)), dim3(256), 0, st, b.fg, b.fhs, b.flo,
+                                   nmod, b.lcs, b.models, stage);
+                LAUNCH_OK();
+            }
+            hipLaunchKernelGGL((k_sl_rank<K>), dim3((u32)(P.lblk.size() / 2)), dim3(SL_NT), 0, st, b.B, b.seg,
+                               b.btab, b.lblk, b.poff, b.coff, b.pk, b.pp, b.models, b.cntT, b.lst);
+            LAUNCH_OK();
+        }
     }
     for (size_t q = 0; q < P.cls_R.size(); q++) {
         const int G = (int)(P.gtab[q].size() / 2);
@@ -1029,6 +1115,7 @@ std::string graph_key(const void* a, const void* b, const void* c, const int64_t
     put((u64)(uintptr_t)a); put((u64)(uintptr_t)b); put((u64)(uintptr_t)c); put((u64)nseg); put((u64)dt);
     put((u64)hasv);
     put((u64)tu.cls.size());
+    put((u64)tu.learned_log2);
     for (auto& cc : tu.cls) { put((u64)cc.max_log2); put((u64)cc.block); put((u64)cc.s); }
     k.append((const char*)off, sizeof(int64_t) * ((size_t)nseg + 1));
     return k;
@@ -1061,6 +1148,7 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
         };
         put(P.seg); put(P.soff); put(P.poff); put(P.coff); put(P.btab); put(P.dtab); put(P.btab_s);
         for (auto& g : P.gtab) put(g);
+        put(P.lseg); put(P.lcs); put(P.lblk);
         HIP_OK(hipMemcpyAsync(b.tables, stage, b.tables_bytes, hipMemcpyHostToDevice, st));
         HIP_OK(hipEventRecord(g_tstage.done, st));
     }
@@ -1118,6 +1206,18 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
         stats->reserved_i[0] = P.NB;
         stats->reserved_i[1] = P.nmerged;
         stats->reserved_i[2] = launched ? 1 : 0;
+        stats->reserved_i[3] = P.NL;
+        stats->mispredict_rate = 0.0;
+        stats->mean_fix_dist = 0.0;
+        if (P.NL > 0) {
+            unsigned long long ls[2];
+            rc = d2h(ls, b.lst, 16, st);
+            if (rc) return rc;
+            i64 nlk = 0;  // keys ranked by the models
+            for (int j = 0; j < P.NL; j++) nlk += P.seg[(size_t)SEGW * P.lseg[j] + 1];
+            stats->mispredict_rate = (double)ls[0] / (double)std::max<i64>(1, nlk);
+            stats->mean_fix_dist = (double)ls[1] / (double)std::max<i64>(1, nlk);
+        }
     }
     return BSPS_OK;
 }

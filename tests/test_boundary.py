@@ -99,7 +99,10 @@ def test_segmented_validation(bsps):
     assert bsps.segmented_workspace_bytes(ok, 0, False, tuning='{"classes": [{"max_log2": 8, "block": 0, "s": 1}]}') == 0
     good = '{"classes": [{"max_log2": 8, "block": 64, "s": 2}, {"max_log2": 30, "block": 4096, "s": 8}]}'
     assert bsps.segmented_workspace_bytes(ok, 0, True, tuning=good) > bsps.segmented_workspace_bytes(ok, 0, False, tuning=good)
-    assert "max_log2" in bsps.tuning_format()
+    assert "max_log2" in bsps.tuning_format() and "learned_above_log2" in bsps.tuning_format()
+    lt = '{"learned_above_log2": %d, "classes": [{"max_log2": 30, "block": 4096, "s": 8}]}'
+    assert bsps.segmented_workspace_bytes(ok, 0, False, tuning=lt % 16) > 0
+    assert bsps.segmented_workspace_bytes(ok, 0, False, tuning=lt % 41) == 0
     # a segment that needs more than 1024 blocks of one tile
     big = np.array([0, 16384 * 1024 + 1], dtype=np.int64)
     assert bsps.segmented_workspace_bytes(big, 0, False) == 0

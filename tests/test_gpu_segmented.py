@@ -141,3 +141,31 @@ def test_bad_tuning_rejected(dev):
     with pytest.raises(bsps.BspsError) as e:
         bsps.sort_segmented_(t, np.array([0, 50, 100]), tuning='{"classes": [{"max_log2": 10}]}')
     assert e.value.code == bsps.EINVAL
+
+
+def test_learned_large_segments(ora, dev):
+    """Segments above 2^16 keys get their bucket counts from a model trained on
+    their own sample (batched forward / backward / update kernels) and every
+    key ranked with the exact splitter check: the output still equals the
+    oracle's, and equals the run with the learned path switched off."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    sizes = W.segment_sizes(48, 14, 19, seed=17)
+    keys, offs = W.segmented_int32(sizes, seed=17)
+    table = _default_table()
+    classes = [{"max_log2": a, "block": b, "s": c} for a, b, c in table]
+    on = json.dumps({"learned_above_log2": 16, "classes": classes})
+    off = json.dumps({"learned_above_log2": 40, "classes": classes})
+    st = _check(ora, dev, keys, offs, tuning=on, table=table)
+    n_large = int(sum(1 for n in sizes if n > (1 << 16)))
+    assert st["learned_segments"] == n_large > 0
+    assert 0.0 <= st["mispredict_rate"] < 0.5, st
+    st_off = _check(ora, dev, keys, offs, tuning=off, table=table)
+    assert st_off["learned_segments"] == 0
+    # key-value, all dtypes, through the learned path
+    vals = np.arange(keys.size, dtype=np.uint32)
+    for dtype in ("int64", "float32"):
+        k2 = W.random_keys(keys.size, dtype, seed=19, distinct=50000)
+        st2 = _check(ora, dev, k2, offs, values=vals, tuning=on, table=table)
+        assert st2["learned_segments"] > 0
+    del torch
