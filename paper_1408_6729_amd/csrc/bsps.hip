@@ -124,6 +124,7 @@ template <typename K> constexpr u32 tileT() { return (u32)(Shape<K>::NT * Shape<
 template <typename K>
 struct MwmBufs {
     u32 *run_start, *run_len, *out_base, *sdesc, *counters, *slot_group, *grp_base, *grp_nb, *bpos, *cuts;
+    u32 *wfirst, *wlast;
     K* bkey;
     u32 S;
     int G, R;
@@ -139,13 +140,15 @@ void carve_mwm(Carver& c, MwmBufs<K>& m, int G, int R, u64 n, u32 tavg) {
     m.run_len = c.take<u32>((u64)G * R);
     m.out_base = c.take<u32>(G);
     m.sdesc = c.take<u32>((u64)G * R * 4);
-    m.counters = c.take<u32>(4);
+    m.counters = c.take<u32>(8);  // slots, oversize, merge claims, largest oversize, work items
     m.slot_group = c.take<u32>(m.S);
     m.grp_base = c.take<u32>(G);
     m.grp_nb = c.take<u32>(G);
     m.bkey = c.take<K>(m.S);
     m.bpos = c.take<u32>(m.S);
     m.cuts = c.take<u32>((u64)m.S * R);
+    m.wfirst = c.take<u32>(m.S);
+    m.wlast = c.take<u32>(m.S);
 }
 
 template <typename K>
@@ -159,6 +162,7 @@ MwmArgs<K> mwm_args(const MwmBufs<K>& m, const K* src, const u32* srcv, K* dst, 
     a.slot_count = m.counters; a.oversize = m.counters + 1; a.work = m.counters + 2;
     a.slot_group = m.slot_group; a.grp_base = m.grp_base; a.grp_nb = m.grp_nb;
     a.bkey = m.bkey; a.bpos = m.bpos; a.cuts = m.cuts; a.S = m.S;
+    a.wfirst = m.wfirst; a.wlast = m.wlast; a.nwork = m.counters + 4;
     a.out_dt = out_dt; a.osmp = osmp; a.oys = oys; a.ospb = ospb;
     return a;
 }
@@ -192,13 +196,15 @@ template <typename K, bool HASV>
 bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     constexpr int NT = Shape<K>::NT;
     const int cus = device_cus();
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.slot_count, 4);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.slot_count, 8);
     LAUNCH_OK();
     hipLaunchKernelGGL((k_mwm_pick<K>), dim3(a.G), dim3(NT), 0, st, a);
     LAUNCH_OK();
     const u64 ncut = (u64)a.S * a.R;
     const u32 gcut = (u32)std::min<u64>(cdiv(ncut, 256), (u64)1 << 20);  // one search per thread: latency-bound
     hipLaunchKernelGGL((k_mwm_cuts<K>), dim3(gcut), dim3(256), 0, st, a);
+    LAUNCH_OK();
+    hipLaunchKernelGGL((k_mwm_plan<K>), dim3(a.G), dim3(PLAN_NT), 0, st, a);
     LAUNCH_OK();
 #ifndef BSPS_MERGE_WGS_PER_CU
 #define BSPS_MERGE_WGS_PER_CU 2

@@ -76,6 +76,9 @@ struct MwmArgs {
     K* bkey;               // [S] boundary records
     u32* bpos;
     u32* cuts;             // [S*R]
+    u32* wfirst;           // [S] work items of the merge: first and last slot of a run of
+    u32* wlast;            //     consecutive chunks of one group that together fit the cap
+    u32* nwork;            // [1] work items
     u32 S;                 // slot capacity
     int out_dt;            // BSPS_DT_NONE: keep order keys; else write raw keys of this dtype
     K* osmp;               // output samples every oys-th key of each group (or NULL)
@@ -421,6 +424,73 @@ __global__ void k_mwm_cuts(MwmArgs<K> a) {
     }
 }
 
+// ======================================================================= MWM: work items
+
+// The exact size of every chunk of a group follows from the cuts (the keys at
+// or below boundary c are the sum of its cuts over the runs). Consecutive
+// chunks are combined while they fit the cap, so that groups whose sample
+// forced small chunks (large groups, few samples per key) still fill the LDS
+// sort; a chunk above the cap stays alone. One workgroup per group.
+constexpr int PLAN_NT = 256, PLAN_MAXC = 4096;
+template <typename K>
+__global__ __launch_bounds__(PLAN_NT) void k_mwm_plan(MwmArgs<K> a) {
+    __shared__ u32 P[PLAN_MAXC];
+    __shared__ unsigned short itf[PLAN_MAXC], itl[PLAN_MAXC];
+    __shared__ u32 wsum[PLAN_NT / 64 + 2];
+    __shared__ u32 sh_n, sh_base;
+    const int g = blockIdx.x, t = threadIdx.x, R = a.R;
+    const u32 gb = a.grp_base[g], nb = a.grp_nb[g];
+    u32 myn = 0;
+    for (int r = t; r < R; r += PLAN_NT) myn += a.run_len[(i64)g * R + r];
+    u32 N;
+    (void)block_excl_scan<PLAN_NT>(myn, N, wsum);
+    if (N == 0 || gb >= a.S) return;  // no chunks
+    const u32 nch = nb + 1;
+    if (nch > PLAN_MAXC) {  // not combined: one item per chunk
+        if (t == 0) sh_base = atomicAdd(a.nwork, nch);
+        __syncthreads();
+        for (u32 c = t; c < nch; c += PLAN_NT) {
+            a.wfirst[sh_base + c] = gb + c;
+            a.wlast[sh_base + c] = gb + c;
+        }
+        return;
+    }
+    for (u32 c = t; c < nb; c += PLAN_NT) P[c] = 0;
+    __syncthreads();
+    const u64 ne = (u64)nb * R;
+    for (u64 e = t; e < ne; e += PLAN_NT) {
+        const u32 c = (u32)(e / R);
+        atomicAdd(&P[c], a.cuts[((i64)gb + c) * R + (i64)(e % R)]);
+    }
+    __syncthreads();
+    if (t == 0) {
+        u32 n = 0, first = 0, acc = 0, prev = 0;
+        for (u32 c = 0; c < nch; c++) {
+            const u32 below = c < nb ? P[c] : N;
+            const u32 sz = below - prev;
+            prev = below;
+            if (c > 0 && acc + sz > a.cap) {
+                itf[n] = (unsigned short)first;
+                itl[n] = (unsigned short)(c - 1);
+                n++;
+                first = c;
+                acc = 0;
+            }
+            acc += sz;
+        }
+        itf[n] = (unsigned short)first;
+        itl[n] = (unsigned short)nb;
+        n++;
+        sh_n = n;
+        sh_base = atomicAdd(a.nwork, n);
+    }
+    __syncthreads();
+    for (u32 i = t; i < sh_n; i += PLAN_NT) {
+        a.wfirst[sh_base + i] = gb + itf[i];
+        a.wlast[sh_base + i] = gb + itl[i];
+    }
+}
+
 // ======================================================================= MWM: chunk sort
 
 template <typename K, bool HASV>
@@ -540,26 +610,29 @@ struct MergeSmem {
 };
 
 template <typename K, bool HASV>
-__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 slot, MergeSmem<K>& S);
+__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 slot, const u32 slot_last,
+                                                MergeSmem<K>& S);
 
-// Persistent merge: workgroups take chunks (slots) one after another.
+// Persistent merge: workgroups take work items (runs of chunks) one after another.
 template <typename K, bool HASV>
 __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_mwm_merge(MwmArgs<K> a) {
     __shared__ MergeSmem<K> S;
-    const u32 nslot = min(a.S, *a.slot_count);
+    const u32 nwork = min(a.S, *a.nwork);
     for (;;) {
         if (threadIdx.x == 0) S.slot = atomicAdd(a.work, 1u);
         __syncthreads();
-        const u32 slot = S.slot;
+        const u32 w = S.slot;
         __syncthreads();
-        if (slot >= nslot) break;
-        mwm_merge_chunk<K, HASV>(a, slot, S);
+        if (w >= nwork) break;
+        mwm_merge_chunk<K, HASV>(a, a.wfirst[w], a.wlast[w], S);
         __syncthreads();
     }
 }
 
+// Merges the chunks slot .. slot_last of one group (one LDS sort).
 template <typename K, bool HASV>
-__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 slot, MergeSmem<K>& S) {
+__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 slot, const u32 slot_last,
+                                                MergeSmem<K>& S) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
     auto& sm = S.sm;
     u32* ppre = S.ppre;
@@ -570,9 +643,10 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     PHASE_START;
     const u32 g = a.slot_group[slot];
     const u32 c = slot - a.grp_base[g];
+    const u32 cl = slot_last - a.grp_base[g];
     const u32 nb = a.grp_nb[g];
     const u32* lorow = a.cuts + (i64)(slot - 1) * R;
-    const u32* hirow = a.cuts + (i64)slot * R;
+    const u32* hirow = a.cuts + (i64)slot_last * R;
     const u32* rl = a.run_len + (i64)g * R;
     const u32* rsp = a.run_start + (i64)g * R;
     // piece lengths and their prefix (runs in order)
@@ -580,7 +654,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     u32 mysum = 0, mylo = 0;
     for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
         const u32 lo = c == 0 ? 0u : lorow[r];
-        const u32 hi = c == nb ? rl[r] : hirow[r];
+        const u32 hi = cl == nb ? rl[r] : hirow[r];
         mysum += hi - lo;
         mylo += lo;
     }
@@ -588,7 +662,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     u32 ex = block_excl_scan<NT>(mysum, N, sm.wsum);
     for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
         const u32 lo = c == 0 ? 0u : lorow[r];
-        const u32 hi = c == nb ? rl[r] : hirow[r];
+        const u32 hi = cl == nb ? rl[r] : hirow[r];
         ppre[r] = ex;
         soff[r] = rsp[r] + lo;
         ex += hi - lo;
