@@ -148,6 +148,15 @@ __device__ __forceinline__ u32 block_excl_scan(u32 x, u32& total, u32* wsum) {
     return before + v - x;
 }
 
+// A value every lane of the wave holds alike, moved to a scalar register
+// (keeps workgroup-uniform values out of the vector registers).
+__device__ __forceinline__ u32 uniform(u32 v) { return (u32)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ u64 uniform(u64 v) {
+    const u32 lo = uniform((u32)v), hi = uniform((u32)(v >> 32));
+    return ((u64)hi << 32) | lo;
+}
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <int NT, typename K>
 __device__ __forceinline__ void block_minmax(K& mn, K& mx, u64* red) {
     constexpr int NW = NT / 64;
@@ -169,6 +178,8 @@ __device__ __forceinline__ void block_minmax(K& mn, K& mx, u64* red) {
         mn = a < mn ? a : mn;
         mx = b > mx ? b : mx;
     }
+    mn = uniform(mn);
+    mx = uniform(mx);
     __syncthreads();
 }
 
@@ -241,17 +252,12 @@ __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&r
                                              u32* cnt, u32* wsum) {
     const int t = threadIdx.x;
     u32* vex = reinterpret_cast<u32*>(exch);
-    if (nbits <= 0) {  // all sort keys equal: input order is the stable order
-#pragma unroll
-        for (int j = 0; j < IT; j++) {
-            rank[j] = (u32)(t * IT + j);
-            exch[padi(t * IT + j)] = sk[j];
-        }
-        __syncthreads();
-        return;
-    }
-    for (int sh = 0; sh < nbits; sh += RB) {
-        const bool last = sh + RB >= nbits;
+    // all sort keys equal (nbits = 0): one pass over the all-zero digit, which
+    // ranks every item at its own position
+    const int npass = nbits <= 0 ? 1 : (nbits + RB - 1) / RB;
+    for (int pass = 0; pass < npass; pass++) {
+        const int sh = pass * RB;
+        const bool last = pass == npass - 1;
         radix_rank<NT, IT>([&](int j) { return (u32)(sk[j] >> sh) & (RADIX - 1); }, rank, cnt, wsum);
 #pragma unroll
         for (int j = 0; j < IT; j++) exch[padi((int)rank[j])] = sk[j];

@@ -641,10 +641,10 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x, R = a.R;
     PHASE_START;
-    const u32 g = a.slot_group[slot];
-    const u32 c = slot - a.grp_base[g];
-    const u32 cl = slot_last - a.grp_base[g];
-    const u32 nb = a.grp_nb[g];
+    const u32 g = uniform(a.slot_group[uniform(slot)]);
+    const u32 c = uniform(slot - a.grp_base[g]);
+    const u32 cl = uniform(slot_last - a.grp_base[g]);
+    const u32 nb = uniform(a.grp_nb[g]);
     const u32* lorow = a.cuts + (i64)(slot - 1) * R;
     const u32* hirow = a.cuts + (i64)slot_last * R;
     const u32* rl = a.run_len + (i64)g * R;
@@ -660,6 +660,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     }
     u32 N;
     u32 ex = block_excl_scan<NT>(mysum, N, sm.wsum);
+    N = uniform(N);
     for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
         const u32 lo = c == 0 ? 0u : lorow[r];
         const u32 hi = cl == nb ? rl[r] : hirow[r];
@@ -671,7 +672,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     __syncthreads();
     u32 LO;
     (void)block_excl_scan<NT>(mylo, LO, sm.wsum);
-    const u32 out = a.out_base[g] + LO;
+    const u32 out = uniform(a.out_base[g] + LO);
     if (N == 0) return;
     PHASE(0);
     if (N > a.cap) {
@@ -809,8 +810,8 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
 #endif
     block_minmax<NT, K>(mn, mx, sm.red64);
     PHASE(2);
-    const int nbits = bitwidth64((u64)(mx - mn));
-    const u32 gstart = a.out_base[g];
+    const int nbits = uniform(bitwidth64((u64)(mx - mn)));
+    const u32 gstart = uniform(a.out_base[g]);
     const u32 osh = a.oys ? (u32)(__ffs(a.oys) - 1) : 0u;
     const u32 om = (1u << osh) - 1;
     K* dst = a.dst + out;
