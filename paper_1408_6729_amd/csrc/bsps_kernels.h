@@ -455,12 +455,17 @@ __global__ __launch_bounds__(PLAN_NT) void k_mwm_plan(MwmArgs<K> a) {
         }
         return;
     }
-    for (u32 c = t; c < nb; c += PLAN_NT) P[c] = 0;
-    __syncthreads();
-    const u64 ne = (u64)nb * R;
-    for (u64 e = t; e < ne; e += PLAN_NT) {
-        const u32 c = (u32)(e / R);
-        atomicAdd(&P[c], a.cuts[((i64)gb + c) * R + (i64)(e % R)]);
+    // one wave per boundary: lanes over the runs, then a wave sum
+    {
+        const int lane = t & 63, w = t >> 6;
+        for (u32 c = w; c < nb; c += PLAN_NT / 64) {
+            const u32* row = a.cuts + ((i64)gb + c) * R;
+            u32 v = 0;
+            for (int r = lane; r < R; r += 64) v += row[r];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) P[c] = v;
+        }
     }
     __syncthreads();
     if (t == 0) {
