@@ -124,7 +124,7 @@ template <typename K> constexpr u32 tileT() { return (u32)(Shape<K>::NT * Shape<
 template <typename K>
 struct MwmBufs {
     u32 *run_start, *run_len, *out_base, *sdesc, *counters, *slot_group, *grp_base, *grp_nb, *bpos, *cuts;
-    u32 *wfirst, *wlast;
+    u32 *below, *wfirst, *wlast;
     K* bkey;
     u32 S;
     int G, R;
@@ -147,6 +147,7 @@ void carve_mwm(Carver& c, MwmBufs<K>& m, int G, int R, u64 n, u32 tavg) {
     m.bkey = c.take<K>(m.S);
     m.bpos = c.take<u32>(m.S);
     m.cuts = c.take<u32>((u64)m.S * R);
+    m.below = c.take<u32>(m.S);
     m.wfirst = c.take<u32>(m.S);
     m.wlast = c.take<u32>(m.S);
 }
@@ -161,7 +162,7 @@ MwmArgs<K> mwm_args(const MwmBufs<K>& m, const K* src, const u32* srcv, K* dst, 
     a.smp = smp; a.cap = cap; a.tavg = tavg;
     a.slot_count = m.counters; a.oversize = m.counters + 1; a.work = m.counters + 2;
     a.slot_group = m.slot_group; a.grp_base = m.grp_base; a.grp_nb = m.grp_nb;
-    a.bkey = m.bkey; a.bpos = m.bpos; a.cuts = m.cuts; a.S = m.S;
+    a.bkey = m.bkey; a.bpos = m.bpos; a.cuts = m.cuts; a.below = m.below; a.S = m.S;
     a.wfirst = m.wfirst; a.wlast = m.wlast; a.nwork = m.counters + 4;
     a.out_dt = out_dt; a.osmp = osmp; a.oys = oys; a.ospb = ospb;
     return a;
@@ -200,9 +201,14 @@ bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     LAUNCH_OK();
     hipLaunchKernelGGL((k_mwm_pick<K>), dim3(a.G), dim3(NT), 0, st, a);
     LAUNCH_OK();
-    const u64 ncut = (u64)a.S * a.R;
-    const u32 gcut = (u32)std::min<u64>(cdiv(ncut, 256), (u64)1 << 20);  // one search per thread: latency-bound
-    hipLaunchKernelGGL((k_mwm_cuts<K>), dim3(gcut), dim3(256), 0, st, a);
+    // one wave per (group, run); with few runs the boundaries are split over
+    // gridDim.y waves so that the launch still holds some 8K waves
+    const u64 nwave = std::max<u64>(1, (u64)a.G * a.R);
+    const u32 ysplit = (u32)std::min<u64>(64, std::max<u64>(1, cdiv(8192, nwave)));
+    hipLaunchKernelGGL((k_mwm_cuts<K>), dim3((u32)cdiv(nwave, CUT_NT / 64), ysplit), dim3(CUT_NT), 0, st, a);
+    LAUNCH_OK();
+    hipLaunchKernelGGL((k_mwm_below<K>), dim3((u32)std::min<u64>(cdiv(a.S, 4), (u64)cus * 16)), dim3(256), 0, st,
+                       a);
     LAUNCH_OK();
     hipLaunchKernelGGL((k_mwm_plan<K>), dim3(a.G), dim3(PLAN_NT), 0, st, a);
     LAUNCH_OK();

@@ -76,6 +76,7 @@ struct MwmArgs {
     K* bkey;               // [S] boundary records
     u32* bpos;
     u32* cuts;             // [S*R]
+    u32* below;            // [S] keys of the group at or below each boundary (sum of its cuts)
     u32* wfirst;           // [S] work items of the merge: first and last slot of a run of
     u32* wlast;            //     consecutive chunks of one group that together fit the cap
     u32* nwork;            // [1] work items
@@ -387,31 +388,62 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
 // ======================================================================= MWM: exact cuts
 
 // cuts[slot*R + r] = number of records of run r that are <= the boundary record
-// of that slot (key first, then position). The run's own samples (every
-// stride-th key, stored compactly) are searched first; the cut then lies
-// within one stride of the run, which is searched last.
+// of that slot (key first, then position). One wave per (group, run, share of
+// the group's boundaries): the run's samples (every stride-th key, stored
+// compactly) are staged in LDS and each boundary is searched there (in global
+// memory when the run has more samples than the stage holds); the cut then
+// lies within one stride of the run, which is bisected in global memory. The
+// kernel is bound by the number of scattered global requests per search, which
+// the staging cuts from about lg(samples) + lg(stride) to lg(stride).
+// gridDim.y splits the boundaries of a (group, run) over several waves when
+// there are few runs.
+constexpr int CUT_NT = 256, CUT_SMAX = 1024;
+
 template <typename K>
-__global__ void k_mwm_cuts(MwmArgs<K> a) {
-    const u32 nslot = min(a.S, *a.slot_count);
-    const i64 total = (i64)nslot * a.R;
-    for (i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
-        const u32 slot = (u32)(idx / a.R);
-        const int r = (int)(idx % a.R);
-        const u32 g = a.slot_group[slot];
-        const u32 c = slot - a.grp_base[g];
-        if (c >= a.grp_nb[g]) continue;
+__global__ __launch_bounds__(CUT_NT) void k_mwm_cuts(MwmArgs<K> a) {
+    __shared__ K ls[CUT_NT / 64][CUT_SMAX];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, R = a.R;
+    const i64 gr = (i64)blockIdx.x * (CUT_NT / 64) + w;
+    const bool live = gr < (i64)a.G * R;
+    u32 nb = 0, gb = 0, rs = 0, len = 0, sidx = 0, scnt = 0, pb = 0, sstr = 1;
+    if (live) {
+        const u32 g = (u32)(gr / R);
+        nb = a.grp_nb[g];
+        gb = a.grp_base[g];
+        rs = a.run_start[gr];
+        len = a.run_len[gr];
+        const u32* d = a.sdesc + gr * 4;
+        sidx = d[0];
+        scnt = d[1];
+        pb = d[2];
+        sstr = d[3];
+    }
+    nb = uniform(nb); gb = uniform(gb); rs = uniform(rs); len = uniform(len);
+    sidx = uniform(sidx); scnt = uniform(scnt); pb = uniform(pb); sstr = uniform(sstr);
+    const bool staged = scnt <= (u32)CUT_SMAX;
+    K* st = ls[w];
+    if (live && nb > 0 && staged)
+        for (u32 j = lane; j < scnt; j += 64) st[j] = a.smp[sidx + j];
+    __syncthreads();
+    if (!live || nb == 0) return;
+    const u32 r = (u32)(gr % R);
+    const u32 step = 64u * gridDim.y;
+    for (u32 c = blockIdx.y * 64u + lane; c < nb; c += step) {
+        const u32 slot = gb + c;
         const K bk = a.bkey[slot];
         const u32 bp = a.bpos[slot];
-        const i64 gr = (i64)g * a.R + r;
-        const u32 rs = a.run_start[gr];
-        const u32 len = a.run_len[gr];
-        const u32* d = a.sdesc + gr * 4;
-        const u32 sidx = d[0], scnt = d[1], pb = d[2], sstr = d[3];
         // J = samples of this run that are <= the boundary
         u32 lo = 0, hi = scnt;
-        while (lo < hi) {
-            const u32 mid = (lo + hi) >> 1;
-            if (rec_le<K>(a.smp[sidx + mid], pb + mid * sstr, bk, bp)) lo = mid + 1; else hi = mid;
+        if (staged) {
+            while (lo < hi) {
+                const u32 mid = (lo + hi) >> 1;
+                if (rec_le<K>(st[mid], pb + mid * sstr, bk, bp)) lo = mid + 1; else hi = mid;
+            }
+        } else {
+            while (lo < hi) {
+                const u32 mid = (lo + hi) >> 1;
+                if (rec_le<K>(a.smp[sidx + mid], pb + mid * sstr, bk, bp)) lo = mid + 1; else hi = mid;
+            }
         }
         const u32 J = lo;
         u32 wlo = J > 0 ? pb + (J - 1) * sstr - rs + 1 : 0u;
@@ -420,7 +452,25 @@ __global__ void k_mwm_cuts(MwmArgs<K> a) {
             const u32 mid = (wlo + whi) >> 1;
             if (rec_le<K>(a.src[rs + mid], rs + mid, bk, bp)) wlo = mid + 1; else whi = mid;
         }
-        a.cuts[(i64)slot * a.R + r] = wlo;
+        a.cuts[(i64)slot * R + r] = wlo;
+    }
+}
+
+// below[slot] = sum of the slot's cuts over the runs: the keys of its group at
+// or below its boundary. One wave per slot.
+template <typename K>
+__global__ __launch_bounds__(256) void k_mwm_below(MwmArgs<K> a) {
+    const u32 nslot = min(a.S, *a.slot_count);
+    const int lane = threadIdx.x & 63, R = a.R;
+    for (u32 slot = blockIdx.x * 4u + (threadIdx.x >> 6); slot < nslot; slot += gridDim.x * 4u) {
+        const u32 g = a.slot_group[slot];
+        if (slot - a.grp_base[g] >= a.grp_nb[g]) continue;  // a group's last chunk has no boundary
+        const u32* row = a.cuts + (i64)slot * R;
+        u32 v = 0;
+        for (int i = lane; i < R; i += 64) v += row[i];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) a.below[slot] = v;
     }
 }
 
@@ -455,18 +505,7 @@ __global__ __launch_bounds__(PLAN_NT) void k_mwm_plan(MwmArgs<K> a) {
         }
         return;
     }
-    // one wave per boundary: lanes over the runs, then a wave sum
-    {
-        const int lane = t & 63, w = t >> 6;
-        for (u32 c = w; c < nb; c += PLAN_NT / 64) {
-            const u32* row = a.cuts + ((i64)gb + c) * R;
-            u32 v = 0;
-            for (int r = lane; r < R; r += 64) v += row[r];
-#pragma unroll
-            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (lane == 0) P[c] = v;
-        }
-    }
+    for (u32 c = t; c < nb; c += PLAN_NT) P[c] = a.below[gb + c];
     __syncthreads();
     if (t == 0) {
         u32 n = 0, first = 0, acc = 0, prev = 0;
