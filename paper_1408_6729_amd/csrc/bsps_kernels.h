@@ -507,26 +507,35 @@ __global__ __launch_bounds__(PLAN_NT) void k_mwm_plan(MwmArgs<K> a) {
     }
     for (u32 c = t; c < nb; c += PLAN_NT) P[c] = a.below[gb + c];
     __syncthreads();
-    if (t == 0) {
+    // greedy combination by wave 0: 64 chunk sizes at a time in registers,
+    // walked in order with uniform (scalar) state
+    if (t < 64) {
         u32 n = 0, first = 0, acc = 0, prev = 0;
-        for (u32 c = 0; c < nch; c++) {
-            const u32 below = c < nb ? P[c] : N;
-            const u32 sz = below - prev;
-            prev = below;
-            if (c > 0 && acc + sz > a.cap) {
-                itf[n] = (unsigned short)first;
-                itl[n] = (unsigned short)(c - 1);
-                n++;
-                first = c;
-                acc = 0;
+        for (u32 c0 = 0; c0 < nch; c0 += 64) {
+            const u32 mine = c0 + t < nb ? P[c0 + t] : N;
+            const u32 cnt = min(64u, nch - c0);
+            for (u32 j = 0; j < cnt; j++) {
+                const u32 below = (u32)__builtin_amdgcn_readlane((int)mine, (int)j);
+                const u32 sz = below - prev;
+                prev = below;
+                if (c0 + j > 0 && acc + sz > a.cap) {
+                    if (t == 0) {
+                        itf[n] = (unsigned short)first;
+                        itl[n] = (unsigned short)(c0 + j - 1);
+                    }
+                    n++;
+                    first = c0 + j;
+                    acc = 0;
+                }
+                acc += sz;
             }
-            acc += sz;
         }
-        itf[n] = (unsigned short)first;
-        itl[n] = (unsigned short)nb;
-        n++;
-        sh_n = n;
-        sh_base = atomicAdd(a.nwork, n);
+        if (t == 0) {
+            itf[n] = (unsigned short)first;
+            itl[n] = (unsigned short)nb;
+            sh_n = n + 1;
+            sh_base = atomicAdd(a.nwork, n + 1);
+        }
     }
     __syncthreads();
     for (u32 i = t; i < sh_n; i += PLAN_NT) {
