@@ -145,15 +145,15 @@ template <typename K, typename SK, int NT, int IT>
 __device__ __forceinline__ void store_sorted(const SK* ex, K mn, int cnt, K* out, int out_dt, K* smp, i64 sbase,
                                              u32 ysh) {
     const int t = threadIdx.x;
-    const u32 ym = (1u << ysh) - 1;
 #pragma unroll
     for (int j = 0; j < IT; j++) {
         const int i = j * NT + t;
-        if (i < cnt) {
-            const K u = (K)ex[padi(i)] + mn;
-            out[i] = rawkey<K>(u, out_dt);
-            if (smp && (((u32)i + 1) & ym) == 0) smp[sbase + (((u32)i + 1) >> ysh) - 1] = u;
-        }
+        if (i < cnt) out[i] = rawkey<K>((K)ex[padi(i)] + mn, out_dt);
+    }
+    // samples: every (2^ysh)-th key, one strided pass over the sorted keys in LDS
+    if (smp) {
+        const int ns = cnt >> ysh;
+        for (int k = t; k < ns; k += NT) smp[sbase + k] = (K)ex[padi(((k + 1) << ysh) - 1)] + mn;
     }
 }
 
@@ -868,10 +868,13 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     const u32 osh = a.oys ? (u32)(__ffs(a.oys) - 1) : 0u;
     const u32 om = (1u << osh) - 1;
     K* dst = a.dst + out;
-    auto emit = [&](u32 i, K u) {
+    // output samples: the chunk positions whose rank in the group plus one is a
+    // multiple of 2^osh, one strided pass over the sorted keys in LDS
+    auto emit_samples = [&](auto* e) {
         if (a.osmp) {
-            const u32 rel = out + i - gstart + 1;
-            if ((rel & om) == 0) a.osmp[(i64)g * a.ospb + (rel >> osh) - 1] = u;
+            const u32 step = om + 1, first = (gstart - out - 1) & om;
+            for (u32 i = first + (u32)t * step; i < N; i += (u32)NT * step)
+                a.osmp[(i64)g * a.ospb + ((out + i - gstart + 1) >> osh) - 1] = (K)e[padi((int)i)] + mn;
         }
     };
     if (sizeof(K) == 8 && nbits > 32) {
@@ -883,12 +886,9 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
 #pragma unroll
         for (int j = 0; j < IT; j++) {
             const u32 i = (u32)(j * NT + t);
-            if (i < N) {
-                const K u = (K)(e[padi((int)i)] + (u64)mn);
-                dst[i] = rawkey<K>(u, a.out_dt);
-                emit(i, u);
-            }
+            if (i < N) dst[i] = rawkey<K>((K)(e[padi((int)i)] + (u64)mn), a.out_dt);
         }
+        emit_samples(e);
     } else {
         u32 sk[IT];
 #pragma unroll
@@ -898,12 +898,9 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
 #pragma unroll
         for (int j = 0; j < IT; j++) {
             const u32 i = (u32)(j * NT + t);
-            if (i < N) {
-                const K u = (K)vex[padi((int)i)] + mn;
-                dst[i] = rawkey<K>(u, a.out_dt);
-                emit(i, u);
-            }
+            if (i < N) dst[i] = rawkey<K>((K)vex[padi((int)i)] + mn, a.out_dt);
         }
+        emit_samples(vex);
         PHASE(4);
     }
     if (HASV) {
