@@ -90,8 +90,11 @@ template <> struct Shape<u64> { static constexpr int NT = BSPS_NT64, IT = BSPS_I
 #define BSPS_WG_PER_CU 2      // occupancy target of the sorting kernels (workgroups per CU)
 #endif
 
-constexpr int RB = 6;                 // radix bits per pass
-constexpr int RADIX = 1 << RB;        // 64 digits
+#ifndef BSPS_RB
+#define BSPS_RB 6
+#endif
+constexpr int RB = BSPS_RB;           // radix bits per pass
+constexpr int RADIX = 1 << RB;        // digits per pass
 constexpr int HALF = RADIX / 2;       // digits d and d + HALF share one 32-bit counter word
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }  // one pad word per 32

@@ -554,6 +554,19 @@ __device__ void mwm_emit(const MwmArgs<K>& a, u32 g, u32 o, K u, u32 gstart) {
     }
 }
 
+// o[d] = h[0] + ... + h[d-1] for the RADIX digits, by wave 0 in steps of 64.
+__device__ __forceinline__ void digit_excl_scan(const u32* h, u32* o, int t) {
+    if (t < 64) {
+        u32 carry = 0;
+        for (int d0 = 0; d0 < RADIX; d0 += 64) {
+            const u32 hv = d0 + t < RADIX ? h[d0 + t] : 0u;
+            const u32 inc = wave_incl_scan(hv);
+            if (d0 + t < RADIX) o[d0 + t] = carry + inc - hv;
+            carry += (u32)__shfl((int)inc, 63, 64);
+        }
+    }
+}
+
 // Oversize chunk: LSD radix passes through global memory by one workgroup.
 // Pieces are first copied (in run order) to scr[out .. out+N), then sorted by
 // digit passes alternating scr <-> dst; the last step writes dst.
@@ -589,11 +602,7 @@ __device__ void mwm_oversize(const MwmArgs<K>& a, u32 g, u32 slot, u32 c, u32 nb
         __syncthreads();
         for (u32 i = t; i < N; i += NT) atomicAdd(&hist[(u32)((u64)(X[i] - mn) >> sh) & (RADIX - 1)], 1u);
         __syncthreads();
-        if (t < 64) {
-            u32 hv = hist[t];
-            u32 inc = wave_incl_scan(hv);
-            doff[t] = inc - hv;
-        }
+        digit_excl_scan(hist, doff, t);
         __syncthreads();
         for (u32 b0 = 0; b0 < N; b0 += T) {
             u32 dig[IT], rank[IT];
@@ -616,11 +625,7 @@ __device__ void mwm_oversize(const MwmArgs<K>& a, u32 g, u32 slot, u32 c, u32 nb
                 }
             }
             __syncthreads();
-            if (t < 64) {
-                u32 hv = tcnt[t];
-                u32 inc = wave_incl_scan(hv);
-                tbase[t] = inc - hv;
-            }
+            digit_excl_scan(tcnt, tbase, t);
             radix_rank<NT, IT>([&](int j) { return dig[j]; }, rank, sm.cnt(), sm.wsum);
 #pragma unroll
             for (int j = 0; j < IT; j++) {
