@@ -42,7 +42,7 @@ extern "C" {
 typedef enum {
     BSPS_OK = 0,
     BSPS_EINVAL = 1,       /* an argument is out of range (see each call) */
-    BSPS_EWORKSPACE = 2,   /* workspace NULL or smaller than bsps_workspace_bytes() */
+    BSPS_EWORKSPACE = 2,   /* workspace NULL, not 256-byte aligned, or smaller than bsps_workspace_bytes() */
     BSPS_EDEVICE = 3,      /* a HIP call failed */
     BSPS_EUNSUPPORTED = 4  /* valid but outside the library limits (n, p) */
 } bsps_status;
@@ -118,7 +118,7 @@ size_t bsps_workspace_bytes(int64_t n, int32_t dtype, int32_t with_values, const
 /*
  * Sort n keys in place (Figure SortD / Figure SortRI).
  *  keys      device, n keys of `dtype`; replaced by the sorted keys
- *  ws        device workspace of ws_bytes >= bsps_workspace_bytes(n, dtype, 0, prm)
+ *  ws        device workspace, 256-byte aligned, of ws_bytes >= bsps_workspace_bytes(n, dtype, 0, prm)
  * Errors: EINVAL for n < 0, p < 1, p > max(n, 1), s < 1, RAN with s*p - 1 > n,
  * unknown dtype/variant/route/bucketing, leaves < 0 or > 4096, nonzero reserved fields;
  * EWORKSPACE; EUNSUPPORTED beyond the limits above. n = 0 and n = 1 are

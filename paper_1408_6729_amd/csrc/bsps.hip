@@ -54,6 +54,11 @@ bsps_status hip_fail(hipError_t e, const char* what, int line) {
     } while (0)
 
 inline u64 cdiv(u64 a, u64 b) { return (a + b - 1) / b; }
+// The learned-rank counters (two u64, updated by 64-bit atomics) follow the
+// p*p count matrix at the next 8-byte boundary.
+inline size_t lstats_off(int p) { return ((size_t)p * p + 1) & ~(size_t)1; }
+// Workspaces are carved into 256-byte aligned pieces and must start aligned.
+inline bool ws_ok(const void* ws) { return ws && ((uintptr_t)ws & 255) == 0; }
 inline i64 hblk(i64 n, int p, int k) { return (i64)(((u64)k * (u64)n) / (u64)p); }
 
 // Bump allocator over the caller's workspace (256-byte aligned pieces). With
@@ -445,7 +450,7 @@ size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* pr
     P.fitws_bytes = 0;
     if (scatter) {
         P.bucket = c.take<u32>(n);
-        P.C = c.take<u32>((u64)p * p + 4);
+        P.C = c.take<u32>(lstats_off(p) + 4);
         P.off = c.take<u32>((u64)p * p);
         if (prm->bucketing == BSPS_LEARNED) {
             const int L = prm->leaves > 0 ? prm->leaves : 4096;
@@ -542,7 +547,7 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
     Carver c(ws);
     Plan<K> P{};
     const size_t need = carve_plan<K>(c, P, n, HASV, prm);
-    if (!ws || ws_bytes < need) return BSPS_EWORKSPACE;
+    if (!ws_ok(ws) || ws_bytes < need) return BSPS_EWORKSPACE;
     const Opts o = opts_for<K>(prm);
     K* io = (K*)keys;
     bsps_status rc;
@@ -632,14 +637,18 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
                 rc = fit_model<K>(P.ssk, ns, BSPS_DT_NONE, p, s, L, 1, P.model, P.fitws, st);
                 if (rc) return rc;
             }
-            hipLaunchKernelGGL(k_zero_u32, dim3((u32)cdiv((u64)p * p + 4, 256)), dim3(256), 0, st, P.C, p * p + 4);
+            hipLaunchKernelGGL(k_zero_u32, dim3((u32)cdiv(lstats_off(p) + 4, 256)), dim3(256), 0, st, P.C,
+                               (int)(lstats_off(p) + 4));
             LAUNCH_OK();
             StageScope sk(ST_RANK_K, st);
+            // per-key bucket ids only for the diagnostic copy: routing needs
+            // just the counts, since the runs of a sorted block are contiguous
+            u32* bids = (stats && stats->buckets) ? P.bucket : nullptr;
             if (prm->bucketing == BSPS_LEARNED)
-                rc = launch_rank<K, true>(P.B, n, p, P.pk, P.pp, BSPS_DT_NONE, P.model, P.bucket, P.C,
-                                          (unsigned long long*)(P.C + (size_t)p * p), st);
+                rc = launch_rank<K, true>(P.B, n, p, P.pk, P.pp, BSPS_DT_NONE, P.model, bids, P.C,
+                                          (unsigned long long*)(P.C + lstats_off(p)), st);
             else
-                rc = launch_rank<K, false>(P.B, n, p, P.pk, P.pp, BSPS_DT_NONE, nullptr, P.bucket, P.C, nullptr, st);
+                rc = launch_rank<K, false>(P.B, n, p, P.pk, P.pp, BSPS_DT_NONE, nullptr, bids, P.C, nullptr, st);
             if (rc) return rc;
         }
         // A5: the p independent prefix computations, then routing into Z (= A).
@@ -649,9 +658,10 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
             LAUNCH_OK();
             hipLaunchKernelGGL(k_route_offsets, dim3(p), dim3(256), 0, st, P.C, P.cntT, p, P.off);
             LAUNCH_OK();
-            const int tpbs = (int)cdiv(cdiv((u64)n, (u64)p), 4096);
-            hipLaunchKernelGGL((k_scatter<K, HASV>), dim3((u32)(p * tpbs)), dim3(256), 0, st, P.B, P.Bv, P.bucket, n, p,
-                               tpbs, P.cntT, P.off, P.bs.A, P.bs.Av);
+            // about 2048 workgroups in all, each taking a share of one block
+            const int wpb = (int)std::max<i64>(1, (2048 + p - 1) / p);
+            hipLaunchKernelGGL((k_scatter<K, HASV>), dim3((u32)(p * wpb)), dim3(SCAT_NT), 0, st, P.B, P.Bv, n, p, wpb,
+                               P.C, P.off, P.bs.A, P.bs.Av);
             LAUNCH_OK();
             hipLaunchKernelGGL(k_bucket_tables, dim3(p), dim3(256), 0, st, n, p, P.cntT, kSampleStride,
                                std::max<u32>(1, P.spb), (const u32*)P.off, P.bm.run_start, P.bm.run_len,
@@ -714,7 +724,7 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         stats->reserved_i[2] = (i64)std::max(ctr[3], ctr2[3]);     // largest oversize chunk
         if (prm->route == BSPS_ROUTE_SCATTER && prm->bucketing == BSPS_LEARNED) {
             unsigned long long ls[2];
-            rc = d2h(ls, P.C + (size_t)p * p, 16, st);
+            rc = d2h(ls, P.C + lstats_off(p), 16, st);
             if (rc) return rc;
             stats->mispredict_rate = (double)ls[0] / (double)n;
             stats->mean_fix_dist = (double)ls[1] / (double)n;
@@ -1145,7 +1155,7 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
     SegBufs<K> b{};
     Carver c(ws);
     const size_t need = carve_seg<K>(c, P, HASV, b, o.tavg);
-    if (!ws || ws_bytes < need) return BSPS_EWORKSPACE;
+    if (!ws_ok(ws) || ws_bytes < need) return BSPS_EWORKSPACE;
     if (P.NB == 0) return BSPS_OK;
     // tables -> workspace (pinned host staging in carve order, asynchronous)
     {
@@ -1293,7 +1303,7 @@ bsps_status bsps_rank(const void* keys, int64_t n, int32_t dtype, int32_t p, con
     if (bucketing == BSPS_LEARNED && !model) return BSPS_EINVAL;
     if (p > kMaxP || n >= (i64)0xFFFFFFFFll) return BSPS_EUNSUPPORTED;
     if (n > 0 && (!keys || (p > 1 && (!spl_keys || !spl_pos)))) return BSPS_EINVAL;
-    if (!ws || ws_bytes < bsps_rank_workspace_bytes(n, p)) return BSPS_EWORKSPACE;
+    if (!ws_ok(ws) || ws_bytes < bsps_rank_workspace_bytes(n, p)) return BSPS_EWORKSPACE;
     if (n == 0) return BSPS_OK;
     hipStream_t s = (hipStream_t)stream;
     unsigned long long* lst = (unsigned long long*)ws;
@@ -1339,7 +1349,7 @@ bsps_status bsps_fit_model(const void* smp_keys, int64_t N, int32_t dtype, int32
     if (N < 1 || p < 1 || s < 1 || leaves < 1 || leaves > MAX_LEAVES || iters < 1 || dtype < 0 || dtype > 2 ||
         !smp_keys || !model)
         return BSPS_EINVAL;
-    if (!ws || ws_bytes < bsps_fit_workspace_bytes(N, leaves)) return BSPS_EWORKSPACE;
+    if (!ws_ok(ws) || ws_bytes < bsps_fit_workspace_bytes(N, leaves)) return BSPS_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     if (dtype == BSPS_I64) return fit_model<u64>((const u64*)smp_keys, N, dtype, p, s, leaves, iters, model, ws, st);
     return fit_model<u32>((const u32*)smp_keys, N, dtype, p, s, leaves, iters, model, ws, st);
@@ -1351,7 +1361,7 @@ bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int3
     if (N < 1 || p < 1 || s < 1 || leaves < 1 || leaves > MAX_LEAVES || dtype < 0 || dtype > 2 || !smp_keys || !model ||
         !out_leaf || !out_grad || !out_gram || !out_loss)
         return BSPS_EINVAL;
-    if (!ws || ws_bytes < bsps_fit_workspace_bytes(N, leaves)) return BSPS_EWORKSPACE;
+    if (!ws_ok(ws) || ws_bytes < bsps_fit_workspace_bytes(N, leaves)) return BSPS_EWORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     Carver c(ws);
     FitWs f = carve_fit(c, N, leaves);

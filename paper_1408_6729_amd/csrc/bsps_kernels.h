@@ -1070,22 +1070,51 @@ __global__ __launch_bounds__(256) void k_route_offsets(const u32* C, const u32* 
     }
 }
 
-// Routing (Figure SortD steps 10-11): key g of block k in bucket b moves to
-// off[k][b] + its position within run (k, b); order within runs is kept.
+// Routing (Figure SortD steps 10-11): run (k, b), the keys of sorted block k
+// that fall in bucket b (contiguous, since the block is sorted), moves to
+// off[k*p + b] with its order kept. Each workgroup takes a share of one block:
+// the block's run starts (the prefix of its count row) and destinations are
+// staged in LDS, every key finds its run by a branch-free bisection there, and
+// keys are read and written position-striped (coalesced within a run).
+constexpr int SCAT_NT = 256, SCAT_IT = 16;
+
 template <typename K, bool HASV>
-__global__ __launch_bounds__(256) void k_scatter(const K* B, const u32* Bv, const u32* bucket, i64 n, int p, int tpb,
-                                                 const u32* cntT, const u32* off, K* Z, u32* Zv) {
-    constexpr int TILE = 256 * 16;
-    const int k = blockIdx.x / tpb, tt = blockIdx.x % tpb;
-    const i64 st = (i64)(((u64)k * (u64)n) / (u64)p), en = (i64)(((u64)(k + 1) * (u64)n) / (u64)p);
-    const i64 base = st + (i64)tt * TILE;
-#pragma unroll 4
-    for (int j = 0; j < 16; j++) {
-        const i64 g = base + j * 256 + threadIdx.x;
-        if (g >= en) break;
-        const u32 b = bucket[g];
-        const u32 dst = off[(i64)k * p + b] + (u32)(g - st) - cntT[(i64)b * p + k];
-        Z[dst] = B[g];
-        if (HASV) Zv[dst] = Bv[g];
+__global__ __launch_bounds__(SCAT_NT) void k_scatter(const K* B, const u32* Bv, i64 n, int p, int wpb, const u32* C,
+                                                     const u32* off, K* Z, u32* Zv) {
+    constexpr int NT = SCAT_NT, TILE = SCAT_NT * SCAT_IT;
+    __shared__ u32 rs[MAXR + 1], od[MAXR];
+    __shared__ u32 wsum[NT / 64 + 2];
+    const int k = blockIdx.x / wpb, w = blockIdx.x % wpb, t = threadIdx.x;
+    const i64 st = blk_start(n, p, k), m = blk_start(n, p, k + 1) - st;
+    const u32* crow = C + (i64)k * p;
+    const int per = (p + NT - 1) / NT;
+    u32 loc = 0;
+    for (int b = t * per; b < (t + 1) * per && b < p; b++) loc += crow[b];
+    u32 tot;
+    u32 ex = block_excl_scan<NT>(loc, tot, wsum);
+    for (int b = t * per; b < (t + 1) * per && b < p; b++) {
+        rs[b] = ex;
+        od[b] = off[(i64)k * p + b];
+        ex += crow[b];
+    }
+    if (t == 0) rs[p] = tot;
+    __syncthreads();
+    int top = 1;  // largest power of two <= p - 1 (bisection steps)
+    while (top * 2 <= p - 1) top *= 2;
+    const i64 lo = m * w / wpb, hi = m * (w + 1) / wpb;
+    for (i64 c0 = lo; c0 < hi; c0 += TILE) {
+#pragma unroll
+        for (int j = 0; j < SCAT_IT; j++) {
+            const i64 c = c0 + j * NT + t;
+            if (c < hi) {
+                // run of position c: the largest b with rs[b] <= c
+                int b = 0;
+                for (int step = top; step > 0; step >>= 1)
+                    if (b + step < p && rs[b + step] <= (u32)c) b += step;
+                const u32 dst = od[b] + (u32)c - rs[b];
+                Z[dst] = B[st + c];
+                if (HASV) Zv[dst] = Bv[st + c];
+            }
+        }
     }
 }

@@ -74,6 +74,7 @@ def test_workspace_checked_before_device(bsps):
     assert need > 2 * 4 * (1 << 20)
     assert _call(bsps, 1 << 20, 0, prm, ws=None, ws_bytes=0) == bsps.EWORKSPACE
     assert _call(bsps, 1 << 20, 0, prm, ws=ct.c_void_p(4096), ws_bytes=need - 1) == bsps.EWORKSPACE
+    assert _call(bsps, 1 << 20, 0, prm, ws=ct.c_void_p(4096 + 8), ws_bytes=need) == bsps.EWORKSPACE  # unaligned
     kv = bsps.workspace_bytes(1 << 20, 0, True, prm)
     assert kv > need
     assert bsps.workspace_bytes(1 << 20, 1, False, prm) > need  # int64 keys

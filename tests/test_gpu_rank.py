@@ -51,6 +51,26 @@ def test_scatter_route_parity(ora, dev, bucketing, dtype, variant):
         assert 0.0 <= st["mispredict_rate"] < 0.5
 
 
+@pytest.mark.parametrize("p", [3, 64, 1024])
+@pytest.mark.parametrize("bucketing", [0, 1])
+def test_scatter_route_without_diagnostics(ora, dev, p, bucketing):
+    """Scatter route with no diagnostic arrays: no per-key bucket ids are kept,
+    and the runs are routed from the count matrix alone (Figure SortD steps
+    10-11); output keys and payloads equal the oracle's."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    n, s = 500003, 16
+    keys = W.random_keys(n, "int32", seed=7, distinct=20000)
+    vals = np.arange(n, dtype=np.uint32)
+    ref = ora.sort(keys, p, s, ora.DET, 1, vals)
+    t = _t(keys, dev)
+    v = _t(vals.view(np.int32), dev)
+    bsps.sort_(t, p, s, ora.DET, values=v, bucketing=bucketing, route=bsps.ROUTE_SCATTER, leaves=64)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), ref["keys"])
+    assert np.array_equal(v.cpu().numpy().view(np.uint32), ref["values"])
+
+
 @pytest.mark.parametrize("p", [2, 100, 1024])
 @pytest.mark.parametrize("bucketing", [0, 1])
 def test_rank_entry_point(ora, dev, p, bucketing):
