@@ -323,39 +323,48 @@ __global__ __launch_bounds__(RankShape<LEARNED>::NT) void k_rank(const K* B, i64
         const i64 base = st + (i64)tt * TILE;
         const i64 cnt64 = en - base;
         const int cnt = cnt64 <= 0 ? 0 : (cnt64 > TILE ? TILE : (int)cnt64);
-#pragma unroll 4
-        for (int j = 0; j < RANK_IT; j++) {
-            if (j * NT + (t & ~63) >= cnt) break;  // the whole wave is past the tile's end
-            const int i = j * NT + t;
-            const bool valid = i < cnt;
-            const i64 g = base + i;
-            int b = p;
-            if (valid) {
-                const K key = okey<K>(B[g], dt);
-                const typename SplitLds<K>::Q q = SplitLds<K>::query(key, (u32)g);
-                if (!LEARNED) {
-                    b = 0;
-                    for (int h = P2 >> 1; h >= 1; h >>= 1) b += S.lt(b + h - 1, q) ? h : 0;
-                } else {
-                    const float x = model_x<K>(key, mh);
-                    const float2 ce = lf2[model_leaf(x, mh)];
-                    const float f = fminf(fmaxf((ce.x * x + ce.y) * (float)p, 0.0f), (float)(p - 1));
-                    const int pred = (int)f;
-                    b = pred;
-                    while (b > 0 && !S.lt(b - 1, q)) b--;
-                    while (b < p - 1 && S.lt(b, q)) b++;
-                    miss += b != pred;
-                    dist += (unsigned long long)(b > pred ? b - pred : pred - b);
-                }
-                if (bucket) bucket[g] = (u32)b;
+        constexpr int RG = sizeof(K) == 8 ? 4 : 8;  // keys whose loads are issued together
+        for (int j0 = 0; j0 < RANK_IT; j0 += RG) {
+            if (j0 * NT + (t & ~63) >= cnt) break;  // the whole wave is past the tile's end
+            K kg[RG];
+#pragma unroll
+            for (int u = 0; u < RG; u++) {
+                const int i = (j0 + u) * NT + t;
+                kg[u] = i < cnt ? B[base + i] : (K)0;
             }
-            const int bprev = __shfl_up(b, 1, 64);
-            const bool head = valid && (lane == 0 || bprev != b);
-            const unsigned long long bound = __ballot(head || !valid);
-            if (head) {
-                const unsigned long long above = lane == 63 ? 0ull : (bound >> (lane + 1));
-                const int len = above ? __ffsll((long long)above) : 64 - lane;
-                atomicAdd(&hist[b], (u32)len);
+#pragma unroll
+            for (int u = 0; u < RG; u++) {
+                const int i = (j0 + u) * NT + t;
+                const bool valid = i < cnt;
+                const i64 g = base + i;
+                int b = p;
+                if (valid) {
+                    const K key = okey<K>(kg[u], dt);
+                    const typename SplitLds<K>::Q q = SplitLds<K>::query(key, (u32)g);
+                    if (!LEARNED) {
+                        b = 0;
+                        for (int h = P2 >> 1; h >= 1; h >>= 1) b += S.lt(b + h - 1, q) ? h : 0;
+                    } else {
+                        const float x = model_x<K>(key, mh);
+                        const float2 ce = lf2[model_leaf(x, mh)];
+                        const float f = fminf(fmaxf((ce.x * x + ce.y) * (float)p, 0.0f), (float)(p - 1));
+                        const int pred = (int)f;
+                        b = pred;
+                        while (b > 0 && !S.lt(b - 1, q)) b--;
+                        while (b < p - 1 && S.lt(b, q)) b++;
+                        miss += b != pred;
+                        dist += (unsigned long long)(b > pred ? b - pred : pred - b);
+                    }
+                    if (bucket) bucket[g] = (u32)b;
+                }
+                const int bprev = __shfl_up(b, 1, 64);
+                const bool head = valid && (lane == 0 || bprev != b);
+                const unsigned long long bound = __ballot(head || !valid);
+                if (head) {
+                    const unsigned long long above = lane == 63 ? 0ull : (bound >> (lane + 1));
+                    const int len = above ? __ffsll((long long)above) : 64 - lane;
+                    atomicAdd(&hist[b], (u32)len);
+                }
             }
         }
         __syncthreads();
