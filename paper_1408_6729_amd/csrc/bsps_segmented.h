@@ -303,30 +303,40 @@ __global__ __launch_bounds__(SL_NT) void k_sl_rank(const K* B, const u32* seg, c
     if (t == 0) wst[0] = wst[1] = 0;
     __syncthreads();
     unsigned long long miss = 0, dist = 0;
-    for (u32 i0 = 0; i0 < m; i0 += SL_NT) {
-        const u32 i = i0 + t;
-        const bool valid = i < m;
-        int bk = p;
-        if (valid) {
-            const K key = B[start + i];
-            const typename SplitLds<K>::Q q = SplitLds<K>::query(key, start + i);
-            const float x = model_x<K>(key, mh);
-            const float2 ce = lf2[model_leaf(x, mh)];
-            const float f = fminf(fmaxf((ce.x * x + ce.y) * (float)p, 0.0f), (float)(p - 1));
-            const int pred = (int)f;
-            bk = pred;
-            while (bk > 0 && !S.lt(bk - 1, q)) bk--;
-            while (bk < p - 1 && S.lt(bk, q)) bk++;
-            miss += bk != pred;
-            dist += (unsigned long long)(bk > pred ? bk - pred : pred - bk);
+    constexpr int RG = sizeof(K) == 8 ? 4 : 8;  // keys whose loads are issued together
+    for (u32 i0 = 0; i0 < m; i0 += SL_NT * RG) {
+        K kg[RG];
+#pragma unroll
+        for (int u = 0; u < RG; u++) {
+            const u32 i = i0 + (u32)u * SL_NT + t;
+            kg[u] = i < m ? B[start + i] : (K)0;
         }
-        const int bprev = __shfl_up(bk, 1, 64);
-        const bool head = valid && (lane == 0 || bprev != bk);
-        const unsigned long long bound = __ballot(head || !valid);
-        if (head) {
-            const unsigned long long above = lane == 63 ? 0ull : (bound >> (lane + 1));
-            const int len = above ? __ffsll((long long)above) : 64 - lane;
-            atomicAdd(&hist[bk], (u32)len);
+#pragma unroll
+        for (int u = 0; u < RG; u++) {
+            const u32 i = i0 + (u32)u * SL_NT + t;
+            const bool valid = i < m;
+            int bk = p;
+            if (valid) {
+                const K key = kg[u];
+                const typename SplitLds<K>::Q q = SplitLds<K>::query(key, start + i);
+                const float x = model_x<K>(key, mh);
+                const float2 ce = lf2[model_leaf(x, mh)];
+                const float f = fminf(fmaxf((ce.x * x + ce.y) * (float)p, 0.0f), (float)(p - 1));
+                const int pred = (int)f;
+                bk = pred;
+                while (bk > 0 && !S.lt(bk - 1, q)) bk--;
+                while (bk < p - 1 && S.lt(bk, q)) bk++;
+                miss += bk != pred;
+                dist += (unsigned long long)(bk > pred ? bk - pred : pred - bk);
+            }
+            const int bprev = __shfl_up(bk, 1, 64);
+            const bool head = valid && (lane == 0 || bprev != bk);
+            const unsigned long long bound = __ballot(head || !valid);
+            if (head) {
+                const unsigned long long above = lane == 63 ? 0ull : (bound >> (lane + 1));
+                const int len = above ? __ffsll((long long)above) : 64 - lane;
+                atomicAdd(&hist[bk], (u32)len);
+            }
         }
     }
     atomicAdd(&wst[0], miss);
