@@ -266,6 +266,7 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
     __shared__ SortSmem<NT, (int)sizeof(K), IT> sm;
     __shared__ u32 spre[MAXR + 1];
+    __shared__ u32 sbase[MAXR];  // first sample index of each run
     __shared__ u32 sh_nb, sh_base;
     u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x, g = blockIdx.x, R = a.R;
@@ -281,6 +282,7 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     u32 ex = block_excl_scan<NT>(mys, totS, sm.wsum);
     for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
         spre[r] = ex;
+        sbase[r] = sd[r * 4 + 0];
         ex += sd[r * 4 + 1];
     }
     if (t == 0) spre[R] = totS;
@@ -326,26 +328,44 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     if (N == 0 || gb >= a.S) return;
     for (u32 i = t; i <= nb; i += NT) a.slot_group[gb + i] = g;
     if (nb == 0) return;
-    // load the subsample: element i is concatenated sample index (i+1)*f - 1
+    // load the subsample: element i is concatenated sample index (i+1)*f - 1.
+    // A thread's elements are consecutive, so the run holding its first one is
+    // found by bisection and the rest by walking; every sample index is formed
+    // first and all loads are then issued together.
     K mn = KeyMax<K>::v, mx = 0;
     u32 v[IT], rank[IT];
     K key[IT];
-#pragma unroll
-    for (int j = 0; j < IT; j++) {
-        const u32 i = (u32)(t * IT + j);
-        v[j] = 0;
-        key[j] = 0;
-        if (i < Sg) {
-            const u32 c = (i + 1) * f - 1;
-            int lo = 0, hi = R;  // largest r with spre[r] <= c (a run with samples)
+    {
+        const u32 i0 = (u32)(t * IT);
+        int r = 0;
+        if (i0 < Sg) {
+            const u32 c0 = (i0 + 1) * f - 1;
+            int lo = 0, hi = R;  // largest r with spre[r] <= c0 (a run with samples)
             while (hi - lo > 1) {
-                int mid = (lo + hi) >> 1;
-                if (spre[mid] <= c) lo = mid; else hi = mid;
+                const int mid = (lo + hi) >> 1;
+                if (spre[mid] <= c0) lo = mid; else hi = mid;
             }
-            key[j] = a.smp[sd[lo * 4 + 0] + (c - spre[lo])];
-            v[j] = c;
-            mn = key[j] < mn ? key[j] : mn;
-            mx = key[j] > mx ? key[j] : mx;
+            r = lo;
+        }
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            const u32 i = i0 + (u32)j;
+            v[j] = 0;
+            key[j] = 0;
+            if (i < Sg) {
+                const u32 c = (i + 1) * f - 1;
+                while (spre[r + 1] <= c) r++;  // stops at r < R: spre[R] = Sraw > c
+                key[j] = (K)(sbase[r] + (c - spre[r]));
+                v[j] = c;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            if (i0 + (u32)j < Sg) {
+                key[j] = a.smp[(u32)key[j]];
+                mn = key[j] < mn ? key[j] : mn;
+                mx = key[j] > mx ? key[j] : mx;
+            }
         }
     }
     block_minmax<NT, K>(mn, mx, sm.red64);
