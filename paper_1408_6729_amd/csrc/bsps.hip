@@ -129,7 +129,8 @@ template <typename K> constexpr u32 tileT() { return (u32)(Shape<K>::NT * Shape<
 template <typename K>
 struct MwmBufs {
     u32 *run_start, *run_len, *out_base, *sdesc, *counters, *slot_group, *grp_base, *grp_nb, *bpos, *cuts;
-    u32 *below, *wfirst, *wlast;
+    u32* below;
+    uint4* witem;
     K* bkey;
     u32 S;
     int G, R;
@@ -153,8 +154,7 @@ void carve_mwm(Carver& c, MwmBufs<K>& m, int G, int R, u64 n, u32 tavg) {
     m.bpos = c.take<u32>(m.S);
     m.cuts = c.take<u32>((u64)m.S * R);
     m.below = c.take<u32>(m.S);
-    m.wfirst = c.take<u32>(m.S);
-    m.wlast = c.take<u32>(m.S);
+    m.witem = c.take<uint4>(2 * (u64)m.S);
 }
 
 template <typename K>
@@ -168,7 +168,7 @@ MwmArgs<K> mwm_args(const MwmBufs<K>& m, const K* src, const u32* srcv, K* dst, 
     a.slot_count = m.counters; a.oversize = m.counters + 1; a.work = m.counters + 2;
     a.slot_group = m.slot_group; a.grp_base = m.grp_base; a.grp_nb = m.grp_nb;
     a.bkey = m.bkey; a.bpos = m.bpos; a.cuts = m.cuts; a.below = m.below; a.S = m.S;
-    a.wfirst = m.wfirst; a.wlast = m.wlast; a.nwork = m.counters + 4;
+    a.witem = m.witem; a.nwork = m.counters + 4;
     a.out_dt = out_dt; a.osmp = osmp; a.oys = oys; a.ospb = ospb;
     return a;
 }

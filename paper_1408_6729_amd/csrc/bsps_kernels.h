@@ -77,8 +77,9 @@ struct MwmArgs {
     u32* bpos;
     u32* cuts;             // [S*R]
     u32* below;            // [S] keys of the group at or below each boundary (sum of its cuts)
-    u32* wfirst;           // [S] work items of the merge: first and last slot of a run of
-    u32* wlast;            //     consecutive chunks of one group that together fit the cap
+    uint4* witem;          // [2S] work items of the merge, runs of consecutive chunks of one
+                           // group that together fit the cap: {first slot, last slot, group,
+                           // first chunk}, {last chunk, group boundaries, group output base, 0}
     u32* nwork;            // [1] work items
     u32 S;                 // slot capacity
     int out_dt;            // BSPS_DT_NONE: keep order keys; else write raw keys of this dtype
@@ -509,7 +510,11 @@ __global__ __launch_bounds__(PLAN_NT) void k_mwm_plan(MwmArgs<K> a) {
     __shared__ u32 wsum[PLAN_NT / 64 + 2];
     __shared__ u32 sh_n, sh_base;
     const int g = blockIdx.x, t = threadIdx.x, R = a.R;
-    const u32 gb = a.grp_base[g], nb = a.grp_nb[g];
+    const u32 gb = a.grp_base[g], nb = a.grp_nb[g], ob = a.out_base[g];
+    auto item = [&](u32 i, u32 cf, u32 cl) {
+        a.witem[2 * (i64)i] = make_uint4(gb + cf, gb + cl, (u32)g, cf);
+        a.witem[2 * (i64)i + 1] = make_uint4(cl, nb, ob, 0u);
+    };
     u32 myn = 0;
     for (int r = t; r < R; r += PLAN_NT) myn += a.run_len[(i64)g * R + r];
     u32 N;
@@ -519,10 +524,7 @@ __global__ __launch_bounds__(PLAN_NT) void k_mwm_plan(MwmArgs<K> a) {
     if (nch > PLAN_MAXC) {  // not combined: one item per chunk
         if (t == 0) sh_base = atomicAdd(a.nwork, nch);
         __syncthreads();
-        for (u32 c = t; c < nch; c += PLAN_NT) {
-            a.wfirst[sh_base + c] = gb + c;
-            a.wlast[sh_base + c] = gb + c;
-        }
+        for (u32 c = t; c < nch; c += PLAN_NT) item(sh_base + c, c, c);
         return;
     }
     for (u32 c = t; c < nb; c += PLAN_NT) P[c] = a.below[gb + c];
@@ -558,10 +560,7 @@ __global__ __launch_bounds__(PLAN_NT) void k_mwm_plan(MwmArgs<K> a) {
         }
     }
     __syncthreads();
-    for (u32 i = t; i < sh_n; i += PLAN_NT) {
-        a.wfirst[sh_base + i] = gb + itf[i];
-        a.wlast[sh_base + i] = gb + itl[i];
-    }
+    for (u32 i = t; i < sh_n; i += PLAN_NT) item(sh_base + i, itf[i], itl[i]);
 }
 
 // ======================================================================= MWM: chunk sort
@@ -688,28 +687,31 @@ struct MergeSmem {
 };
 
 template <typename K, bool HASV>
-__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 slot, const u32 slot_last,
+__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4 wi0, const uint4 wi1,
                                                 MergeSmem<K>& S);
 
-// Persistent merge: workgroups take work items (runs of chunks) one after another.
+// Persistent merge: workgroups take work items (runs of chunks) one after
+// another; the next item is claimed while the current one is merged.
 template <typename K, bool HASV>
 __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_mwm_merge(MwmArgs<K> a) {
     __shared__ MergeSmem<K> S;
     const u32 nwork = min(a.S, *a.nwork);
+    if (threadIdx.x == 0) S.slot = atomicAdd(a.work, 1u);
+    __syncthreads();
+    u32 w = S.slot;
     for (;;) {
-        if (threadIdx.x == 0) S.slot = atomicAdd(a.work, 1u);
-        __syncthreads();
-        const u32 w = S.slot;
-        __syncthreads();
+        __syncthreads();  // every thread has read S.slot
         if (w >= nwork) break;
-        mwm_merge_chunk<K, HASV>(a, a.wfirst[w], a.wlast[w], S);
+        if (threadIdx.x == 0) S.slot = atomicAdd(a.work, 1u);
+        mwm_merge_chunk<K, HASV>(a, a.witem[2 * (i64)w], a.witem[2 * (i64)w + 1], S);
         __syncthreads();
+        w = S.slot;
     }
 }
 
 // Merges the chunks slot .. slot_last of one group (one LDS sort).
 template <typename K, bool HASV>
-__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 slot, const u32 slot_last,
+__device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4 wi0, const uint4 wi1,
                                                 MergeSmem<K>& S) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
     auto& sm = S.sm;
@@ -719,10 +721,8 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x, R = a.R;
     PHASE_START;
-    const u32 g = uniform(a.slot_group[uniform(slot)]);
-    const u32 c = uniform(slot - a.grp_base[g]);
-    const u32 cl = uniform(slot_last - a.grp_base[g]);
-    const u32 nb = uniform(a.grp_nb[g]);
+    const u32 slot = uniform(wi0.x), slot_last = uniform(wi0.y), g = uniform(wi0.z), c = uniform(wi0.w);
+    const u32 cl = uniform(wi1.x), nb = uniform(wi1.y), obase = uniform(wi1.z);
     const u32* lorow = a.cuts + (i64)(slot - 1) * R;
     const u32* hirow = a.cuts + (i64)slot_last * R;
     const u32* rl = a.run_len + (i64)g * R;
@@ -750,7 +750,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     __syncthreads();
     u32 LO;
     (void)block_excl_scan<NT>(mylo, LO, sm.wsum);
-    const u32 out = uniform(a.out_base[g] + LO);
+    const u32 out = uniform(obase + LO);
     if (N == 0) return;
     PHASE(0);
     if (N > a.cap) {
@@ -889,7 +889,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const u32 s
     block_minmax<NT, K>(mn, mx, sm.red64);
     PHASE(2);
     const int nbits = uniform(bitwidth64((u64)(mx - mn)));
-    const u32 gstart = uniform(a.out_base[g]);
+    const u32 gstart = obase;
     const u32 osh = a.oys ? (u32)(__ffs(a.oys) - 1) : 0u;
     const u32 om = (1u << osh) - 1;
     K* dst = a.dst + out;
