@@ -87,7 +87,7 @@ template <> struct Shape<u64> { static constexpr int NT = BSPS_NT64, IT = BSPS_I
 #define BSPS_DIG_RECOMPUTE 1  // recompute digits instead of keeping them in registers
 #endif
 #ifndef BSPS_WG_PER_CU
-#define BSPS_WG_PER_CU 2      // occupancy target of the sorting kernels (workgroups per CU)
+#define BSPS_WG_PER_CU 2      // occupancy target of the sorting kernels: minimum waves per SIMD (launch bound)
 #endif
 
 #ifndef BSPS_RB
