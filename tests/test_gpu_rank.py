@@ -71,6 +71,42 @@ def test_scatter_route_without_diagnostics(ora, dev, p, bucketing):
     assert np.array_equal(v.cpu().numpy().view(np.uint32), ref["values"])
 
 
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("bucketing", [0, 1])
+def test_scatter_route_random(ora, dev, dtype, bucketing):
+    """Seeded sweep of the scatter route: random n, p (odd and even, up to
+    1024), s, leaf count, variant and payload; sorted keys, payloads and the
+    count matrix equal the oracle's (Figure SortD steps 9-12)."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    rng = np.random.default_rng(11 + 7 * bucketing + {"int32": 0, "int64": 1, "float32": 2}[dtype])
+    for trial in range(4):
+        n = int(rng.integers(2, 300000))
+        p = int(rng.integers(2, min(n, 1024) + 1))
+        s = int(rng.integers(1, 40))
+        variant = trial % 2
+        if variant == 1 and s * p - 1 > n:
+            s = max(1, (n + 1) // p)
+        leaves = int(rng.integers(1, 4097))
+        if dtype == "float32":
+            keys = W.lognormal_f32(n, seed=200 + trial, zeros=min(64, n // 4))
+        else:
+            keys = W.random_keys(n, dtype, seed=200 + trial, distinct=None if trial % 2 else int(rng.integers(1, 5000)))
+        kv = trial % 2 == 0
+        vals = np.arange(n, dtype=np.uint32) if kv else None
+        ref = ora.sort(keys, p, s, variant, trial + 1, vals)
+        t = _t(keys, dev)
+        v = _t(vals.view(np.int32), dev) if kv else None
+        st = bsps.sort_(t, p, s, variant, seed=trial + 1, values=v, bucketing=bucketing, route=bsps.ROUTE_SCATTER,
+                        leaves=leaves, stats=True)
+        torch.cuda.synchronize()
+        case = f"n={n} p={p} s={s} variant={variant} leaves={leaves} kv={kv}"
+        assert np.array_equal(_bits(t.cpu().numpy()), _bits(ref["keys"])), case
+        if kv:
+            assert np.array_equal(v.cpu().numpy().view(np.uint32), ref["values"]), case
+        assert np.array_equal(st["count_matrix"], ref["C"]), case
+
+
 @pytest.mark.parametrize("p", [2, 100, 1024])
 @pytest.mark.parametrize("bucketing", [0, 1])
 def test_rank_entry_point(ora, dev, p, bucketing):
