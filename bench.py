@@ -20,7 +20,8 @@ Beside it (in "detail"), each timed the same way:
 
 Prints one JSON line: throughput in keys/s, the roofline of the dominant
 kernel (algorithmic bytes over its HIP-event-timed duration against the
-8 TB/s HBM peak), and the CPU oracle timed on a bounded sample.
+8 TB/s HBM peak, and against the rate the library's reference copy kernel
+attains on the same array), and the CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c0,learned,int64_kv,segmented]
 """
@@ -178,6 +179,24 @@ def bench_c0(bsps, torch, W, args, timer):
         ok = is_sorted(torch, out)
         res[name] = {"ms": ms, "keys_per_s": n / (ms / 1e3), "sorted": ok, "stages": stages}
         log(f"c0 {name}: {ms:.3f} ms/step, {n / ms / 1e6:.2f} Gkeys/s, sorted={ok}")
+    # attainable bandwidth: the library's reference copy kernel on the same
+    # 2^28-key array, HIP events on the stream it runs on
+    dst = torch.empty_like(base)
+    for _ in range(3):
+        bsps.stream_copy(base, dst)
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bsps.stream_copy(base, dst)
+    e1.record()
+    e1.synchronize()
+    cms = e0.elapsed_time(e1) / reps
+    cbytes = 2 * base.numel() * base.element_size()
+    ok = bool(torch.equal(dst, base))
+    res["stream_copy"] = {"ms": cms, "gbs": cbytes / (cms / 1e3) / 1e9, "bytes_moved": cbytes, "exact": ok}
+    log(f"c0 stream copy: {cms:.3f} ms, {cbytes / cms / 1e6:.0f} GB/s, exact={ok}")
+    del dst
     return n, p, s, res
 
 
@@ -306,7 +325,7 @@ def main():
     timer = Timer(bsps)
     n, p, s, c0 = bench_c0(bsps, torch, W, args, timer)
     det = c0["det"]
-    detail = {"det": det, "ran": c0["ran"]}
+    detail = {"det": det, "ran": c0["ran"], "stream_copy": c0["stream_copy"]}
     if "learned" in only:
         detail["learned_vs_splitter"] = bench_learned(bsps, torch, W, args, timer)
     if "int64_kv" in only:
@@ -323,7 +342,8 @@ def main():
     workload = "C0"
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom, workload), "kernel": dom,
-                "alg_bytes_per_launch": alg_bytes}
+                "alg_bytes_per_launch": alg_bytes, "attainable_copy_gbs": c0["stream_copy"]["gbs"],
+                "frac_of_attainable": achieved / c0["stream_copy"]["gbs"]}
     detail["floor_fraction_6w"] = (6 * 4 * n) / (det["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
     detail["floor_note"] = "6 * 4 bytes per key (three permuting passes) / time / 8 TB/s"
     cpu = None

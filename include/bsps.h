@@ -204,6 +204,14 @@ bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int3
                             int32_t leaves, const void* model, int32_t* out_leaf, float* out_grad,
                             float* out_gram, float* out_loss, void* ws, size_t ws_bytes, void* stream);
 
+/* Reference copy used to measure the attainable HBM bandwidth next to the
+ * sort's kernels: copies `bytes` from src to dst (device pointers, both
+ * 16-byte aligned, not overlapping; bytes a multiple of 16) with 16-byte
+ * nontemporal vector loads and stores, asynchronously on `stream`. EINVAL for
+ * misaligned pointers or sizes (checked on the host before any HIP call);
+ * EUNSUPPORTED above 2^31 workgroups (32 TiB). */
+bsps_status bsps_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Human-readable name of a status code (static storage). */
 const char* bsps_status_string(int32_t status);
 /* Format of the tuning table accepted by bsps_sort_segmented (static storage). */

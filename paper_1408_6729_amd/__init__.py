@@ -81,6 +81,8 @@ def _load():
     L.bsps_segmented_workspace_bytes.argtypes = [vp, i32, i32, i32, ct.c_char_p]
     L.bsps_tuning_format.restype = ct.c_char_p
     L.bsps_tuning_format.argtypes = []
+    L.bsps_stream_copy.restype = i32
+    L.bsps_stream_copy.argtypes = [vp, vp, sz, vp]
     L.bsps_release_cache.restype = None
     L.bsps_release_cache.argtypes = []
     L.bsps_timing.argtypes = [ct.c_int]
@@ -327,6 +329,20 @@ def sort_segmented_(keys, offsets, values=None, tuning: str | None = None, stats
 
 def tuning_format() -> str:
     return _lib.bsps_tuning_format().decode()
+
+
+def stream_copy(src, dst) -> None:
+    """Copies the contiguous CUDA tensor src into dst (same number of bytes, a
+    multiple of 16, 16-byte aligned) with the library's reference copy kernel,
+    on the current stream: the attainable-bandwidth yardstick of the bench."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("stream_copy: sizes differ")
+    code = _lib.bsps_stream_copy(ct.c_void_p(src.data_ptr()), ct.c_void_p(dst.data_ptr()), nbytes,
+                                 ct.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if code:
+        raise BspsError(code, "bsps_stream_copy")
 
 
 def release_cache() -> None:

@@ -1432,6 +1432,18 @@ const char* bsps_status_string(int32_t status) {
     }
 }
 
+bsps_status bsps_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst || (bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return BSPS_EINVAL;
+    if (bytes == 0) return BSPS_OK;
+    const u64 n16 = bytes / 16;
+    const u64 grid = cdiv(n16, (u64)COPY_NT * COPY_PER);
+    if (grid > 0x7fffffffull) return BSPS_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_stream_copy, dim3((u32)grid), dim3(COPY_NT), 0, (hipStream_t)stream, (const v4u32*)src,
+                       (v4u32*)dst, n16);
+    LAUNCH_OK();
+    return BSPS_OK;
+}
+
 void bsps_release_cache(void) {
     for (auto& kv : g_graphs.execs) (void)hipGraphExecDestroy(kv.second);
     g_graphs.execs.clear();

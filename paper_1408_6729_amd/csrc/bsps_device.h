@@ -99,6 +99,8 @@ constexpr int HALF = RADIX / 2;       // digits d and d + HALF share one 32-bit 
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }  // one pad word per 32
 
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+
 // The digit counters and the key exchange buffer are never live at the same
 // time (ranking ends with a barrier before keys are scattered), so they share
 // one LDS region: `u` holds HALF*NT counter words or NT*IT exchange slots of

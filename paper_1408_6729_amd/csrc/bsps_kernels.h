@@ -49,6 +49,23 @@ __device__ unsigned long long g_phase[16];
 #define PHASE_START do {} while (0)
 #endif
 
+// Reference copy (attainable HBM bandwidth): every workgroup copies 1024
+// consecutive 16-byte vectors, four per thread, position-striped, with
+// nontemporal loads and stores (the data is not reused).
+constexpr int COPY_NT = 256, COPY_PER = 4;
+
+__global__ __launch_bounds__(COPY_NT) void k_stream_copy(const v4u32* __restrict__ src, v4u32* __restrict__ dst,
+                                                         u64 n16) {
+    const u64 b = (u64)blockIdx.x * (COPY_NT * COPY_PER) + threadIdx.x;
+    v4u32 v[COPY_PER];
+#pragma unroll
+    for (int k = 0; k < COPY_PER; k++)
+        if (b + (u64)k * COPY_NT < n16) v[k] = __builtin_nontemporal_load(src + b + (u64)k * COPY_NT);
+#pragma unroll
+    for (int k = 0; k < COPY_PER; k++)
+        if (b + (u64)k * COPY_NT < n16) __builtin_nontemporal_store(v[k], dst + b + (u64)k * COPY_NT);
+}
+
 // ======================================================================= tables
 
 template <typename K>

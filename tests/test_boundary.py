@@ -107,3 +107,13 @@ def test_segmented_validation(bsps):
     # a segment that needs more than 1024 blocks of one tile
     big = np.array([0, 16384 * 1024 + 1], dtype=np.int64)
     assert bsps.segmented_workspace_bytes(big, 0, False) == 0
+
+
+def test_stream_copy_checked_before_device(bsps):
+    """The reference copy rejects misaligned pointers and sizes on the host."""
+    f = bsps.lib.bsps_stream_copy
+    assert f(ct.c_void_p(4096), ct.c_void_p(8192), 4096 + 8, None) == bsps.EINVAL  # size not a multiple of 16
+    assert f(ct.c_void_p(4096 + 4), ct.c_void_p(8192), 4096, None) == bsps.EINVAL  # source misaligned
+    assert f(ct.c_void_p(4096), ct.c_void_p(8192 + 8), 4096, None) == bsps.EINVAL  # destination misaligned
+    assert f(None, ct.c_void_p(8192), 4096, None) == bsps.EINVAL
+    assert f(ct.c_void_p(4096), ct.c_void_p(8192), 0, None) == bsps.OK  # nothing to copy, no device call

@@ -140,3 +140,16 @@ def test_float_special_values(ora, dev):
     keys = W.lognormal_f32(1 << 20, zeros=1024)
     keys[:7] = np.array([np.inf, -np.inf, -0.0, 0.0, 1e-45, -1e-45, 3.4e38], dtype=np.float32)
     _check(ora, dev, keys, 64, 16, ora.RAN, seed=2)
+
+
+def test_stream_copy_exact(dev):
+    """The reference copy kernel behind the bench's attainable-bandwidth line
+    copies every byte, including a tail shorter than one grid stride."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    for n in (4, 1 << 20, (1 << 22) + 12):
+        src = torch.randint(-2**31, 2**31 - 1, (n,), dtype=torch.int32, device=dev)
+        dst = torch.zeros_like(src)
+        bsps.stream_copy(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst), n
