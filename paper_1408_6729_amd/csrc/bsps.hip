@@ -608,8 +608,12 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         {
             StageScope sc(ST_COUNT, st);
             const u64 ncnt = (u64)(p + 1) * p;
-            hipLaunchKernelGGL((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pp,
-                               P.cntT);
+            if (P.spb > 0 && P.spb <= (u32)COUNT_SMAX)
+                hipLaunchKernelGGL((k_count_staged<K>), dim3(p), dim3(COUNT_NT), 0, st, P.B, n, p, P.pk, P.pp, P.bsmp,
+                                   P.spb, kSampleStride, P.cntT);
+            else
+                hipLaunchKernelGGL((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pp,
+                                   P.cntT);
             LAUNCH_OK();
         }
         // A5: prefix sums -> runs of every bucket. A6: merge them (routing fused).

@@ -1023,6 +1023,45 @@ __global__ void k_count(const K* B, i64 n, int p, const K* pk, const u32* pp, u3
     cntT[idx] = res;
 }
 
+// The same counts with one workgroup per block: the block's samples (every
+// ys-th key, at block positions (j+1)*ys - 1; floor(mk/ys) of them) are staged
+// in LDS and each splitter is bisected there, so only the last bisection,
+// inside one sample stride, reads the block in global memory. For blocks of
+// at most COUNT_SMAX samples.
+constexpr int COUNT_NT = 256, COUNT_SMAX = 8192;
+
+template <typename K>
+__global__ __launch_bounds__(COUNT_NT) void k_count_staged(const K* B, i64 n, int p, const K* pk, const u32* pp,
+                                                           const K* bsmp, u32 spb, u32 ys, u32* cntT) {
+    __shared__ K ls[COUNT_SMAX];
+    const int k = blockIdx.x, t = threadIdx.x;
+    const i64 st = blk_start(n, p, k), mk = blk_start(n, p, k + 1) - st;
+    const u32 ns = min((u32)(mk / ys), spb);
+    for (u32 j = t; j < ns; j += COUNT_NT) ls[j] = bsmp[(i64)k * spb + j];
+    __syncthreads();
+    for (int i = t; i <= p; i += COUNT_NT) {
+        u32 res;
+        if (i == 0) res = 0;
+        else if (i == p) res = (u32)mk;
+        else {
+            const K sk = pk[i - 1];
+            const u32 sp = pp[i - 1];
+            u32 lo = 0, hi = ns;  // samples <= the splitter
+            while (lo < hi) {
+                const u32 mid = (lo + hi) >> 1;
+                if (rec_le<K>(ls[mid], (u32)(st + (u64)(mid + 1) * ys - 1), sk, sp)) lo = mid + 1; else hi = mid;
+            }
+            u32 wlo = lo * ys, whi = lo < ns ? (lo + 1) * ys - 1 : (u32)mk;
+            while (wlo < whi) {
+                const u32 mid = (wlo + whi) >> 1;
+                if (rec_le<K>(B[st + mid], (u32)(st + mid), sk, sp)) wlo = mid + 1; else whi = mid;
+            }
+            res = wlo;
+        }
+        cntT[(i64)i * p + k] = res;
+    }
+}
+
 // Bucket merge tables: group = bucket i, run = block k. One workgroup per
 // bucket. out_base[i] = sum_k cntT[i][k] (keys in smaller buckets). Samples of
 // the runs are the block samples every yb-th key that fall inside the run.
