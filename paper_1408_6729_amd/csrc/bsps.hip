@@ -129,8 +129,8 @@ template <typename K> constexpr u32 tileT() { return (u32)(Shape<K>::NT * Shape<
 template <typename K>
 struct MwmBufs {
     u32 *run_start, *run_len, *out_base, *sdesc, *counters, *slot_group, *grp_base, *grp_nb, *bpos, *cuts;
-    u32* below;
-    uint4* witem;
+    u32 *below, *heavy;
+    uint4 *witem, *gpar;
     K* bkey;
     u32 S;
     int G, R;
@@ -146,7 +146,7 @@ void carve_mwm(Carver& c, MwmBufs<K>& m, int G, int R, u64 n, u32 tavg) {
     m.run_len = c.take<u32>((u64)G * R);
     m.out_base = c.take<u32>(G);
     m.sdesc = c.take<u32>((u64)G * R * 4);
-    m.counters = c.take<u32>(8);  // slots, oversize, merge claims, largest oversize, work items
+    m.counters = c.take<u32>(8);  // slots, oversize, merge claims, largest oversize, work items, listed groups
     m.slot_group = c.take<u32>(m.S);
     m.grp_base = c.take<u32>(G);
     m.grp_nb = c.take<u32>(G);
@@ -155,6 +155,8 @@ void carve_mwm(Carver& c, MwmBufs<K>& m, int G, int R, u64 n, u32 tavg) {
     m.cuts = c.take<u32>((u64)m.S * R);
     m.below = c.take<u32>(m.S);
     m.witem = c.take<uint4>(2 * (u64)m.S);
+    m.heavy = c.take<u32>(G);
+    m.gpar = c.take<uint4>(2 * (u64)G);
 }
 
 template <typename K>
@@ -169,6 +171,7 @@ MwmArgs<K> mwm_args(const MwmBufs<K>& m, const K* src, const u32* srcv, K* dst, 
     a.slot_group = m.slot_group; a.grp_base = m.grp_base; a.grp_nb = m.grp_nb;
     a.bkey = m.bkey; a.bpos = m.bpos; a.cuts = m.cuts; a.below = m.below; a.S = m.S;
     a.witem = m.witem; a.nwork = m.counters + 4;
+    a.heavy = m.heavy; a.nheavy = m.counters + 5; a.gpar = m.gpar;
     a.out_dt = out_dt; a.osmp = osmp; a.oys = oys; a.ospb = ospb;
     return a;
 }
@@ -204,7 +207,10 @@ bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     const int cus = device_cus();
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.slot_count, 8);
     LAUNCH_OK();
-    hipLaunchKernelGGL((k_mwm_pick<K>), dim3(a.G), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL((k_mwm_size<K>), dim3(a.G), dim3(SIZE_NT), 0, st, a);
+    LAUNCH_OK();
+    // the groups with boundaries only (listed by k_mwm_size), in loops
+    hipLaunchKernelGGL((k_mwm_pick<K>), dim3((u32)std::min<u64>(a.G, (u64)cus * 2)), dim3(NT), 0, st, a);
     LAUNCH_OK();
     // one wave per (group, run); with few runs the boundaries are split over
     // gridDim.y waves so that the launch still holds some 8K waves
@@ -215,7 +221,7 @@ bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     hipLaunchKernelGGL((k_mwm_below<K>), dim3((u32)std::min<u64>(cdiv(a.S, 4), (u64)cus * 16)), dim3(256), 0, st,
                        a);
     LAUNCH_OK();
-    hipLaunchKernelGGL((k_mwm_plan<K>), dim3(a.G), dim3(PLAN_NT), 0, st, a);
+    hipLaunchKernelGGL((k_mwm_plan<K>), dim3((u32)std::min<u64>(a.G, (u64)cus * 4)), dim3(PLAN_NT), 0, st, a);
     LAUNCH_OK();
 #ifndef BSPS_MERGE_WGS_PER_CU
 #define BSPS_MERGE_WGS_PER_CU 2

@@ -98,6 +98,9 @@ struct MwmArgs {
                            // group that together fit the cap: {first slot, last slot, group,
                            // first chunk}, {last chunk, group boundaries, group output base, 0}
     u32* nwork;            // [1] work items
+    u32* heavy;            // [G] groups with chunk boundaries (listed by k_mwm_size)
+    u32* nheavy;           // [1] their number
+    uint4* gpar;           // [2G] per listed group: {f, Sg, q, dsh}, {N, 0, 0, 0} (see k_mwm_size)
     u32 S;                 // slot capacity
     int out_dt;            // BSPS_DT_NONE: keep order keys; else write raw keys of this dtype
     K* osmp;               // output samples every oys-th key of each group (or NULL)
@@ -273,41 +276,35 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
 
 // ======================================================================= MWM: pick boundaries
 
-// One workgroup per group: sort (a regular subsample of) the group's samples
-// and keep every q-th as a chunk boundary. The chunk target leaves room for
-// the spread of chunk sizes: a chunk holds q samples' worth of keys plus, per
-// run, less than one sample stride y more or fewer, so its size varies by
-// about y * sqrt(R / 3); the target is cap minus four such spreads (but at
-// least a.tavg, the floor the slot capacity was sized for).
+// Chunking of every group, one light workgroup per group: the group's size N
+// and sample count, the subsample factor f (at most T subsamples are sorted),
+// the chunk target and the boundary count nb (below). Slots are allocated and
+// mapped to the group; a group without boundaries gets its one work item here,
+// the others are listed for k_mwm_pick and k_mwm_plan with their parameters.
+//
+// The chunk target leaves room for the spread of chunk sizes: a chunk holds q
+// samples' worth of keys plus, per run, less than one sample stride y more or
+// fewer, so its size varies by about y * sqrt(R / 3); the target is cap minus
+// four such spreads (but at least a.tavg, the floor the slot capacity was
+// sized for).
+constexpr int SIZE_NT = 256;
+
 template <typename K>
-__global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
-    constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
-    __shared__ SortSmem<NT, (int)sizeof(K), IT> sm;
-    __shared__ u32 spre[MAXR + 1];
-    __shared__ u32 sbase[MAXR];  // first sample index of each run
-    __shared__ u32 sh_nb, sh_base;
-    u32* vex = sm.template ex<u32>();
+__global__ __launch_bounds__(SIZE_NT) void k_mwm_size(MwmArgs<K> a) {
+    constexpr int T = Shape<K>::NT * Shape<K>::IT;
+    __shared__ u32 wsum[SIZE_NT / 64 + 2];
+    __shared__ u32 sh_base;
     const int t = threadIdx.x, g = blockIdx.x, R = a.R;
     const u32* sd = a.sdesc + (i64)g * R * 4;
-    // exclusive prefix of the runs' sample counts (runs in order), group size
-    const int RPT = (R + NT - 1) / NT;
     u32 mys = 0, myn = 0;
-    for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
+    for (int r = t; r < R; r += SIZE_NT) {
         mys += sd[r * 4 + 1];
         myn += a.run_len[(i64)g * R + r];
     }
-    u32 totS;
-    u32 ex = block_excl_scan<NT>(mys, totS, sm.wsum);
-    for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
-        spre[r] = ex;
-        sbase[r] = sd[r * 4 + 0];
-        ex += sd[r * 4 + 1];
-    }
-    if (t == 0) spre[R] = totS;
+    u32 Sraw, N;
+    (void)block_excl_scan<SIZE_NT>(mys, Sraw, wsum);
     __syncthreads();
-    u32 totN;
-    (void)block_excl_scan<NT>(myn, totN, sm.wsum);
-    const u32 Sraw = totS, N = totN;
+    (void)block_excl_scan<SIZE_NT>(myn, N, wsum);
     u32 nb = 0, f = 1, Sg = 0, q = 1, dsh = 0;
     if (N > a.cap && Sraw > 0) {
         f = (Sraw + T - 1) / T;
@@ -336,90 +333,132 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
         u32 b = slots ? atomicAdd(a.slot_count, slots) : 0u;
         if (b + slots > a.S) { slots = 0; b = a.S; }  // cannot happen: capacity n/tavg + 2G + 1
         sh_base = b;
-        sh_nb = slots ? nb : 0u;
         a.grp_base[g] = b;
         a.grp_nb[g] = slots ? nb : 0u;
+        if (slots && nb > 0) {
+            const u32 h = atomicAdd(a.nheavy, 1u);
+            a.heavy[h] = (u32)g;
+            a.gpar[2 * (i64)g] = make_uint4(f, Sg, q, dsh);
+            a.gpar[2 * (i64)g + 1] = make_uint4(N, 0u, 0u, 0u);
+        } else if (slots) {  // one chunk: its work item
+            const u32 w = atomicAdd(a.nwork, 1u);
+            a.witem[2 * (i64)w] = make_uint4(b, b, (u32)g, 0u);
+            a.witem[2 * (i64)w + 1] = make_uint4(0u, 0u, a.out_base[g], 0u);
+        }
     }
     __syncthreads();
     const u32 gb = sh_base;
-    nb = sh_nb;
     if (N == 0 || gb >= a.S) return;
-    for (u32 i = t; i <= nb; i += NT) a.slot_group[gb + i] = g;
-    if (nb == 0) return;
-    // load the subsample: element i is concatenated sample index (i+1)*f - 1.
-    // A thread's elements are consecutive, so the run holding its first one is
-    // found by bisection and the rest by walking; every sample index is formed
-    // first and all loads are then issued together.
-    K mn = KeyMax<K>::v, mx = 0;
-    u32 v[IT], rank[IT];
-    K key[IT];
-    {
-        const u32 i0 = (u32)(t * IT);
-        int r = 0;
-        if (i0 < Sg) {
-            const u32 c0 = (i0 + 1) * f - 1;
-            int lo = 0, hi = R;  // largest r with spre[r] <= c0 (a run with samples)
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (spre[mid] <= c0) lo = mid; else hi = mid;
-            }
-            r = lo;
+    for (u32 i = t; i <= nb; i += SIZE_NT) a.slot_group[gb + i] = (u32)g;
+}
+
+// Boundaries of the listed groups, workgroups looping over the list: sort (a
+// regular subsample of) the group's samples and keep every q-th as a chunk
+// boundary (parameters from k_mwm_size).
+template <typename K>
+__global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
+    constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
+    __shared__ SortSmem<NT, (int)sizeof(K), IT> sm;
+    __shared__ u32 spre[MAXR + 1];
+    __shared__ u32 sbase[MAXR];  // first sample index of each run
+    u32* vex = sm.template ex<u32>();
+    const int t = threadIdx.x, R = a.R;
+    const u32 nheavy = *a.nheavy;
+    for (u32 h = blockIdx.x; h < nheavy; h += gridDim.x) {
+        const u32 g = uniform(a.heavy[h]);
+        const uint4 gp = a.gpar[2 * (i64)g];
+        const u32 f = uniform(gp.x), Sg = uniform(gp.y), q = uniform(gp.z), dsh = uniform(gp.w);
+        const u32 gb = uniform(a.grp_base[g]), nb = uniform(a.grp_nb[g]);
+        const u32* sd = a.sdesc + (i64)g * R * 4;
+        // exclusive prefix of the runs' sample counts (runs in order)
+        const int RPT = (R + NT - 1) / NT;
+        u32 mys = 0;
+        for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) mys += sd[r * 4 + 1];
+        u32 totS;
+        u32 ex = block_excl_scan<NT>(mys, totS, sm.wsum);
+        for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
+            spre[r] = ex;
+            sbase[r] = sd[r * 4 + 0];
+            ex += sd[r * 4 + 1];
         }
-#pragma unroll
+        if (t == 0) spre[R] = totS;
+        __syncthreads();
+        // load the subsample: element i is concatenated sample index (i+1)*f - 1.
+        // A thread's elements are consecutive, so the run holding its first one is
+        // found by bisection and the rest by walking; every sample index is formed
+        // first and all loads are then issued together.
+        K mn = KeyMax<K>::v, mx = 0;
+        u32 v[IT], rank[IT];
+        K key[IT];
+        {
+            const u32 i0 = (u32)(t * IT);
+            int r = 0;
+            if (i0 < Sg) {
+                const u32 c0 = (i0 + 1) * f - 1;
+                int lo = 0, hi = R;  // largest r with spre[r] <= c0 (a run with samples)
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (spre[mid] <= c0) lo = mid; else hi = mid;
+                }
+                r = lo;
+            }
+    #pragma unroll
+            for (int j = 0; j < IT; j++) {
+                const u32 i = i0 + (u32)j;
+                v[j] = 0;
+                key[j] = 0;
+                if (i < Sg) {
+                    const u32 c = (i + 1) * f - 1;
+                    while (spre[r + 1] <= c) r++;  // stops at r < R: spre[R] = Sraw > c
+                    key[j] = (K)(sbase[r] + (c - spre[r]));
+                    v[j] = c;
+                }
+            }
+    #pragma unroll
+            for (int j = 0; j < IT; j++) {
+                if (i0 + (u32)j < Sg) {
+                    key[j] = a.smp[(u32)key[j]];
+                    mn = key[j] < mn ? key[j] : mn;
+                    mx = key[j] > mx ? key[j] : mx;
+                }
+            }
+        }
+        block_minmax<NT, K>(mn, mx, sm.red64);
+        const int nbits = bitwidth64((u64)(mx - mn));
+        if (sizeof(K) == 8 && nbits > 32) {
+            u64 sk[IT];
+    #pragma unroll
+            for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u64)(key[j] - mn) : (u64)(mx - mn);
+            wg_sort_regs<NT, IT, u64, true>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
+            u64* e = sm.template ex<u64>();
+    #pragma unroll
+            for (int j = 0; j < IT; j++) key[j] = (K)(e[padi(t * IT + j)] + (u64)mn);
+        } else {
+            u32 sk[IT];
+    #pragma unroll
+            for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u32)(key[j] - mn) : (u32)(mx - mn);
+            wg_sort_regs<NT, IT, u32, true>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
+    #pragma unroll
+            for (int j = 0; j < IT; j++) key[j] = (K)vex[padi(t * IT + j)] + mn;
+        }
+        wg_scatter_vals<NT, IT>(v, rank, vex);
+        // boundary b (1..nb) = sorted element b*q - 1 - dsh
+    #pragma unroll
         for (int j = 0; j < IT; j++) {
-            const u32 i = i0 + (u32)j;
-            v[j] = 0;
-            key[j] = 0;
-            if (i < Sg) {
-                const u32 c = (i + 1) * f - 1;
-                while (spre[r + 1] <= c) r++;  // stops at r < R: spre[R] = Sraw > c
-                key[j] = (K)(sbase[r] + (c - spre[r]));
-                v[j] = c;
+            const u32 i = (u32)(t * IT + j);
+            if (i < Sg && (i + 1 + dsh) % q == 0 && (i + 1 + dsh) / q <= nb) {
+                const u32 b = (i + 1 + dsh) / q;
+                const u32 c = vex[padi((int)i)];
+                int lo = 0, hi = R;
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (spre[mid] <= c) lo = mid; else hi = mid;
+                }
+                a.bkey[gb + b - 1] = key[j];
+                a.bpos[gb + b - 1] = sd[lo * 4 + 2] + (c - spre[lo]) * sd[lo * 4 + 3];
             }
         }
-#pragma unroll
-        for (int j = 0; j < IT; j++) {
-            if (i0 + (u32)j < Sg) {
-                key[j] = a.smp[(u32)key[j]];
-                mn = key[j] < mn ? key[j] : mn;
-                mx = key[j] > mx ? key[j] : mx;
-            }
-        }
-    }
-    block_minmax<NT, K>(mn, mx, sm.red64);
-    const int nbits = bitwidth64((u64)(mx - mn));
-    if (sizeof(K) == 8 && nbits > 32) {
-        u64 sk[IT];
-#pragma unroll
-        for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u64)(key[j] - mn) : (u64)(mx - mn);
-        wg_sort_regs<NT, IT, u64, true>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
-        u64* e = sm.template ex<u64>();
-#pragma unroll
-        for (int j = 0; j < IT; j++) key[j] = (K)(e[padi(t * IT + j)] + (u64)mn);
-    } else {
-        u32 sk[IT];
-#pragma unroll
-        for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u32)(key[j] - mn) : (u32)(mx - mn);
-        wg_sort_regs<NT, IT, u32, true>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
-#pragma unroll
-        for (int j = 0; j < IT; j++) key[j] = (K)vex[padi(t * IT + j)] + mn;
-    }
-    wg_scatter_vals<NT, IT>(v, rank, vex);
-    // boundary b (1..nb) = sorted element b*q - 1 - dsh
-#pragma unroll
-    for (int j = 0; j < IT; j++) {
-        const u32 i = (u32)(t * IT + j);
-        if (i < Sg && (i + 1 + dsh) % q == 0 && (i + 1 + dsh) / q <= nb) {
-            const u32 b = (i + 1 + dsh) / q;
-            const u32 c = vex[padi((int)i)];
-            int lo = 0, hi = R;
-            while (hi - lo > 1) {
-                int mid = (lo + hi) >> 1;
-                if (spre[mid] <= c) lo = mid; else hi = mid;
-            }
-            a.bkey[gb + b - 1] = key[j];
-            a.bpos[gb + b - 1] = sd[lo * 4 + 2] + (c - spre[lo]) * sd[lo * 4 + 3];
-        }
+        __syncthreads();  // LDS is reused by the next listed group
     }
 }
 
@@ -518,66 +557,67 @@ __global__ __launch_bounds__(256) void k_mwm_below(MwmArgs<K> a) {
 // or below boundary c are the sum of its cuts over the runs). Consecutive
 // chunks are combined while they fit the cap, so that groups whose sample
 // forced small chunks (large groups, few samples per key) still fill the LDS
-// sort; a chunk above the cap stays alone. One workgroup per group.
+// sort; a chunk above the cap stays alone. Workgroups loop over the groups
+// listed by k_mwm_size (a group of one chunk got its work item there).
 constexpr int PLAN_NT = 256, PLAN_MAXC = 4096;
 template <typename K>
 __global__ __launch_bounds__(PLAN_NT) void k_mwm_plan(MwmArgs<K> a) {
     __shared__ u32 P[PLAN_MAXC];
     __shared__ unsigned short itf[PLAN_MAXC], itl[PLAN_MAXC];
-    __shared__ u32 wsum[PLAN_NT / 64 + 2];
     __shared__ u32 sh_n, sh_base;
-    const int g = blockIdx.x, t = threadIdx.x, R = a.R;
-    const u32 gb = a.grp_base[g], nb = a.grp_nb[g], ob = a.out_base[g];
-    auto item = [&](u32 i, u32 cf, u32 cl) {
-        a.witem[2 * (i64)i] = make_uint4(gb + cf, gb + cl, (u32)g, cf);
-        a.witem[2 * (i64)i + 1] = make_uint4(cl, nb, ob, 0u);
-    };
-    u32 myn = 0;
-    for (int r = t; r < R; r += PLAN_NT) myn += a.run_len[(i64)g * R + r];
-    u32 N;
-    (void)block_excl_scan<PLAN_NT>(myn, N, wsum);
-    if (N == 0 || gb >= a.S) return;  // no chunks
-    const u32 nch = nb + 1;
-    if (nch > PLAN_MAXC) {  // not combined: one item per chunk
-        if (t == 0) sh_base = atomicAdd(a.nwork, nch);
+    const int t = threadIdx.x;
+    const u32 nheavy = *a.nheavy;
+    for (u32 h = blockIdx.x; h < nheavy; h += gridDim.x) {
+        __syncthreads();  // LDS of the previous listed group is free
+        const u32 g = uniform(a.heavy[h]);
+        const u32 gb = uniform(a.grp_base[g]), nb = uniform(a.grp_nb[g]), ob = uniform(a.out_base[g]);
+        const u32 N = uniform(a.gpar[2 * (i64)g + 1].x);
+        auto item = [&](u32 i, u32 cf, u32 cl) {
+            a.witem[2 * (i64)i] = make_uint4(gb + cf, gb + cl, g, cf);
+            a.witem[2 * (i64)i + 1] = make_uint4(cl, nb, ob, 0u);
+        };
+        const u32 nch = nb + 1;
+        if (nch > PLAN_MAXC) {  // not combined: one item per chunk
+            if (t == 0) sh_base = atomicAdd(a.nwork, nch);
+            __syncthreads();
+            for (u32 c = t; c < nch; c += PLAN_NT) item(sh_base + c, c, c);
+            continue;
+        }
+        for (u32 c = t; c < nb; c += PLAN_NT) P[c] = a.below[gb + c];
         __syncthreads();
-        for (u32 c = t; c < nch; c += PLAN_NT) item(sh_base + c, c, c);
-        return;
-    }
-    for (u32 c = t; c < nb; c += PLAN_NT) P[c] = a.below[gb + c];
-    __syncthreads();
-    // greedy combination by wave 0: 64 chunk sizes at a time in registers,
-    // walked in order with uniform (scalar) state
-    if (t < 64) {
-        u32 n = 0, first = 0, acc = 0, prev = 0;
-        for (u32 c0 = 0; c0 < nch; c0 += 64) {
-            const u32 mine = c0 + t < nb ? P[c0 + t] : N;
-            const u32 cnt = min(64u, nch - c0);
-            for (u32 j = 0; j < cnt; j++) {
-                const u32 below = (u32)__builtin_amdgcn_readlane((int)mine, (int)j);
-                const u32 sz = below - prev;
-                prev = below;
-                if (c0 + j > 0 && acc + sz > a.cap) {
-                    if (t == 0) {
-                        itf[n] = (unsigned short)first;
-                        itl[n] = (unsigned short)(c0 + j - 1);
+        // greedy combination by wave 0: 64 chunk sizes at a time in registers,
+        // walked in order with uniform (scalar) state
+        if (t < 64) {
+            u32 n = 0, first = 0, acc = 0, prev = 0;
+            for (u32 c0 = 0; c0 < nch; c0 += 64) {
+                const u32 mine = c0 + t < nb ? P[c0 + t] : N;
+                const u32 cnt = min(64u, nch - c0);
+                for (u32 j = 0; j < cnt; j++) {
+                    const u32 below = (u32)__builtin_amdgcn_readlane((int)mine, (int)j);
+                    const u32 sz = below - prev;
+                    prev = below;
+                    if (c0 + j > 0 && acc + sz > a.cap) {
+                        if (t == 0) {
+                            itf[n] = (unsigned short)first;
+                            itl[n] = (unsigned short)(c0 + j - 1);
+                        }
+                        n++;
+                        first = c0 + j;
+                        acc = 0;
                     }
-                    n++;
-                    first = c0 + j;
-                    acc = 0;
+                    acc += sz;
                 }
-                acc += sz;
+            }
+            if (t == 0) {
+                itf[n] = (unsigned short)first;
+                itl[n] = (unsigned short)nb;
+                sh_n = n + 1;
+                sh_base = atomicAdd(a.nwork, n + 1);
             }
         }
-        if (t == 0) {
-            itf[n] = (unsigned short)first;
-            itl[n] = (unsigned short)nb;
-            sh_n = n + 1;
-            sh_base = atomicAdd(a.nwork, n + 1);
-        }
+        __syncthreads();
+        for (u32 i = t; i < sh_n; i += PLAN_NT) item(sh_base + i, itf[i], itl[i]);
     }
-    __syncthreads();
-    for (u32 i = t; i < sh_n; i += PLAN_NT) item(sh_base + i, itf[i], itl[i]);
 }
 
 // ======================================================================= MWM: chunk sort
