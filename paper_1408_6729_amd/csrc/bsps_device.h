@@ -98,6 +98,9 @@ constexpr int RADIX = 1 << RB;        // digits per pass
 constexpr int HALF = RADIX / 2;       // digits d and d + HALF share one 32-bit counter word
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }  // one pad word per 32
+// padi(j*NT + t) for 0 <= t < NT, NT a multiple of 32: a fixed offset from
+// padi(t), so striped accesses need no address arithmetic per item
+template <int NT> __device__ __forceinline__ int padj(int j, int t) { return j * (NT + NT / 32) + padi(t); }
 
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
@@ -192,12 +195,15 @@ __device__ __forceinline__ void block_minmax(K& mn, K& mx, u64* red) {
 
 // rank[j] = position of item j (thread t, blocked position t*IT + j) after a
 // stable sort by digit dig[j] in [0, RADIX). Counter word (h, t) sits at
-// h*ROW + t + t/32 (row stride ROW = NT + NT/32): thread t's raking slice of
-// HALF words in flattened (h, t) order is contiguous and the per-item
-// read-modify-writes of a wave hit consecutive banks.
+// padi(h*NT + t) = h*ROW + padi(t) (row stride ROW = NT + NT/32): thread t's
+// raking slice of HALF words in flattened (h, t) order is contiguous, and the
+// per-item read-modify-writes of a wave hit consecutive banks. Digits d and
+// d + HALF share word (d, t) as its low and high 16 bits.
 template <int NT, int IT, typename DF>
 __device__ __forceinline__ void radix_rank(DF digf, u32 (&rank)[IT], u32* cnt, u32* wsum) {
+    constexpr u32 ROW = NT + NT / 32;
     const int t = threadIdx.x;
+    const u32 padt = (u32)padi(t);
 #if BSPS_DIG_RECOMPUTE
 #define DIG(j) digf(j)
 #else
@@ -206,13 +212,14 @@ __device__ __forceinline__ void radix_rank(DF digf, u32 (&rank)[IT], u32* cnt, u
     for (int j = 0; j < IT; j++) dig[j] = digf(j);
 #define DIG(j) dig[j]
 #endif
+    // each thread clears its own raking slice
 #pragma unroll
-    for (int h = 0; h < HALF; h++) cnt[padi(h * NT + t)] = 0u;
+    for (int i = 0; i < HALF; i++) cnt[padi(t * HALF + i)] = 0u;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < IT; j++) {
         const u32 d = DIG(j);
-        const int a = padi((int)(d & (HALF - 1)) * NT + t);
+        const u32 a = (d & (HALF - 1)) * ROW + padt;
         const u32 sh = (d >> (RB - 1)) << 4;
         const u32 w = cnt[a];
         rank[j] = (w >> sh) & 0xffffu;
@@ -224,6 +231,9 @@ __device__ __forceinline__ void radix_rank(DF digf, u32 (&rank)[IT], u32* cnt, u
     for (int i = 0; i < HALF; i++) sum += cnt[padi(t * HALF + i)];
     u32 total;
     u32 run = block_excl_scan<NT>(sum, total, wsum);
+    // every item of a high digit follows all items of the low digits: the high
+    // halves start at the low total (at most NT*IT, so neither half overflows)
+    run += (total & 0xffffu) << 16;
 #pragma unroll
     for (int i = 0; i < HALF; i++) {
         const int a = padi(t * HALF + i);
@@ -232,13 +242,11 @@ __device__ __forceinline__ void radix_rank(DF digf, u32 (&rank)[IT], u32* cnt, u
         run += v;
     }
     __syncthreads();
-    const u32 tot_lo = total & 0xffffu;
 #pragma unroll
     for (int j = 0; j < IT; j++) {
         const u32 d = DIG(j);
-        const u32 w = cnt[padi((int)(d & (HALF - 1)) * NT + t)];
-        const u32 base = (d >> (RB - 1)) ? ((w >> 16) + tot_lo) : (w & 0xffffu);
-        rank[j] += base;
+        const u32 sh = (d >> (RB - 1)) << 4;
+        rank[j] += (cnt[(d & (HALF - 1)) * ROW + padt] >> sh) & 0xffffu;
     }
 #undef DIG
     __syncthreads();

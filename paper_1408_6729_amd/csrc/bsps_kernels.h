@@ -169,7 +169,7 @@ __device__ __forceinline__ void store_sorted(const SK* ex, K mn, int cnt, K* out
 #pragma unroll
     for (int j = 0; j < IT; j++) {
         const int i = j * NT + t;
-        if (i < cnt) out[i] = rawkey<K>((K)ex[padi(i)] + mn, out_dt);
+        if (i < cnt) out[i] = rawkey<K>((K)ex[padj<NT>(j, t)] + mn, out_dt);
     }
     // samples: every (2^ysh)-th key, one strided pass over the sorted keys in LDS
     if (smp) {
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
 #pragma unroll
         for (int j = 0; j < IT; j++) {
             const int i = j * NT + t;
-            if (i < cnt) ov[i] = vex[padi(i)];
+            if (i < cnt) ov[i] = vex[padj<NT>(j, t)];
         }
     }
 }
@@ -871,7 +871,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
             ks[j] = 0;
             vs[j] = 0;
             if (i < N) {
-                const u32 si = srcidx[padi((int)i)];
+                const u32 si = srcidx[padj<NT>(j, t)];
                 ks[j] = a.src[si];
                 if (HASV) vs[j] = a.srcv[si];
             }
@@ -881,7 +881,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
 #pragma unroll
         for (int j = 0; j < IT; j++) {
             const u32 i = (u32)(j * NT + t);
-            if (i < N) exk[padi((int)i)] = ks[j];
+            if (i < N) exk[padj<NT>(j, t)] = ks[j];
         }
         __syncthreads();
 #pragma unroll
@@ -897,7 +897,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
 #pragma unroll
             for (int j = 0; j < IT; j++) {
                 const u32 i = (u32)(j * NT + t);
-                if (i < N) srcidx[padi((int)i)] = vs[j];
+                if (i < N) srcidx[padj<NT>(j, t)] = vs[j];
             }
             __syncthreads();
 #pragma unroll
@@ -968,7 +968,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
 #pragma unroll
         for (int j = 0; j < IT; j++) {
             const u32 i = (u32)(j * NT + t);
-            if (i < N) dst[i] = rawkey<K>((K)(e[padi((int)i)] + (u64)mn), a.out_dt);
+            if (i < N) dst[i] = rawkey<K>((K)(e[padj<NT>(j, t)] + (u64)mn), a.out_dt);
         }
         emit_samples(e);
     } else {
@@ -980,7 +980,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
 #pragma unroll
         for (int j = 0; j < IT; j++) {
             const u32 i = (u32)(j * NT + t);
-            if (i < N) dst[i] = rawkey<K>((K)vex[padi((int)i)] + mn, a.out_dt);
+            if (i < N) dst[i] = rawkey<K>((K)vex[padj<NT>(j, t)] + mn, a.out_dt);
         }
         emit_samples(vex);
         PHASE(4);
@@ -991,7 +991,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
 #pragma unroll
         for (int j = 0; j < IT; j++) {
             const u32 i = (u32)(j * NT + t);
-            if (i < N) dv[i] = vex[padi((int)i)];
+            if (i < N) dv[i] = vex[padj<NT>(j, t)];
         }
     }
 }
