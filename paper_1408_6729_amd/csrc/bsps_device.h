@@ -96,6 +96,7 @@ template <> struct Shape<u64> { static constexpr int NT = BSPS_NT64, IT = BSPS_I
 constexpr int RB = BSPS_RB;           // radix bits per pass
 constexpr int RADIX = 1 << RB;        // digits per pass
 constexpr int HALF = RADIX / 2;       // digits d and d + HALF share one 32-bit counter word
+static_assert(RB >= 5 && RB <= 8, "the half of a digit is its top bit shifted right to bit 4");
 
 __device__ __forceinline__ int padi(int i) { return i + (i >> 5); }  // one pad word per 32
 // padi(j*NT + t) for 0 <= t < NT, NT a multiple of 32: a fixed offset from
@@ -123,13 +124,24 @@ template <int NT, int KB, int IT> struct SortSmem {
 
 // ---------------------------------------------------------------- scans
 
+// Inclusive scan over the 64 lanes of a wave by DPP lane moves, all in
+// registers: shifts by 1, 2, 4 and 8 lanes within each row of 16, then the
+// broadcasts of lane 15 (into rows 1 and 3) and of lane 31 (into rows 2 and 3).
 __device__ __forceinline__ u32 wave_incl_scan(u32 v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        u32 y = __shfl_up(v, o, 64);
-        if (lane >= o) v += y;
-    }
+    const int lane = threadIdx.x & 63, rl = lane & 15;
+    u32 y;
+    y = (u32)__builtin_amdgcn_mov_dpp((int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    if (rl >= 1) v += y;
+    y = (u32)__builtin_amdgcn_mov_dpp((int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    if (rl >= 2) v += y;
+    y = (u32)__builtin_amdgcn_mov_dpp((int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    if (rl >= 4) v += y;
+    y = (u32)__builtin_amdgcn_mov_dpp((int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    if (rl >= 8) v += y;
+    y = (u32)__builtin_amdgcn_mov_dpp((int)v, 0x142, 0xf, 0xf, false);  // row_bcast:15
+    if (lane & 16) v += y;
+    y = (u32)__builtin_amdgcn_mov_dpp((int)v, 0x143, 0xf, 0xf, false);  // row_bcast:31
+    if (lane >= 32) v += y;
     return v;
 }
 
@@ -142,12 +154,7 @@ __device__ __forceinline__ u32 block_excl_scan(u32 x, u32& total, u32* wsum) {
     if (lane == 63) wsum[w] = v;
     __syncthreads();
     if (w == 0) {
-        u32 s = lane < NW ? wsum[lane] : 0u;
-#pragma unroll
-        for (int o = 1; o < NW; o <<= 1) {
-            u32 y = __shfl_up(s, o, 64);
-            if (lane >= o) s += y;
-        }
+        const u32 s = wave_incl_scan(lane < NW ? wsum[lane] : 0u);
         if (lane < NW) wsum[lane] = s;
     }
     __syncthreads();
@@ -198,9 +205,10 @@ __device__ __forceinline__ void block_minmax(K& mn, K& mx, u64* red) {
 // padi(h*NT + t) = h*ROW + padi(t) (row stride ROW = NT + NT/32): thread t's
 // raking slice of HALF words in flattened (h, t) order is contiguous, and the
 // per-item read-modify-writes of a wave hit consecutive banks. Digits d and
-// d + HALF share word (d, t) as its low and high 16 bits.
-template <int NT, int IT, typename DF>
-__device__ __forceinline__ void radix_rank(DF digf, u32 (&rank)[IT], u32* cnt, u32* wsum) {
+// d + HALF share word (d, t) as its low and high 16 bits; hsf(j) is the bit
+// offset of item j's half, 16 * (dig[j] >= HALF).
+template <int NT, int IT, typename DF, typename HF>
+__device__ __forceinline__ void radix_rank(DF digf, HF hsf, u32 (&rank)[IT], u32* cnt, u32* wsum) {
     constexpr u32 ROW = NT + NT / 32;
     const int t = threadIdx.x;
     const u32 padt = (u32)padi(t);
@@ -216,14 +224,17 @@ __device__ __forceinline__ void radix_rank(DF digf, u32 (&rank)[IT], u32* cnt, u
 #pragma unroll
     for (int i = 0; i < HALF; i++) cnt[padi(t * HALF + i)] = 0u;
     __syncthreads();
+    u32 ai[IT];  // counter word of each item
 #pragma unroll
     for (int j = 0; j < IT; j++) {
         const u32 d = DIG(j);
-        const u32 a = (d & (HALF - 1)) * ROW + padt;
-        const u32 sh = (d >> (RB - 1)) << 4;
+        u32 a = (d & (HALF - 1)) * ROW + padt;
+        asm volatile("" : "+v"(a));  // kept, not recomputed from the digit, for the second read
+        const u32 sh = hsf(j);
         const u32 w = cnt[a];
         rank[j] = (w >> sh) & 0xffffu;
         cnt[a] = w + (1u << sh);
+        ai[j] = a;
     }
     __syncthreads();
     u32 sum = 0;
@@ -244,9 +255,7 @@ __device__ __forceinline__ void radix_rank(DF digf, u32 (&rank)[IT], u32* cnt, u
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < IT; j++) {
-        const u32 d = DIG(j);
-        const u32 sh = (d >> (RB - 1)) << 4;
-        rank[j] += (cnt[(d & (HALF - 1)) * ROW + padt] >> sh) & 0xffffu;
+        rank[j] += (cnt[ai[j]] >> hsf(j)) & 0xffffu;
     }
 #undef DIG
     __syncthreads();
@@ -271,7 +280,9 @@ __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&r
     for (int pass = 0; pass < npass; pass++) {
         const int sh = pass * RB;
         const bool last = pass == npass - 1;
-        radix_rank<NT, IT>([&](int j) { return (u32)(sk[j] >> sh) & (RADIX - 1); }, rank, cnt, wsum);
+        const int hsh = sh + RB - 5;  // moves the digit's top bit to bit 4
+        radix_rank<NT, IT>([&](int j) { return (u32)(sk[j] >> sh) & (RADIX - 1); },
+                           [&](int j) { return (u32)(sk[j] >> hsh) & 16u; }, rank, cnt, wsum);
 #pragma unroll
         for (int j = 0; j < IT; j++) exch[padi((int)rank[j])] = sk[j];
         __syncthreads();

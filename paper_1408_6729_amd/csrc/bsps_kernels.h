@@ -702,7 +702,8 @@ __device__ void mwm_oversize(const MwmArgs<K>& a, u32 g, u32 slot, u32 c, u32 nb
             }
             __syncthreads();
             digit_excl_scan(tcnt, tbase, t);
-            radix_rank<NT, IT>([&](int j) { return dig[j]; }, rank, sm.cnt(), sm.wsum);
+            radix_rank<NT, IT>([&](int j) { return dig[j]; }, [&](int j) { return (dig[j] >> (RB - 5)) & 16u; }, rank,
+                               sm.cnt(), sm.wsum);
 #pragma unroll
             for (int j = 0; j < IT; j++) {
                 const u32 i = b0 + t * IT + j;
