@@ -163,6 +163,50 @@ __device__ __forceinline__ u32 block_excl_scan(u32 x, u32& total, u32* wsum) {
     return before + v - x;
 }
 
+// The same two scans on 64-bit values (four packed 16-bit counts).
+template <int CTRL> __device__ __forceinline__ u64 dpp_move64(u64 x) {
+    const u32 lo = (u32)__builtin_amdgcn_mov_dpp((int)(u32)x, CTRL, 0xf, 0xf, false);
+    const u32 hi = (u32)__builtin_amdgcn_mov_dpp((int)(u32)(x >> 32), CTRL, 0xf, 0xf, false);
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ u64 wave_incl_scan64(u64 v) {
+    const int lane = threadIdx.x & 63, rl = lane & 15;
+    u64 y;
+    y = dpp_move64<0x111>(v);
+    if (rl >= 1) v += y;
+    y = dpp_move64<0x112>(v);
+    if (rl >= 2) v += y;
+    y = dpp_move64<0x114>(v);
+    if (rl >= 4) v += y;
+    y = dpp_move64<0x118>(v);
+    if (rl >= 8) v += y;
+    y = dpp_move64<0x142>(v);
+    if (lane & 16) v += y;
+    y = dpp_move64<0x143>(v);
+    if (lane >= 32) v += y;
+    return v;
+}
+
+// ws holds NT/64 values; the caller puts a barrier between this scan and the
+// next write of ws.
+template <int NT>
+__device__ __forceinline__ u64 block_excl_scan64(u64 x, u64& total, u64* ws) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const u64 v = wave_incl_scan64(x);
+    if (lane == 63) ws[w] = v;
+    __syncthreads();
+    if (w == 0) {
+        const u64 s = wave_incl_scan64(lane < NW ? ws[lane] : (u64)0);
+        if (lane < NW) ws[lane] = s;
+    }
+    __syncthreads();
+    total = ws[NW - 1];
+    const u64 before = w ? ws[w - 1] : (u64)0;
+    return before + v - x;
+}
+
 // A value every lane of the wave holds alike, moved to a scalar register
 // (keeps workgroup-uniform values out of the vector registers).
 __device__ __forceinline__ u32 uniform(u32 v) { return (u32)__builtin_amdgcn_readfirstlane((int)v); }
@@ -261,6 +305,34 @@ __device__ __forceinline__ void radix_rank(DF digf, HF hsf, u32 (&rank)[IT], u32
     __syncthreads();
 }
 
+// The same rank for a pass of at most 2 bits (digits 0..3) without LDS
+// counters: each thread counts its digits in one register (8 bits per digit;
+// IT < 256), the four counts are widened to 16-bit fields of a 64-bit value,
+// and one workgroup scan of those gives every digit's thread offsets. ws is
+// LDS scratch for NT/64 64-bit values.
+template <int NT, int IT, typename DF>
+__device__ __forceinline__ void radix_rank4(DF digf, u32 (&rank)[IT], u64* ws) {
+    static_assert(IT < 256 && NT * IT <= 65535, "8-bit thread counts, 16-bit totals");
+    u32 c = 0;
+#pragma unroll
+    for (int j = 0; j < IT; j++) {
+        const u32 sh = digf(j) << 3;
+        rank[j] = (c >> sh) & 0xffu;
+        c += 1u << sh;
+    }
+    const u64 x = (u64)(c & 0xffu) | ((u64)(c & 0xff00u) << 8) | ((u64)(c & 0xff0000u) << 16) |
+                  ((u64)(c & 0xff000000u) << 24);
+    u64 tot;
+    const u64 ex = block_excl_scan64<NT>(x, tot, ws);
+    // field d of base: items of the lower digits plus this digit's items in
+    // the threads before this one (each field stays below 2^16)
+    const u32 t0 = (u32)tot & 0xffffu, t1 = (u32)(tot >> 16) & 0xffffu, t2 = (u32)(tot >> 32) & 0xffffu;
+    const u64 base = ex + (((u64)t0 << 16) | ((u64)(t0 + t1) << 32) | ((u64)(t0 + t1 + t2) << 48));
+#pragma unroll
+    for (int j = 0; j < IT; j++) rank[j] += (u32)(base >> (digf(j) << 4)) & 0xffffu;
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- workgroup sort
 
 // Sorts the NT*IT items held in registers (blocked order; unused tail items
@@ -269,7 +341,12 @@ __device__ __forceinline__ void radix_rank(DF digf, HF hsf, u32 (&rank)[IT], u32
 // and rank[j] is the final position of item j, whose payload is still v[j];
 // the caller stores the keys, then calls wg_scatter_vals() for the payloads.
 // SK = u32 or u64; exch holds NT*IT + NT*IT/32 elements of SK.
-template <int NT, int IT, typename SK, bool HASV>
+// SMALLPASS: a last pass of at most 2 bits ranks without LDS counters (more
+// code; kernels short of registers leave it off).
+#ifndef BSPS_SMALLPASS
+#define BSPS_SMALLPASS 1
+#endif
+template <int NT, int IT, typename SK, bool HASV, bool SMALLPASS = (bool)BSPS_SMALLPASS>
 __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&rank)[IT], int nbits, SK* exch,
                                              u32* cnt, u32* wsum) {
     const int t = threadIdx.x;
@@ -280,9 +357,14 @@ __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&r
     for (int pass = 0; pass < npass; pass++) {
         const int sh = pass * RB;
         const bool last = pass == npass - 1;
-        const int hsh = sh + RB - 5;  // moves the digit's top bit to bit 4
-        radix_rank<NT, IT>([&](int j) { return (u32)(sk[j] >> sh) & (RADIX - 1); },
-                           [&](int j) { return (u32)(sk[j] >> hsh) & 16u; }, rank, cnt, wsum);
+        if (SMALLPASS && nbits - sh <= 2) {
+            // a last pass of at most 2 bits (or all keys equal)
+            radix_rank4<NT, IT>([&](int j) { return (u32)(sk[j] >> sh) & 3u; }, rank, reinterpret_cast<u64*>(cnt));
+        } else {
+            const int hsh = sh + RB - 5;  // moves the digit's top bit to bit 4
+            radix_rank<NT, IT>([&](int j) { return (u32)(sk[j] >> sh) & (RADIX - 1); },
+                               [&](int j) { return (u32)(sk[j] >> hsh) & 16u; }, rank, cnt, wsum);
+        }
 #pragma unroll
         for (int j = 0; j < IT; j++) exch[padi((int)rank[j])] = sk[j];
         __syncthreads();

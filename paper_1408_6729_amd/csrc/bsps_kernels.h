@@ -429,7 +429,7 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
             u64 sk[IT];
     #pragma unroll
             for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u64)(key[j] - mn) : (u64)(mx - mn);
-            wg_sort_regs<NT, IT, u64, true>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
+            wg_sort_regs<NT, IT, u64, true, false>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
             u64* e = sm.template ex<u64>();
     #pragma unroll
             for (int j = 0; j < IT; j++) key[j] = (K)(e[padi(t * IT + j)] + (u64)mn);
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
             u32 sk[IT];
     #pragma unroll
             for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u32)(key[j] - mn) : (u32)(mx - mn);
-            wg_sort_regs<NT, IT, u32, true>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
+            wg_sort_regs<NT, IT, u32, true, false>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
     #pragma unroll
             for (int j = 0; j < IT; j++) key[j] = (K)vex[padi(t * IT + j)] + mn;
         }
@@ -820,26 +820,48 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
         return;
     }
     PHASE(1);
-    // gather: thread t owns chunk positions t*IT .. t*IT+IT-1 (blocked order,
-    // which the stable sort needs), walking the pieces from the one that holds
-    // its first position
+    // gather: item j of thread t holds chunk position t*IT + j (blocked order,
+    // which the stable sort of payloads needs), or j*NT + t (striped:
+    // keys-only merges through the LDS-staged gather)
     const u32 i0 = (u32)(t * IT);
+    constexpr bool STRIPED = BSPS_GATHER_LDS && !HASV;
+    auto item_ok = [&](int j) { return STRIPED ? (u32)(j * NT + t) < N : i0 + (u32)j < N; };
     K kr[IT];
     u32 v[IT], rank[IT];
     K mn = KeyMax<K>::v, mx = 0;
 #if BSPS_GATHER_LDS
     // Every position's source index is written to LDS piece by piece; the
     // loads are then issued position-striped (consecutive lanes read
-    // consecutive keys of a piece, coalesced) and the keys are turned back
-    // into blocked order through LDS.
+    // consecutive keys of a piece, coalesced). With payloads the keys are
+    // turned back into blocked order through LDS, which the stable sort needs;
+    // keys alone are sorted from the striped order, since the order of equal
+    // keys cannot be seen in the output.
     {
         u32* srcidx = sm.template ex<u32>();
         if (N >= 64u * (u32)R) {
-            // long pieces: each wave fills the positions of its pieces
+            // long pieces: each wave fills a contiguous range of pieces, 64 at
+            // a time: lane l reads piece rb + l's table entries, then the wave
+            // writes the pieces' positions one after another (no LDS read
+            // waits on another)
+            constexpr int NW = NT / 64;
             const int lane = t & 63, w = t >> 6;
-            for (int r = w; r < R; r += NT / 64) {
-                const u32 p0 = ppre[r], len = ppre[r + 1] - p0, s0 = soff[r];
-                for (u32 i = lane; i < len; i += 64) srcidx[padi((int)(p0 + i))] = s0 + i;
+            const int per = (R + NW - 1) / NW;
+            const int r0 = w * per, r1 = min(R, r0 + per);
+            for (int rb = r0; rb < r1; rb += 64) {
+                const int r = rb + lane;
+                u32 p0 = 0, len = 0, s0 = 0;
+                if (r < r1) {
+                    p0 = ppre[r];
+                    len = ppre[r + 1] - p0;
+                    s0 = soff[r];
+                }
+                const int nr = min(64, r1 - rb);
+                for (int k = 0; k < nr; k++) {
+                    const u32 q0 = (u32)__builtin_amdgcn_readlane((int)p0, k);
+                    const u32 ql = (u32)__builtin_amdgcn_readlane((int)len, k);
+                    const u32 qs = (u32)__builtin_amdgcn_readlane((int)s0, k);
+                    for (u32 i = (u32)lane; i < ql; i += 64) srcidx[padi((int)(q0 + i))] = qs + i;
+                }
             }
         } else if (i0 < N) {
             // short pieces: each thread walks its own positions from the piece
@@ -864,6 +886,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
             }
         }
         __syncthreads();
+        PHASE(5);
         K ks[IT];
         u32 vs[IT];
 #pragma unroll
@@ -877,18 +900,25 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
                 if (HASV) vs[j] = a.srcv[si];
             }
         }
-        __syncthreads();
-        K* exk = sm.template ex<K>();
+        PHASE(6);
+        if (HASV) {
+            __syncthreads();
+            K* exk = sm.template ex<K>();
 #pragma unroll
-        for (int j = 0; j < IT; j++) {
-            const u32 i = (u32)(j * NT + t);
-            if (i < N) exk[padj<NT>(j, t)] = ks[j];
+            for (int j = 0; j < IT; j++) {
+                const u32 i = (u32)(j * NT + t);
+                if (i < N) exk[padj<NT>(j, t)] = ks[j];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < IT; j++) kr[j] = i0 + j < N ? exk[padi((int)(i0 + j))] : (K)0;
+        } else {
+#pragma unroll
+            for (int j = 0; j < IT; j++) kr[j] = ks[j];
         }
-        __syncthreads();
 #pragma unroll
         for (int j = 0; j < IT; j++) {
-            kr[j] = i0 + j < N ? exk[padi((int)(i0 + j))] : (K)0;
-            if (i0 + j < N) {
+            if (item_ok(j)) {
                 mn = kr[j] < mn ? kr[j] : mn;
                 mx = kr[j] > mx ? kr[j] : mx;
             }
@@ -963,7 +993,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
     if (sizeof(K) == 8 && nbits > 32) {
         u64 sk[IT];
 #pragma unroll
-        for (int j = 0; j < IT; j++) sk[j] = i0 + j < N ? (u64)(kr[j] - mn) : (u64)(mx - mn);
+        for (int j = 0; j < IT; j++) sk[j] = item_ok(j) ? (u64)(kr[j] - mn) : (u64)(mx - mn);
         wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
         const u64* e = sm.template ex<u64>();
 #pragma unroll
@@ -975,7 +1005,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
     } else {
         u32 sk[IT];
 #pragma unroll
-        for (int j = 0; j < IT; j++) sk[j] = i0 + j < N ? (u32)(kr[j] - mn) : (u32)(mx - mn);
+        for (int j = 0; j < IT; j++) sk[j] = item_ok(j) ? (u32)(kr[j] - mn) : (u32)(mx - mn);
         wg_sort_regs<NT, IT, u32, HASV>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
         PHASE(3);
 #pragma unroll
