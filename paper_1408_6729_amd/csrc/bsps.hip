@@ -288,9 +288,21 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
         return BSPS_OK;
     }
     ta.out = b.A; ta.outv = b.Av; ta.out_dt = BSPS_DT_NONE; ta.smp = b.tsmp; ta.ys = kSampleStride; ta.spt = b.spt;
+    u32 tgrid = (u32)(p * b.tpb);
+    if (!HASV) {
+        // keys only: a persistent grid of the workgroups that are resident at
+        // once, each loading its next tile while it sorts the current one
+        static int occ = -1;
+        if (occ < 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_tile_sort<K, HASV>, NT, 0) != hipSuccess)
+            occ = 0;
+        if (occ > 0) {
+            ta.persist = 1;
+            tgrid = (u32)std::min<u64>(tgrid, (u64)device_cus() * occ);
+        }
+    }
     {
         StageScope sc(tstage, st);
-        hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3((u32)(p * b.tpb)), dim3(NT), 0, st, ta);
+        hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3(tgrid), dim3(NT), 0, st, ta);
     }
     LAUNCH_OK();
     StageScope sc(mstage, st);

@@ -128,6 +128,9 @@ struct TileArgs {
     const u32* dtab;
     K* outd;
     u32* outdv;
+    // Keys only, no btab: a persistent grid loops over the p*tpb tiles and
+    // loads each next tile while it sorts the current one.
+    int persist;
 };
 
 // Processor k owns [floor(k n / p), floor((k+1) n / p)): blocks differ in size by at most one.
@@ -199,44 +202,17 @@ __device__ __forceinline__ void load_blocked(const T* p, int valid, T (&r)[IT]) 
     }
 }
 
+// Sorts one tile whose keys (raw, cnt of them from base; blocked order) are in
+// kr, payloads in v, and writes it out with its samples.
 template <typename K, bool HASV>
-__global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(TileArgs<K> a) {
-    constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT;
-    __shared__ SortSmem<NT, (int)sizeof(K), IT> sm;
+__device__ __forceinline__ void tile_sort_body(const TileArgs<K>& a, SortSmem<Shape<K>::NT, (int)sizeof(K), Shape<K>::IT>& sm,
+                                               K (&kr)[Shape<K>::IT], u32 (&v)[Shape<K>::IT], int cnt, i64 base,
+                                               K* outk, u32* outv, int odt, K* smp, i64 sbase) {
+    constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
     u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x;
-    i64 base, cnt64, sbase = (i64)blockIdx.x * a.spt;
-    K* outk = a.out;
-    u32* outv = a.outv;
-    int odt = a.out_dt;
-    K* smp = a.smp;
-    if (a.btab) {
-        const u32* bt = a.btab + 4 * (i64)blockIdx.x;
-        base = bt[0];
-        cnt64 = bt[1];
-        sbase = bt[3];
-        if (a.dtab && a.dtab[bt[2]]) {
-            outk = a.outd;
-            outv = a.outdv;
-            odt = a.in_dt;
-            smp = nullptr;
-        } else {
-            odt = BSPS_DT_NONE;
-        }
-    } else {
-        const int k = blockIdx.x / a.tpb, tt = blockIdx.x % a.tpb;
-        const i64 st = blk_start(a.n, a.p, k), en = blk_start(a.n, a.p, k + 1);
-        base = st + (i64)tt * T;
-        cnt64 = en - base;
-    }
-    const int cnt = cnt64 <= 0 ? 0 : (cnt64 > T ? T : (int)cnt64);
-    if (cnt == 0) return;
-    const int i0 = t * IT;
-    const int valid = cnt - i0;  // items of this thread: positions i0 .. i0+IT-1
-    K kr[IT];
-    u32 v[IT], rank[IT];
-    load_blocked<K, IT>(a.in + base + i0, valid, kr);
-    if (HASV) load_blocked<u32, IT>(a.inv + base + i0, valid, v);
+    const int valid = cnt - t * IT;  // items of this thread: positions t*IT .. t*IT+IT-1
+    u32 rank[IT];
     K mn = KeyMax<K>::v, mx = 0;
 #pragma unroll
     for (int j = 0; j < IT; j++) {
@@ -272,6 +248,85 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
             if (i < cnt) ov[i] = vex[padj<NT>(j, t)];
         }
     }
+}
+
+// Tile tt of block k: [blk_start(k) + tt*T, min(that + T, blk_start(k+1))).
+template <typename K>
+__device__ __forceinline__ void tile_range(const TileArgs<K>& a, u32 tile, i64& base, int& cnt) {
+    constexpr int T = Shape<K>::NT * Shape<K>::IT;
+    const int k = (int)(tile / (u32)a.tpb), tt = (int)(tile % (u32)a.tpb);
+    const i64 st = blk_start(a.n, a.p, k), en = blk_start(a.n, a.p, k + 1);
+    base = st + (i64)tt * T;
+    const i64 c = en - base;
+    cnt = c <= 0 ? 0 : (c > T ? T : (int)c);
+}
+
+template <typename K, bool HASV>
+__global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(TileArgs<K> a) {
+    constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
+    __shared__ SortSmem<NT, (int)sizeof(K), IT> sm;
+    const int t = threadIdx.x, i0 = t * IT;
+    K kr[IT];
+    u32 v[IT];
+    if (!HASV && a.persist) {
+        const u32 ntile = (u32)a.p * (u32)a.tpb;
+        u32 tile = blockIdx.x;
+        i64 base;
+        int cnt;
+        if (tile >= ntile) return;
+        tile_range(a, tile, base, cnt);
+        K nk[IT];
+        load_blocked<K, IT>(a.in + base + i0, cnt - i0, nk);
+#pragma unroll
+        for (int j = 0; j < IT; j++) v[j] = 0;
+        for (;;) {
+#pragma unroll
+            for (int j = 0; j < IT; j++) kr[j] = nk[j];
+            const i64 cbase = base;
+            const int ccnt = cnt;
+            const u32 ctile = tile;
+            tile += gridDim.x;
+            // the next tile's keys are in flight while this one is sorted
+            if (tile < ntile) {
+                tile_range(a, tile, base, cnt);
+                load_blocked<K, IT>(a.in + base + i0, cnt - i0, nk);
+            }
+            if (ccnt > 0)
+                tile_sort_body<K, HASV>(a, sm, kr, v, ccnt, cbase, a.out, a.outv, a.out_dt, a.smp,
+                                        (i64)ctile * a.spt);
+            if (tile >= ntile) break;
+            __syncthreads();
+        }
+        return;
+    }
+    i64 base, cnt64, sbase = (i64)blockIdx.x * a.spt;
+    K* outk = a.out;
+    u32* outv = a.outv;
+    int odt = a.out_dt;
+    K* smp = a.smp;
+    if (a.btab) {
+        const u32* bt = a.btab + 4 * (i64)blockIdx.x;
+        base = bt[0];
+        cnt64 = bt[1];
+        sbase = bt[3];
+        if (a.dtab && a.dtab[bt[2]]) {
+            outk = a.outd;
+            outv = a.outdv;
+            odt = a.in_dt;
+            smp = nullptr;
+        } else {
+            odt = BSPS_DT_NONE;
+        }
+    } else {
+        int c;
+        tile_range(a, blockIdx.x, base, c);
+        cnt64 = c;
+    }
+    const int cnt = cnt64 <= 0 ? 0 : (cnt64 > NT * IT ? NT * IT : (int)cnt64);
+    if (cnt == 0) return;
+    load_blocked<K, IT>(a.in + base + i0, cnt - i0, kr);
+    if (HASV) load_blocked<u32, IT>(a.inv + base + i0, cnt - i0, v);
+    tile_sort_body<K, HASV>(a, sm, kr, v, cnt, base, outk, outv, odt, smp, sbase);
 }
 
 // ======================================================================= MWM: pick boundaries
