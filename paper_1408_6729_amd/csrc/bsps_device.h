@@ -106,20 +106,24 @@ template <int NT> __device__ __forceinline__ int padj(int j, int t) { return j *
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
 // The digit counters and the key exchange buffer are never live at the same
-// time (ranking ends with a barrier before keys are scattered), so they share
-// one LDS region: `u` holds HALF*NT counter words or NT*IT exchange slots of
-// 8 bytes, whichever is larger, each with one pad word per 32.
-template <int NT, int KB, int IT> struct SortSmem {
+// time (ranking ends with a barrier before keys are scattered), so they may
+// share one LDS region: `u` holds HALF*NT counter words or NT*IT exchange
+// slots of KB bytes, whichever is larger, each with one pad word per 32.
+// SEP gives the exchange buffer its own region (twice the LDS), which lets a
+// sort pass drop three of its barriers (see wg_sort_regs).
+template <int NT, int KB, int IT, bool SEP = false> struct SortSmem {
     static constexpr int CNT = HALF * NT;
     static constexpr int CNTW = CNT + CNT / 32;
     static constexpr int EXW = (NT * IT + NT * IT / 32) * KB / 4;  // IT items of KB bytes per thread, padded
-    static constexpr int UW = CNTW > EXW ? CNTW : EXW;
+    static constexpr int UW = SEP ? CNTW : (CNTW > EXW ? CNTW : EXW);
+    static constexpr int XW = SEP ? EXW : 1;
     u32 u[UW];
+    u32 x[XW];
     u32 wsum[NT / 64 + 2];
     u32 misc[16];
     u64 red64[NT / 64 * 2];
     __device__ __forceinline__ u32* cnt() { return u; }
-    template <typename T> __device__ __forceinline__ T* ex() { return reinterpret_cast<T*>(u); }
+    template <typename T> __device__ __forceinline__ T* ex() { return reinterpret_cast<T*>(SEP ? x : u); }
 };
 
 // ---------------------------------------------------------------- scans
@@ -251,7 +255,12 @@ __device__ __forceinline__ void block_minmax(K& mn, K& mx, u64* red) {
 // per-item read-modify-writes of a wave hit consecutive banks. Digits d and
 // d + HALF share word (d, t) as its low and high 16 bits; hsf(j) is the bit
 // offset of item j's half, 16 * (dig[j] >= HALF).
-template <int NT, int IT, typename DF, typename HF>
+//
+// SEP (counters apart from the exchange buffer): each thread clears its own
+// column (no other thread touches it between the scan of the last pass and
+// the counting of this one), so neither the clear nor the end of the rank
+// needs a barrier.
+template <int NT, int IT, bool SEP = false, typename DF, typename HF>
 __device__ __forceinline__ void radix_rank(DF digf, HF hsf, u32 (&rank)[IT], u32* cnt, u32* wsum) {
     constexpr u32 ROW = NT + NT / 32;
     const int t = threadIdx.x;
@@ -264,10 +273,15 @@ __device__ __forceinline__ void radix_rank(DF digf, HF hsf, u32 (&rank)[IT], u32
     for (int j = 0; j < IT; j++) dig[j] = digf(j);
 #define DIG(j) dig[j]
 #endif
-    // each thread clears its own raking slice
+    if (SEP) {
 #pragma unroll
-    for (int i = 0; i < HALF; i++) cnt[padi(t * HALF + i)] = 0u;
-    __syncthreads();
+        for (int h = 0; h < HALF; h++) cnt[h * ROW + padt] = 0u;
+    } else {
+        // each thread clears its own raking slice
+#pragma unroll
+        for (int i = 0; i < HALF; i++) cnt[padi(t * HALF + i)] = 0u;
+        __syncthreads();
+    }
     u32 ai[IT];  // counter word of each item
 #pragma unroll
     for (int j = 0; j < IT; j++) {
@@ -302,7 +316,7 @@ __device__ __forceinline__ void radix_rank(DF digf, HF hsf, u32 (&rank)[IT], u32
         rank[j] += (cnt[ai[j]] >> hsf(j)) & 0xffffu;
     }
 #undef DIG
-    __syncthreads();
+    if (!SEP) __syncthreads();
 }
 
 // The same rank for a pass of at most 2 bits (digits 0..3) without LDS
@@ -310,7 +324,7 @@ __device__ __forceinline__ void radix_rank(DF digf, HF hsf, u32 (&rank)[IT], u32
 // IT < 256), the four counts are widened to 16-bit fields of a 64-bit value,
 // and one workgroup scan of those gives every digit's thread offsets. ws is
 // LDS scratch for NT/64 64-bit values.
-template <int NT, int IT, typename DF>
+template <int NT, int IT, bool SEP = false, typename DF>
 __device__ __forceinline__ void radix_rank4(DF digf, u32 (&rank)[IT], u64* ws) {
     static_assert(IT < 256 && NT * IT <= 65535, "8-bit thread counts, 16-bit totals");
     u32 c = 0;
@@ -330,7 +344,7 @@ __device__ __forceinline__ void radix_rank4(DF digf, u32 (&rank)[IT], u64* ws) {
     const u64 base = ex + (((u64)t0 << 16) | ((u64)(t0 + t1) << 32) | ((u64)(t0 + t1 + t2) << 48));
 #pragma unroll
     for (int j = 0; j < IT; j++) rank[j] += (u32)(base >> (digf(j) << 4)) & 0xffffu;
-    __syncthreads();
+    if (!SEP) __syncthreads();  // ws lies in the counter region
 }
 
 // ---------------------------------------------------------------- workgroup sort
@@ -346,7 +360,7 @@ __device__ __forceinline__ void radix_rank4(DF digf, u32 (&rank)[IT], u64* ws) {
 #ifndef BSPS_SMALLPASS
 #define BSPS_SMALLPASS 1
 #endif
-template <int NT, int IT, typename SK, bool HASV, bool SMALLPASS = (bool)BSPS_SMALLPASS>
+template <int NT, int IT, typename SK, bool HASV, bool SMALLPASS = (bool)BSPS_SMALLPASS, bool SEP = false>
 __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&rank)[IT], int nbits, SK* exch,
                                              u32* cnt, u32* wsum) {
     const int t = threadIdx.x;
@@ -359,11 +373,12 @@ __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&r
         const bool last = pass == npass - 1;
         if (SMALLPASS && nbits - sh <= 2) {
             // a last pass of at most 2 bits (or all keys equal)
-            radix_rank4<NT, IT>([&](int j) { return (u32)(sk[j] >> sh) & 3u; }, rank, reinterpret_cast<u64*>(cnt));
+            radix_rank4<NT, IT, SEP>([&](int j) { return (u32)(sk[j] >> sh) & 3u; }, rank,
+                                     reinterpret_cast<u64*>(cnt));
         } else {
             const int hsh = sh + RB - 5;  // moves the digit's top bit to bit 4
-            radix_rank<NT, IT>([&](int j) { return (u32)(sk[j] >> sh) & (RADIX - 1); },
-                               [&](int j) { return (u32)(sk[j] >> hsh) & 16u; }, rank, cnt, wsum);
+            radix_rank<NT, IT, SEP>([&](int j) { return (u32)(sk[j] >> sh) & (RADIX - 1); },
+                                    [&](int j) { return (u32)(sk[j] >> hsh) & 16u; }, rank, cnt, wsum);
         }
 #pragma unroll
         for (int j = 0; j < IT; j++) exch[padi((int)rank[j])] = sk[j];
@@ -371,7 +386,9 @@ __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&r
         if (last) break;
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = exch[padi(t * IT + j)];
-        __syncthreads();
+        // with SEP the next write of exch (the next scatter) follows the rank's
+        // barriers; payloads reuse exch at once
+        if (!SEP || HASV) __syncthreads();
         if (HASV) {
 #pragma unroll
             for (int j = 0; j < IT; j++) vex[padi((int)rank[j])] = v[j];

@@ -205,7 +205,7 @@ __device__ __forceinline__ void load_blocked(const T* p, int valid, T (&r)[IT]) 
 // Sorts one tile whose keys (raw, cnt of them from base; blocked order) are in
 // kr, payloads in v, and writes it out with its samples.
 template <typename K, bool HASV>
-__device__ __forceinline__ void tile_sort_body(const TileArgs<K>& a, SortSmem<Shape<K>::NT, (int)sizeof(K), Shape<K>::IT>& sm,
+__device__ __forceinline__ void tile_sort_body(const TileArgs<K>& a, SortSmem<Shape<K>::NT, (int)sizeof(K), Shape<K>::IT, !HASV>& sm,
                                                K (&kr)[Shape<K>::IT], u32 (&v)[Shape<K>::IT], int cnt, i64 base,
                                                K* outk, u32* outv, int odt, K* smp, i64 sbase) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
@@ -230,13 +230,14 @@ __device__ __forceinline__ void tile_sort_body(const TileArgs<K>& a, SortSmem<Sh
         u64 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = j < valid ? (u64)(kr[j] - mn) : (u64)(mx - mn);
-        wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
+        wg_sort_regs<NT, IT, u64, HASV, (bool)BSPS_SMALLPASS, !HASV>(sk, v, rank, nbits, sm.template ex<u64>(),
+                                                                     sm.cnt(), sm.wsum);
         store_sorted<K, u64, NT, IT>(sm.template ex<u64>(), mn, cnt, out, odt, smp, sbase, ysh);
     } else {
         u32 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = j < valid ? (u32)(kr[j] - mn) : (u32)(mx - mn);
-        wg_sort_regs<NT, IT, u32, HASV>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
+        wg_sort_regs<NT, IT, u32, HASV, (bool)BSPS_SMALLPASS, !HASV>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
         store_sorted<K, u32, NT, IT>(vex, mn, cnt, out, odt, smp, sbase, ysh);
     }
     if (HASV) {
@@ -264,7 +265,7 @@ __device__ __forceinline__ void tile_range(const TileArgs<K>& a, u32 tile, i64& 
 template <typename K, bool HASV>
 __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(TileArgs<K> a) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
-    __shared__ SortSmem<NT, (int)sizeof(K), IT> sm;
+    __shared__ SortSmem<NT, (int)sizeof(K), IT, !HASV> sm;
     const int t = threadIdx.x, i0 = t * IT;
     K kr[IT];
     u32 v[IT];
@@ -893,7 +894,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
     // keys cannot be seen in the output.
     {
         u32* srcidx = sm.template ex<u32>();
-        if (N >= 64u * (u32)R) {
+        if (N >= 48u * (u32)R) {
             // long pieces: each wave fills a contiguous range of pieces, 64 at
             // a time: lane l reads piece rb + l's table entries, then the wave
             // writes the pieces' positions one after another (no LDS read
