@@ -98,6 +98,17 @@ def test_edges(ora, dev, n):
         _check(ora, dev, keys, p, 3, ora.DET)
 
 
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("n,p", [(2 * 16384 + 1, 2), (3 * 16384 + 2, 3), (5_000_003, 61)])
+def test_tile_loop_edges(ora, dev, dtype, n, p):
+    """Keys-only tile sorts run as a persistent grid that loads each next tile
+    early: a block one tile long beside blocks one key longer leaves an empty
+    tile inside the loop (first two cases), and 5*10^6 keys in 61 ragged blocks
+    give more tiles than resident workgroups, with a partial tile per block."""
+    keys = W.random_keys(n, dtype, seed=n + p, distinct=max(1, n // 3))
+    _check(ora, dev, keys, p, 8, ora.DET)
+
+
 def test_p_limit(dev):
     import torch
     import paper_1408_6729_amd as bsps
