@@ -850,9 +850,12 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
         mysum += hi - lo;
         mylo += lo;
     }
-    u32 N;
-    u32 ex = block_excl_scan<NT>(mysum, N, sm.wsum);
-    N = uniform(N);
+    // one scan of both sums: the chunk's piece lengths (low 32 bits; their
+    // total N < 2^32) and the group's keys below the chunk (high 32 bits)
+    u64 both;
+    const u64 exb = block_excl_scan64<NT>(((u64)mylo << 32) | mysum, both, sm.red64);
+    const u32 N = uniform((u32)both);
+    u32 ex = (u32)exb;
     for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
         const u32 lo = c == 0 ? 0u : lorow[r];
         const u32 hi = cl == nb ? rl[r] : hirow[r];
@@ -862,9 +865,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
     }
     if (t == 0) ppre[R] = N;
     __syncthreads();
-    u32 LO;
-    (void)block_excl_scan<NT>(mylo, LO, sm.wsum);
-    const u32 out = uniform(obase + LO);
+    const u32 out = uniform(obase + (u32)(both >> 32));
     if (N == 0) return;
     PHASE(0);
     if (N > a.cap) {
