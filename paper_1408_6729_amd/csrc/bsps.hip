@@ -269,6 +269,22 @@ void carve_block_sort(Carver& c, BlockSortBufs<K>& b, u64 n, int p, bool hasv, u
     }
 }
 
+// Grid of a tile-sort launch over ntile tiles. Keys only: a persistent grid of
+// the workgroups that are resident at once (ta.persist), each loading its next
+// tile while it sorts the current one; with payloads one workgroup per tile.
+template <typename K, bool HASV, bool TT = false>
+u32 tile_grid(TileArgs<K>& ta, u32 ntile) {
+    constexpr int NT = Shape<K>::NT;
+    ta.ntile = ntile;
+    if (HASV) return ntile;
+    static int occ = -1;
+    if (occ < 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_tile_sort<K, HASV, TT>, NT, 0) != hipSuccess)
+        occ = 0;
+    if (occ <= 0) return ntile;
+    ta.persist = 1;
+    return (u32)std::max<u64>(1, std::min<u64>(ntile, (u64)device_cus() * occ));
+}
+
 // in (dtype in_dt) -> out (order keys, or raw keys of out_dt), every block of
 // the p-way split sorted. scr/scrv: n-element scratch for oversize chunks
 // (may be the input). osmp: block samples every yb-th key (slot stride spb).
@@ -288,18 +304,7 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
         return BSPS_OK;
     }
     ta.out = b.A; ta.outv = b.Av; ta.out_dt = BSPS_DT_NONE; ta.smp = b.tsmp; ta.ys = kSampleStride; ta.spt = b.spt;
-    u32 tgrid = (u32)(p * b.tpb);
-    if (!HASV) {
-        // keys only: a persistent grid of the workgroups that are resident at
-        // once, each loading its next tile while it sorts the current one
-        static int occ = -1;
-        if (occ < 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_tile_sort<K, HASV>, NT, 0) != hipSuccess)
-            occ = 0;
-        if (occ > 0) {
-            ta.persist = 1;
-            tgrid = (u32)std::min<u64>(tgrid, (u64)device_cus() * occ);
-        }
-    }
+    const u32 tgrid = tile_grid<K, HASV>(ta, (u32)(p * b.tpb));
     {
         StageScope sc(tstage, st);
         hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3(tgrid), dim3(NT), 0, st, ta);
@@ -1030,7 +1035,7 @@ bsps_status enqueue_segmented(const SegPlan& P, const SegBufs<K>& b, K* io, u32*
     ta.btab = b.btab; ta.dtab = b.dtab; ta.outd = io; ta.outdv = vals;
     {
         StageScope sc(ST_TILE, st);
-        hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3(P.NB), dim3(NT), 0, st, ta);
+        hipLaunchKernelGGL((k_tile_sort<K, HASV, true>), dim3(tile_grid<K, HASV, true>(ta, P.NB)), dim3(NT), 0, st, ta);
         LAUNCH_OK();
     }
     if (P.nmerged == 0) return BSPS_OK;

@@ -128,9 +128,10 @@ struct TileArgs {
     const u32* dtab;
     K* outd;
     u32* outdv;
-    // Keys only, no btab: a persistent grid loops over the p*tpb tiles and
-    // loads each next tile while it sorts the current one.
+    // Keys only: a persistent grid loops over the ntile tiles (p*tpb, or the
+    // btab entries) and loads each next tile while it sorts the current one.
     int persist;
+    u32 ntile;
 };
 
 // Processor k owns [floor(k n / p), floor((k+1) n / p)): blocks differ in size by at most one.
@@ -262,14 +263,16 @@ __device__ __forceinline__ void tile_range(const TileArgs<K>& a, u32 tile, i64& 
     cnt = c <= 0 ? 0 : (c > T ? T : (int)c);
 }
 
-template <typename K, bool HASV>
+// TT: the persistent loop reads its tiles from btab (compiled apart, so that
+// the block-layout loop keeps its own register allocation).
+template <typename K, bool HASV, bool TT = false>
 __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(TileArgs<K> a) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
     __shared__ SortSmem<NT, (int)sizeof(K), IT, !HASV> sm;
     const int t = threadIdx.x, i0 = t * IT;
     K kr[IT];
     u32 v[IT];
-    if (!HASV && a.persist) {
+    if (!HASV && !TT && a.persist) {
         const u32 ntile = (u32)a.p * (u32)a.tpb;
         u32 tile = blockIdx.x;
         i64 base;
@@ -296,6 +299,58 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
                 tile_sort_body<K, HASV>(a, sm, kr, v, ccnt, cbase, a.out, a.outv, a.out_dt, a.smp,
                                         (i64)ctile * a.spt);
             if (tile >= ntile) break;
+            __syncthreads();
+        }
+        return;
+    }
+    if (!HASV && TT && a.persist) {
+        // tile -> its keys [base, base + cnt), output, output type and samples
+        auto info = [&](u32 tile, i64& base, int& cnt, K*& outk, int& odt, K*& smp, i64& sbase) {
+            outk = a.out;
+            odt = a.out_dt;
+            smp = a.smp;
+            if (TT) {
+                const u32* bt = a.btab + 4 * (i64)tile;
+                base = bt[0];
+                cnt = bt[1] > (u32)(NT * IT) ? NT * IT : (int)bt[1];
+                sbase = bt[3];
+                if (a.dtab && a.dtab[bt[2]]) {
+                    outk = a.outd;
+                    odt = a.in_dt;
+                    smp = nullptr;
+                } else {
+                    odt = BSPS_DT_NONE;
+                }
+            } else {
+                tile_range(a, tile, base, cnt);
+                sbase = (i64)tile * a.spt;
+            }
+        };
+        u32 tile = blockIdx.x;
+        if (tile >= a.ntile) return;
+        i64 base, sbase;
+        int cnt, odt;
+        K *outk, *smp;
+        info(tile, base, cnt, outk, odt, smp, sbase);
+        K nk[IT];
+        load_blocked<K, IT>(a.in + base + i0, cnt - i0, nk);
+#pragma unroll
+        for (int j = 0; j < IT; j++) v[j] = 0;
+        for (;;) {
+#pragma unroll
+            for (int j = 0; j < IT; j++) kr[j] = nk[j];
+            const i64 cbase = base, csbase = sbase;
+            const int ccnt = cnt, codt = odt;
+            K* const coutk = outk;
+            K* const csmp = smp;
+            tile += gridDim.x;
+            // the next tile's keys are in flight while this one is sorted
+            if (tile < a.ntile) {
+                info(tile, base, cnt, outk, odt, smp, sbase);
+                load_blocked<K, IT>(a.in + base + i0, cnt - i0, nk);
+            }
+            if (ccnt > 0) tile_sort_body<K, HASV>(a, sm, kr, v, ccnt, cbase, coutk, nullptr, codt, csmp, csbase);
+            if (tile >= a.ntile) break;
             __syncthreads();
         }
         return;
