@@ -109,6 +109,28 @@ def test_tile_loop_edges(ora, dev, dtype, n, p):
     _check(ora, dev, keys, p, 8, ora.DET)
 
 
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("span_bits", [1, 2, 3, 7, 13])
+@pytest.mark.parametrize("kv", [False, True])
+def test_narrow_ranges(ora, dev, dtype, span_bits, kv):
+    """Keys spanning 2^span_bits consecutive order-key values. The rebased
+    keys have 1-2 bits (a single pass of at most 2 bits, ranked without LDS
+    counters), 3 bits (one 6-bit pass), 7 bits (6 + a 1-bit pass) or 13 bits
+    (6 + 6 + 1), in the tile sorts and in every merge chunk."""
+    rng = np.random.default_rng(span_bits * 7 + (1 if kv else 0))
+    n = 3 * 16384 + 1234
+    off = rng.integers(0, 1 << span_bits, size=n)
+    if dtype == "int32":
+        keys = (np.int64(-(1 << 20)) + off).astype(np.int32)
+    elif dtype == "int64":
+        keys = (np.int64(1 << 40) + off).astype(np.int64)
+    else:
+        # consecutive float32 bit patterns above 1.0
+        keys = (np.uint32(0x3f800000) + off.astype(np.uint32)).view(np.float32)
+    _check(ora, dev, keys, 5, 4, ora.DET, kv=kv)
+    _check(ora, dev, keys, 5, 4, ora.RAN, kv=kv)
+
+
 def test_p_limit(dev):
     import torch
     import paper_1408_6729_amd as bsps
