@@ -310,7 +310,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures a single GPU: this build has no multi-GPU path (the p virtual "
+        print("bench.py measures a single GPU: the library has no multi-GPU path (the p virtual "
               "processors live on one GPU); run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     only = set(args.only.split(","))
