@@ -12,7 +12,8 @@
  * Conventions for every entry point:
  *  - Pointers are DEVICE pointers unless a comment says HOST. The caller owns
  *    all memory; the library allocates no device memory on any sort path and
- *    frees nothing it did not allocate.
+ *    frees nothing it did not allocate. (bsps_sort_noalloc instead uses a
+ *    fixed scratch array that the library's code holds on every GPU.)
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream). Work is
  *    enqueued asynchronously and the call returns after enqueueing, except in
  *    diagnostic mode (a non-NULL bsps_stats*), where the call synchronizes the
@@ -131,6 +132,29 @@ bsps_status bsps_sort(void* keys, int64_t n, int32_t dtype, const bsps_params* p
  * keys keep their input order, so payloads of equal keys keep theirs. */
 bsps_status bsps_sort_kv(void* keys, uint32_t* values, int64_t n, int32_t dtype, const bsps_params* prm,
                          void* ws, size_t ws_bytes, void* stream, bsps_stats* st);
+
+/*
+ * Allocation-free sort, for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): bsps_sort (values == NULL) or bsps_sort_kv (values != NULL)
+ * with the workspace taken from a scratch array that the library holds
+ * statically on every GPU it runs on (BSPS_NOALLOC_SCRATCH_BYTES per GPU,
+ * reserved when the library's code is loaded on that GPU and kept until the
+ * process ends). The call allocates and frees nothing and records no timing
+ * events. The scratch address of the current device is looked up on the first
+ * call on that device (the device current at the call must be the one
+ * `stream` belongs to). Every call on one GPU shares that GPU's scratch:
+ * calls that overlap in time on one GPU (two host threads, or two streams
+ * whose work runs concurrently) race and give wrong results; calls in order
+ * on one stream are safe. The sort clears everything it reads before use, so
+ * the previous call's contents do not matter.
+ * Errors: as bsps_sort; EUNSUPPORTED when the workspace the sort needs,
+ * bsps_workspace_bytes(n, dtype, values != NULL, prm), exceeds
+ * BSPS_NOALLOC_SCRATCH_BYTES (checked on the host before any HIP call).
+ */
+#define BSPS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+bsps_status bsps_sort_noalloc(void* keys, uint32_t* values, int64_t n, int32_t dtype, const bsps_params* prm,
+                              void* stream);
 
 /*
  * Sort nseg independent segments [h_offsets[i], h_offsets[i+1]) of one key

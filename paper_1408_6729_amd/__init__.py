@@ -61,6 +61,8 @@ def _load():
     L.bsps_sort.argtypes = [vp, i64, i32, PP, vp, sz, vp, SP]
     L.bsps_sort_kv.restype = i32
     L.bsps_sort_kv.argtypes = [vp, vp, i64, i32, PP, vp, sz, vp, SP]
+    L.bsps_sort_noalloc.restype = i32
+    L.bsps_sort_noalloc.argtypes = [vp, vp, i64, i32, PP, vp]
     L.bsps_status_string.restype = ct.c_char_p
     L.bsps_status_string.argtypes = [i32]
     L.bsps_rank.restype = i32
@@ -202,6 +204,25 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
 
 def _ptr(t):
     return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # BSPS_NOALLOC_SCRATCH_BYTES of bsps.h
+
+
+def sort_noalloc_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, bucketing: int = SPLITTER,
+                  route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0) -> None:
+    """As sort_(), through bsps_sort_noalloc: no workspace is allocated, the
+    library's per-GPU scratch array is used (sizes whose workspace exceeds
+    NOALLOC_SCRATCH_BYTES are rejected with EUNSUPPORTED)."""
+    assert keys.is_cuda and keys.is_contiguous() and keys.dim() == 1
+    n = keys.numel()
+    if values is not None:
+        assert values.is_cuda and values.is_contiguous() and values.numel() == n and values.element_size() == 4
+    prm = make_params(p, s, variant, seed, bucketing, route, leaves, chunk_cap)
+    code = _lib.bsps_sort_noalloc(ct.c_void_p(keys.data_ptr()), _ptr(values), n, _dtype_code(keys), ct.byref(prm),
+                                  ct.c_void_p(_stream(keys)))
+    if code != OK:
+        raise BspsError(code, "bsps_sort_noalloc")
 
 
 def rank(keys, p: int, spl_keys, spl_pos, bucketing: int = SPLITTER, model=None, buckets=None, counts=None,

@@ -24,7 +24,14 @@
 #include "bsps_segmented.h"
 
 #include <map>
+#include <mutex>
 #include <string>
+
+// Scratch memory of the allocation-free entry point (bsps_sort_noalloc): a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never uses its name as an address: the per-device address comes
+// from hipGetSymbolAddress (scratch_base below).
+static __device__ __align__(256) unsigned char scratch[BSPS_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -108,12 +115,15 @@ struct StageTimer {
     }
 };
 StageTimer g_timer;
+// Set while an allocation-free call enqueues: no timing events are created.
+thread_local bool t_no_events = false;
 struct StageScope {
     int stage;
     hipStream_t st;
     hipEvent_t e0 = nullptr;
     StageScope(int s_, hipStream_t st_) : stage(s_), st(st_) {
-        if (stage < ST_N && g_timer.on && (e0 = g_timer.get()) && hipEventRecord(e0, st) != hipSuccess) e0 = nullptr;
+        if (stage < ST_N && g_timer.on && !t_no_events && (e0 = g_timer.get()) && hipEventRecord(e0, st) != hipSuccess)
+            e0 = nullptr;
     }
     ~StageScope() {
         if (!e0) return;
@@ -504,6 +514,29 @@ bsps_status validate(i64 n, int dtype, const bsps_params* prm) {
     if (n > 1 && cdiv(cdiv((u64)n, (u64)prm->p), T) > (u64)MAXR) return BSPS_EUNSUPPORTED;
     const i64 ns = prm->variant == BSPS_DET ? (i64)prm->p * prm->s : (i64)prm->p * prm->s - 1;
     if (ns > (i64)MAXR * (i64)T || ns >= (i64)0xFFFFFFFFll) return BSPS_EUNSUPPORTED;
+    return BSPS_OK;
+}
+
+// ------------------------------------------------------------------ allocation-free entry point
+
+// Address of `scratch` on the current device, looked up once per device with
+// that device current and kept for later calls.
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices];
+std::mutex g_scratch_mu;
+
+bsps_status scratch_base(void** out) {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return BSPS_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return BSPS_EDEVICE;
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
     return BSPS_OK;
 }
 
@@ -1308,6 +1341,32 @@ bsps_status bsps_sort(void* keys, int64_t n, int32_t dtype, const bsps_params* p
 bsps_status bsps_sort_kv(void* keys, uint32_t* values, int64_t n, int32_t dtype, const bsps_params* prm, void* ws,
                          size_t ws_bytes, void* stream, bsps_stats* st) {
     return dispatch_sort<true>(keys, values, n, dtype, prm, ws, ws_bytes, stream, st);
+}
+
+bsps_status bsps_sort_noalloc(void* keys, uint32_t* values, int64_t n, int32_t dtype, const bsps_params* prm,
+                              void* stream) {
+    bsps_status rc = validate(n, dtype, prm);
+    if (rc) return rc;
+    if (n <= 1) return BSPS_OK;
+    if (!keys) return BSPS_EINVAL;
+    const size_t need = bsps_workspace_bytes(n, dtype, values != nullptr, prm);
+    if (need == 0) return BSPS_EINVAL;
+    if (need > BSPS_NOALLOC_SCRATCH_BYTES) return BSPS_EUNSUPPORTED;
+    void* ws = nullptr;
+    rc = scratch_base(&ws);
+    if (rc) return rc;
+    // the sort clears every counter it reads before use, so the previous
+    // call's contents of the scratch do not matter
+    t_no_events = true;
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == BSPS_I64)
+        rc = values ? run_sort<u64, true>(keys, values, n, dtype, prm, ws, BSPS_NOALLOC_SCRATCH_BYTES, s, nullptr)
+                    : run_sort<u64, false>(keys, nullptr, n, dtype, prm, ws, BSPS_NOALLOC_SCRATCH_BYTES, s, nullptr);
+    else
+        rc = values ? run_sort<u32, true>(keys, values, n, dtype, prm, ws, BSPS_NOALLOC_SCRATCH_BYTES, s, nullptr)
+                    : run_sort<u32, false>(keys, nullptr, n, dtype, prm, ws, BSPS_NOALLOC_SCRATCH_BYTES, s, nullptr);
+    t_no_events = false;
+    return rc;
 }
 
 size_t bsps_fit_workspace_bytes(int64_t N, int32_t leaves) {
