@@ -134,35 +134,181 @@ def test_rank_entry_point(ora, dev, p, bucketing):
         assert st["mispredict_rate"] < 0.3, st
 
 
+# ----------------------------------------------------------------- learned model vs the oracle
+#
+# Training and inference take one integer decision in floating point: the leaf
+# floor(L r(x)) of every sample. The GPU takes it in FP32, the oracle in FP64.
+# The test samples are therefore built so that every sample's L r(x) lies far
+# (about 0.15 leaf widths or more) from a leaf boundary, while each leaf's own
+# data is not a straight line: leaf l holds k keys at design positions
+# w = (l + z_j) / L, with z_j in [0.15, 0.85] drawn per leaf and mirrored about
+# 1/2 (z_j + z_{k-1-j} = 1). The targets are y = (l + (j + 1/2)/k) / L, so
+# y - w depends on j only through a pattern that averages to zero in every leaf;
+# the least-squares root then predicts L r = l + z_j up to terms of order
+# 1/L^2, and both sides put every sample in leaf l. The FP32 root and x differ
+# from FP64 by a few 1e-4 leaf widths at L = 4096.
+
+
+def _f32_from_order(ok):
+    """float32 values whose totalOrder keys are `ok` (inverse of the order map)."""
+    ok = ok.astype(np.uint32)
+    bits = np.where(ok & np.uint32(0x80000000), ok & np.uint32(0x7FFFFFFF), ~ok)
+    return bits.astype(np.uint32).view(np.float32)
+
+
+def _leaf_pos(root, lohi, okeys, L):
+    """L r(x) of each order key in FP64 (the value the leaf decision floors)."""
+    lo, hi = lohi
+    x = (okeys.astype(np.float64) - lo) / (hi - lo)
+    return (root[0] * (x - root[2]) + root[1]) * L
+
+
+def _leafy_sample(L, k, seed):
+    """Order keys (uint64, sorted, distinct) of L*k positive float32 keys laid
+    out as described above, spanning 2^16 order-key units per leaf."""
+    rng = np.random.default_rng(seed)
+    half = np.stack([0.15 + np.sort(rng.choice(22000, size=k // 2, replace=False)) / 65536.0 for _ in range(L)])
+    z = np.concatenate([half, 1.0 - half[:, ::-1]], axis=1)
+    w = (np.arange(L)[:, None] + z).reshape(-1)
+    ok = (0x80000000 + (1 << 20) + np.round(w * (1 << 16))).astype(np.uint64)
+    assert np.all(np.diff(ok) > 0)
+    return ok
+
+
+def _check_margins(ora, ok, m, L, root=None):
+    v = _leaf_pos(m["root"] if root is None else root, m["lohi"], ok, L)
+    lid = np.clip(np.floor(v), 0, L - 1).astype(np.int64)
+    fr = v - np.floor(v)
+    assert np.min(np.minimum(fr, 1 - fr)) > 0.1, "a sample lies near a leaf boundary"
+    return lid
+
+
+@pytest.mark.parametrize("iters", [1, 2])
+def test_model_fit_matches_oracle(ora, dev, iters):
+    """Fit kernels (init, centres, forward, backward, Newton update; root then
+    leaves) against the oracle's FP64 fit of the same sorted sample: the range,
+    the root line and every leaf's centre, slope and intercept, for one and two
+    Newton iterations. p = 1024, s = 64, L = 4096 as in the learned workload."""
+    import paper_1408_6729_amd as bsps
+    p, s, L = 1024, 64, 4096
+    ok = _leafy_sample(L, 16, seed=11)
+    m = ora.rmi_fit(ok, p, s, L, iters)
+    model = bsps.fit_model(_t(_f32_from_order(ok), dev), p, s, leaves=L, iters=iters)
+    hdr, leaf = bsps.model_fields(model)
+    assert (hdr["lo"], hdr["hi"]) == tuple(m["lohi"])
+    assert hdr["L"] == L and hdr["p"] == p and hdr["s"] == s
+    # root: sums of N = 2^16 terms by FP32 tree reductions (see the design notes)
+    assert np.allclose([hdr["a"], hdr["b"], hdr["mur"]], m["root"], rtol=1e-4, atol=1e-6)
+    c, d, mu = (leaf[:, i].astype(np.float64) for i in range(3))
+    # leaf membership by the oracle's root; the margin makes it the GPU's too
+    lid = _check_margins(ora, ok, m, L)
+    x = (ok.astype(np.float64) - m["lohi"][0]) / (m["lohi"][1] - m["lohi"][0])
+    cnt = np.bincount(lid, minlength=L)
+    sx = np.bincount(lid, weights=x, minlength=L)
+    sxx = np.bincount(lid, weights=x * x, minlength=L)
+    sig = np.sqrt(np.maximum(sxx / np.maximum(cnt, 1) - (sx / np.maximum(cnt, 1)) ** 2, 0))
+    empty = cnt == 0
+    # empty leaves: c = 0, d = (samples below) / (p s), exactly in FP32
+    assert np.array_equal(c[empty], np.zeros(empty.sum()))
+    below = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    assert np.array_equal(leaf[empty, 1], (below[empty] / (p * s)).astype(np.float32))
+    used = ~empty
+    eps = 2.0 ** -23  # bound of the FP32 error of x (rounding of u - lo and of 1/(hi - lo))
+    assert np.all(np.abs(mu[used] - m["mu"][used]) <= 4 * eps + 1e-5 * np.abs(m["mu"][used]))
+    assert np.all(np.abs(d[used] - m["d"][used]) <= 2e-5)
+    # slope: relative error about 2 eps / sigma_x of the leaf (centred x); leaves
+    # whose x spread is below FP32 resolution are singular on either side
+    ok_c = used & (sig > 2.0 ** -16) & (cnt >= 2)
+    tol = np.abs(m["c"][ok_c]) * (1e-4 + 8 * eps / sig[ok_c]) + 1e-6
+    err = np.abs(c[ok_c] - m["c"][ok_c])
+    assert np.all(err <= tol), (err / tol).max()
+    assert ok_c.sum() > 0.8 * used.sum()
+    # the leaves' data are not lines: the fit leaves a residual
+    assert np.abs(m["c"][used] - 1).max() > 1e-3
+
+
+@pytest.mark.parametrize("L", [2, 8])
+@pytest.mark.parametrize("iters", [1, 2])
+def test_model_fit_hand_worked(dev, L, iters):
+    """The GPU fit of the 8-key example worked by hand (tests/golden/rmi_worked_n8.json):
+    root, leaf lines, centres and the empty-leaf intercepts of L = 8, in FP32."""
+    import json
+    import os
+    from fractions import Fraction
+    import paper_1408_6729_amd as bsps
+    with open(os.path.join(os.path.dirname(__file__), "golden", "rmi_worked_n8.json")) as f:
+        g = json.load(f)
+    u = np.array(g["sample_okeys"], dtype=np.int64)
+    keys = (u - (1 << 31)).astype(np.int32)  # int32 keys whose order keys are u
+    model = bsps.fit_model(_t(keys, dev), g["p"], g["s"], leaves=L, iters=iters)
+    hdr, leaf = bsps.model_fields(model)
+    assert (hdr["lo"], hdr["hi"]) == tuple(float(v) for v in g["lohi"])
+    fr = lambda v: float(Fraction(v))  # noqa: E731
+    assert np.allclose([hdr["a"], hdr["b"], hdr["mur"]], [fr(g["root"][k]) for k in ("a", "b", "mu_r")],
+                       rtol=0, atol=2e-6)
+    e = g["models"][str(L)]
+    for i, name in enumerate(("c", "d", "mu")):
+        assert np.allclose(leaf[:, i], [fr(v) for v in e[name]], rtol=0, atol=4e-6), name
+
+
+@pytest.mark.parametrize("k", [1, 16])
+def test_model_fit_equally_spaced(dev, k):
+    """Equally spaced sample keys, the closed form of the CPU pin: root a = (N-1)/N,
+    b = mu_r = 1/2, leaf l: c = (N-1)/N (0 for one-record leaves),
+    mu = (l k + (k-1)/2)/(N-1), d = (l k + k/2)/N, at L = 4096."""
+    import paper_1408_6729_amd as bsps
+    L = 4096
+    N = L * k
+    p = 1024 if N >= 1024 else N
+    s = N // p
+    t = np.arange(N)
+    keys = (1000 + 7 * t - (1 << 31)).astype(np.int32)
+    model = bsps.fit_model(_t(keys, dev), p, s, leaves=L, iters=1)
+    hdr, leaf = bsps.model_fields(model)
+    a = (N - 1) / N
+    assert np.allclose([hdr["a"], hdr["b"], hdr["mur"]], [a, 0.5, 0.5], rtol=0, atol=1e-5)
+    lidx = np.arange(L)
+    # slope: relative error about 8 eps / sigma_x of a leaf (eps = 2^-23, sigma_x =
+    # sqrt((k^2 - 1)/12) / (N - 1) for k equally spaced records)
+    sig = np.sqrt((k * k - 1) / 12) / (N - 1)
+    tol = a * 8 * 2.0 ** -23 / sig if k > 1 else 0.0
+    assert np.allclose(leaf[:, 0], np.full(L, a if k > 1 else 0.0), rtol=0, atol=tol + 1e-7)
+    assert np.allclose(leaf[:, 2], (lidx * k + (k - 1) / 2) / (N - 1), rtol=0, atol=1e-6)
+    assert np.allclose(leaf[:, 1], (lidx * k + k / 2) / N, rtol=0, atol=1e-6)
+
+
 def test_model_gradient_matches_fp64(ora, dev):
-    """Backward kernel: FP32 gradient and Gram sums equal the FP64 oracle's at
-    the same parameters and leaf assignment."""
+    """Forward and backward kernels at given parameters: the oracle's FP64 fit
+    rounded to FP32 and perturbed (seeded), written into the model buffer. The
+    FP32 gradient, Gram sums and loss equal the oracle's FP64 ones at the same
+    parameters, with the leaf of every sample decided alike on both sides."""
     import torch
     import paper_1408_6729_amd as bsps
-    n, p, s, L = 1 << 20, 256, 64, 512
-    keys = W.lognormal_f32(n, zeros=32)
-    ref = ora.sort(keys, p, s, ora.DET)
-    smp = ref["B_keys"][ref["sample_pos"]]
-    smp_t = _t(smp, dev)
-    model = bsps.fit_model(smp_t, p, s, leaves=L, iters=2)
-    # perturb the fitted leaves so the gradient is far from zero
-    hdr, leaf = bsps.model_fields(model)
+    p, s, L = 256, 64, 512
+    ok = _leafy_sample(L, 32, seed=12)
+    m = ora.rmi_fit(ok, p, s, L, 2)
     rng = np.random.default_rng(1)
-    leaf = leaf.copy()
-    leaf[:, 0] *= 1 + 0.1 * rng.standard_normal(L).astype(np.float32)
-    leaf[:, 1] += 0.01 * rng.standard_normal(L).astype(np.float32)
-    raw = model.cpu().numpy().copy()
-    raw[48:48 + 12 * L] = np.frombuffer(leaf.astype(np.float32).tobytes(), dtype=np.uint8)
+    c = (m["c"] * (1 + 0.1 * rng.standard_normal(L))).astype(np.float32)
+    d = (m["d"] + 0.01 * rng.standard_normal(L)).astype(np.float32)
+    mu = m["mu"].astype(np.float32)
+    root = m["root"].astype(np.float32)
+    lo, hi = m["lohi"]
+    hdr = np.zeros(48, dtype=np.uint8)
+    hdr[0:16] = np.frombuffer(np.array([lo, hi], dtype=np.float64).tobytes(), dtype=np.uint8)
+    inv = np.float32(1.0 / (hi - lo))
+    hdr[16:32] = np.frombuffer(np.array([root[0], root[1], root[2], inv], dtype=np.float32).tobytes(), np.uint8)
+    hdr[32:48] = np.frombuffer(np.array([L, p, s, 0], dtype=np.int32).tobytes(), dtype=np.uint8)
+    tab = np.stack([c, d, mu], axis=1).astype(np.float32)
+    raw = np.concatenate([hdr, np.frombuffer(tab.tobytes(), dtype=np.uint8)])
     model = torch.from_numpy(raw).to(dev)
+    smp_t = _t(_f32_from_order(ok), dev)
     lid, grad, gram, loss = bsps.model_grad(smp_t, p, s, L, model)
     torch.cuda.synchronize()
-    lid = lid.cpu().numpy()
-    u = ora.order_keys(smp).astype(np.float64)
-    x = ((u - hdr["lo"]) * np.float64(hdr["inv"])).astype(np.float32).astype(np.float64)
-    y = (np.arange(smp.size) + 0.5) / (p * s)
-    assert (np.diff(lid) >= 0).all()
-    l64, g64, h64 = ora.rmi_grad(x, y, lid, leaf[:, 0].astype(np.float64), leaf[:, 1].astype(np.float64),
-                                 leaf[:, 2].astype(np.float64))
+    lid_ref = _check_margins(ora, ok, m, L, root.astype(np.float64)).astype(np.int32)
+    assert np.array_equal(lid.cpu().numpy(), lid_ref)
+    x = (ok.astype(np.float64) - lo) / (hi - lo)
+    y = (np.arange(ok.size) + 0.5) / (p * s)
+    l64, g64, h64 = ora.rmi_grad(x, y, lid_ref, c.astype(np.float64), d.astype(np.float64), mu.astype(np.float64))
     g = grad.cpu().numpy().astype(np.float64)
     h = gram.cpu().numpy().astype(np.float64)
     scale = np.abs(g64).max()

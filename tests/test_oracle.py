@@ -405,3 +405,64 @@ def test_rmi_fit_predicts_close_and_correction_is_exact(ora):
         while b < p - 1 and spl[b] < rec:
             b += 1
         assert b == true[g]
+
+
+# ----------------------------------------------------------------- learned model: closed forms
+
+def _frac(v):
+    from fractions import Fraction
+    return float(Fraction(v))
+
+
+@pytest.mark.parametrize("L", [2, 8])
+@pytest.mark.parametrize("iters", [1, 2])
+def test_rmi_fit_hand_worked(ora, L, iters):
+    """The two-stage model fitted by hand on 8 keys (tests/golden/rmi_worked_n8.json):
+    root line, leaf lines, centres, the empty-leaf intercepts (samples below over p*s)
+    and the clamped predictions. A target of t/(p s) instead of (t + 1/2)/(p s), a
+    dropped root or leaf Newton step or a wrong empty-leaf intercept fails here."""
+    g = _gold("rmi_worked_n8.json")
+    sk = np.array(g["sample_okeys"], dtype=np.uint64)
+    m = ora.rmi_fit(sk, g["p"], g["s"], L, iters)
+    assert m["lohi"].tolist() == g["lohi"]
+    exp_root = [_frac(g["root"][k]) for k in ("a", "b", "mu_r")]
+    assert np.allclose(m["root"], exp_root, rtol=0, atol=1e-12)
+    e = g["models"][str(L)]
+    for name in ("c", "d", "mu"):
+        assert np.allclose(m[name], [_frac(v) for v in e[name]], rtol=0, atol=1e-12), name
+    pr = g["predict"][str(L)]
+    got = ora.rmi_predict(m, np.array(pr["u"], dtype=np.uint64))
+    assert got.tolist() == pr["bucket"]
+
+
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_rmi_fit_equally_spaced_is_exact(ora, k):
+    """Equally spaced sample keys u_t = 1000 + 7t, N = L k = p s: the sample CDF is
+    a line, so the fit is exact (closed form): root a = (N-1)/N, b = mu_r = 1/2; leaf l
+    holds t in [l k, l k + k) with c = (N-1)/N (0 for a one-record leaf), mu = (l k + (k-1)/2)/(N-1),
+    d = (l k + k/2)/N; the loss is zero, every sample key is predicted in its
+    own bucket floor(t/s), and a key 4/7 of the way from sample t to sample
+    t+1 has f = (t + 4/7 + 1/2)/N, i.e. bucket floor((t+1)/s)."""
+    L = 64
+    N = L * k
+    p = 16
+    s = N // p
+    t = np.arange(N)
+    sk = (1000 + 7 * t).astype(np.uint64)
+    m = ora.rmi_fit(sk, p, s, L, 1)
+    a = (N - 1) / N
+    assert np.allclose(m["root"], [a, 0.5, 0.5], rtol=0, atol=1e-12)
+    lidx = np.arange(L)
+    # one record per leaf (k = 1) is a singular leaf: only the intercept moves
+    assert np.allclose(m["c"], np.full(L, a if k > 1 else 0.0), rtol=0, atol=1e-9)
+    assert np.allclose(m["mu"], (lidx * k + (k - 1) / 2) / (N - 1), rtol=0, atol=1e-12)
+    assert np.allclose(m["d"], (lidx * k + k / 2) / N, rtol=0, atol=1e-12)
+    # zero loss at the fitted parameters
+    x = (sk.astype(np.float64) - 1000) / (7 * (N - 1))
+    y = (t + 0.5) / (p * s)
+    leaf = t // k
+    loss, _, _ = ora.rmi_grad(x, y, leaf.astype(np.int32), m["c"], m["d"], m["mu"])
+    assert loss < 1e-24
+    assert ora.rmi_predict(m, sk).tolist() == (t // s).tolist()
+    mid = (1000 + 7 * t[:-1] + 4).astype(np.uint64)
+    assert ora.rmi_predict(m, mid).tolist() == ((t[:-1] + 1) // s).tolist()
