@@ -19,6 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bsp_oracle.c")
+_SRC_MT = os.path.join(_HERE, "bsp_oracle_mt.c")
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 DET, RAN = 0, 1
@@ -26,11 +27,12 @@ KIND = {"int32": 0, "int64": 1, "float32": 2}
 
 
 def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (-O2, no SIMD intrinsics, single thread)."""
+    """Compile liboracle.so with gcc (-O2, no SIMD intrinsics): the
+    single-thread oracle and its threaded driver."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-                               "-Wno-unused-parameter", _SRC, "-o", tmp, "-lm"])
+                               "-Wno-unused-parameter", "-pthread", _SRC, _SRC_MT, "-o", tmp, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -61,6 +63,7 @@ def lib():
         L.ora_sort.argtypes = [u64p, ct.c_int64, ct.c_int, ct.c_int, ct.c_int, ct.c_uint64,
                                i64p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        L.ora_sort_mt.argtypes = L.ora_sort.argtypes + [ct.c_int]
         L.ora_rank.argtypes = [u64p, ct.c_int64, u64p, i64p, ct.c_int, i64p]
         L.ora_rmi_grad.restype = ct.c_double
         L.ora_rmi_grad.argtypes = [f64p, f64p, i32p, ct.c_int64, ct.c_int, f64p, f64p, f64p, f64p, f64p]
@@ -115,9 +118,20 @@ class OracleError(ValueError):
     pass
 
 
+def default_threads() -> int:
+    """Host threads for the threaded driver: the cores this process may use,
+    at most 16 (the CPU share of one GPU on the GPU machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def sort(keys: np.ndarray, p: int, s: int, variant: int = DET, seed: int = 1,
-         values: np.ndarray | None = None, intermediates: bool = True) -> dict:
-    """Run the simulated BSP sort. Returns a dict with
+         values: np.ndarray | None = None, intermediates: bool = True, threads: int = 1) -> dict:
+    """Run the simulated BSP sort (threads > 1: the same per-processor steps
+    spread over that many host threads, byte-identical result). Returns a dict with
     keys, values (if given), perm, and when `intermediates`:
     B_keys/B_perm (block-sorted), sample_key/sample_pos (sorted sample, order keys
     and positions in the block-sorted array), spl_key/spl_pos (p-1 splitters),
@@ -142,7 +156,10 @@ def sort(keys: np.ndarray, p: int, s: int, variant: int = DET, seed: int = 1,
         Z = np.empty(max(n, 1), dtype=np.int64)
         args = [B.ctypes.data, sk.ctypes.data, sp.ctypes.data, pk.ctypes.data, pp.ctypes.data,
                 C.ctypes.data, Z.ctypes.data]
-    rc = lib().ora_sort(ok, n, p, s, variant, seed & 0xFFFFFFFFFFFFFFFF, perm, *args)
+    if threads > 1:
+        rc = lib().ora_sort_mt(ok, n, p, s, variant, seed & 0xFFFFFFFFFFFFFFFF, perm, *args, int(threads))
+    else:
+        rc = lib().ora_sort(ok, n, p, s, variant, seed & 0xFFFFFFFFFFFFFFFF, perm, *args)
     if rc:
         raise OracleError(f"oracle failed rc={rc}")
     perm = perm[:n]

@@ -144,14 +144,43 @@ static int item_cmp(const void* pa, const void* pb) {
     return a->idx < b->idx ? -1 : (a->idx > b->idx ? 1 : 0);  /* ties keep input order */
 }
 
-/* B_key/B_idx receive the block-sorted keys and the original index of each. */
-static void local_sort(const uint64_t* ok, int64_t n, int p, uint64_t* B_key, int64_t* B_idx, item_t* tmp) {
-    for (int k = 0; k < p; k++) {
-        int64_t a = ora_block_start(n, p, k), b = ora_block_start(n, p, k + 1);
-        for (int64_t g = a; g < b; g++) { tmp[g - a].key = ok[g]; tmp[g - a].idx = g; }
-        qsort(tmp, (size_t)(b - a), sizeof(item_t), item_cmp);
-        for (int64_t g = a; g < b; g++) { B_key[g] = tmp[g - a].key; B_idx[g] = tmp[g - a].idx; }
-    }
+/* One simulated run: the arrays every step reads and writes. Each step below
+ * is the work of ONE virtual processor and touches only that processor's
+ * share of the output arrays, so the p processors may be simulated one after
+ * the other (ora_sort) or on host threads (the driver in bsp_oracle_mt.c)
+ * with the same result. */
+typedef struct ora_run {
+    const uint64_t* ok;  /* input order keys */
+    int64_t n;
+    int p;
+    uint64_t* B_key;     /* block-sorted keys */
+    int64_t* B_idx;      /* their original indices */
+    const rec_t* S;      /* the p-1 splitters */
+    int64_t* bucket;     /* bucket of every block-sorted record */
+    int64_t* C;          /* C[k*p + i] */
+    const int64_t* off;  /* routing offsets off[k*p + i] */
+    uint64_t* Z_key;     /* routed array */
+    int64_t* Z_idx;
+    int64_t* perm;       /* output: original index of output element j */
+    int bad;             /* set when a step finds an inconsistency */
+} ora_run_t;
+
+/* Scratch one processor needs for any step: ceil(n/p) items (local sort)
+ * or the heap of the p-way merge. */
+size_t ora_step_scratch_bytes(int64_t n, int p) {
+    size_t a = sizeof(item_t) * (size_t)((n + p - 1) / p);
+    size_t b = (sizeof(int) + 2 * sizeof(int64_t)) * (size_t)p;
+    return (a > b ? a : b) + 64;
+}
+
+/* O2 for processor k: sort its share stably; B receives the sorted keys and
+ * the original index of each. */
+void ora_step_local_sort(ora_run_t* R, int k, void* scratch) {
+    item_t* tmp = (item_t*)scratch;
+    int64_t a = ora_block_start(R->n, R->p, k), b = ora_block_start(R->n, R->p, k + 1);
+    for (int64_t g = a; g < b; g++) { tmp[g - a].key = R->ok[g]; tmp[g - a].idx = g; }
+    qsort(tmp, (size_t)(b - a), sizeof(item_t), item_cmp);
+    for (int64_t g = a; g < b; g++) { R->B_key[g] = tmp[g - a].key; R->B_idx[g] = tmp[g - a].idx; }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -206,23 +235,120 @@ static int64_t bucket_of(rec_t r, const rec_t* S, int64_t nsplit) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Steps O6, O8, O9 for one processor                                        */
+/* ------------------------------------------------------------------------ */
+
+/* O6 for processor k: partition its sorted keys by the splitters (Figure
+ * SortD step 9) and count C[k][i]. The bucket ids along a sorted block never
+ * decrease; a decrease would mean the block is not sorted. */
+void ora_step_partition(ora_run_t* R, int k) {
+    int p = R->p;
+    int64_t a = ora_block_start(R->n, p, k), b = ora_block_start(R->n, p, k + 1);
+    int64_t prev = 0;
+    for (int64_t g = a; g < b; g++) {
+        rec_t r = {R->B_key[g], g};
+        int64_t bk = bucket_of(r, R->S, p - 1);
+        if (bk < prev) R->bad = 1;
+        prev = bk;
+        R->bucket[g] = bk;
+        R->C[(int64_t)k * p + bk]++;
+    }
+}
+
+/* O8 for processor k: send each of its runs to its offset, order preserving
+ * (Figure SortD steps 10-11). */
+void ora_step_route(ora_run_t* R, int k, void* scratch) {
+    int p = R->p;
+    int64_t* cur = (int64_t*)scratch;  /* next free slot of each of k's runs */
+    for (int i = 0; i < p; i++) cur[i] = R->off[(int64_t)k * p + i];
+    int64_t a = ora_block_start(R->n, p, k), b = ora_block_start(R->n, p, k + 1);
+    for (int64_t g = a; g < b; g++) {
+        int64_t d = cur[R->bucket[g]]++;
+        R->Z_key[d] = R->B_key[g];
+        R->Z_idx[d] = R->B_idx[g];
+    }
+}
+
+/* O9 for processor i: merge the sorted runs it received; on equal keys the
+ * run from the lower-numbered processor goes first (Section 5.1.1). A binary
+ * heap over the p run heads, ordered by (key, source). Bucket i's output
+ * starts where its first run starts, off[0][i]. */
+void ora_step_merge(ora_run_t* R, int i, void* scratch) {
+    int p = R->p;
+    int* heap = (int*)scratch;
+    int64_t* head = (int64_t*)((char*)scratch + ((sizeof(int) * (size_t)p + 7) & ~(size_t)7));
+    int64_t* end = head + p;
+    const uint64_t* Z_key = R->Z_key;
+    int64_t outpos = R->off[i];
+    int hn = 0;
+    for (int k = 0; k < p; k++) {
+        head[k] = R->off[(int64_t)k * p + i];
+        end[k] = head[k] + R->C[(int64_t)k * p + i];
+        if (head[k] < end[k]) {
+            /* sift up */
+            int c = hn++;
+            heap[c] = k;
+            while (c > 0) {
+                int par = (c - 1) / 2;
+                int u = heap[c], v = heap[par];
+                int less = Z_key[head[u]] < Z_key[head[v]] ||
+                           (Z_key[head[u]] == Z_key[head[v]] && u < v);
+                if (!less) break;
+                heap[c] = v; heap[par] = u; c = par;
+            }
+        }
+    }
+    while (hn > 0) {
+        int k = heap[0];
+        R->perm[outpos++] = R->Z_idx[head[k]];
+        head[k]++;
+        if (head[k] == end[k]) heap[0] = heap[--hn];
+        /* sift down */
+        int c = 0;
+        for (;;) {
+            int l = 2 * c + 1, r = l + 1, m = c;
+            if (l < hn) {
+                int u = heap[l], v = heap[m];
+                if (Z_key[head[u]] < Z_key[head[v]] || (Z_key[head[u]] == Z_key[head[v]] && u < v)) m = l;
+            }
+            if (r < hn) {
+                int u = heap[r], v = heap[m];
+                if (Z_key[head[u]] < Z_key[head[v]] || (Z_key[head[u]] == Z_key[head[v]] && u < v)) m = r;
+            }
+            if (m == c) break;
+            int t = heap[c]; heap[c] = heap[m]; heap[m] = t; c = m;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Whole method                                                               */
 /* ------------------------------------------------------------------------ */
 
+/* Runs step(R, q, scratch) for q = 0..count-1. ora_sort passes the plain loop
+ * below; bsp_oracle_mt.c passes one that spreads q over host threads. */
+typedef void (*ora_step_fn)(ora_run_t* R, int q, void* scratch);
+typedef int (*ora_each_fn)(ora_run_t* R, int count, ora_step_fn step, size_t scratch_bytes, void* ctx);
+
+static int each_sequential(ora_run_t* R, int count, ora_step_fn step, size_t scratch_bytes, void* ctx) {
+    (void)ctx;
+    void* scratch = malloc(scratch_bytes);
+    if (!scratch) return ORA_ENOMEM;
+    for (int q = 0; q < count; q++) step(R, q, scratch);
+    free(scratch);
+    return ORA_OK;
+}
+
+static void step_partition(ora_run_t* R, int k, void* scratch) { (void)scratch; ora_step_partition(R, k); }
+
 /*
- * ora_sort: sorts n order keys with p simulated processors and oversampling
- * parameter s (the splitter stride of the sorted sample).
- *   perm[j]     original index of output element j (required)
- *   B_idx[g]    original index of the block-sorted array element g (optional)
- *   smp_key/pos sorted sample records (optional, ora_sample_size entries)
- *   spl_key/pos the p-1 splitters (optional)
- *   C[k*p+i]    keys of processor k that fall in bucket i (optional)
- *   Z_idx[j]    original index of element j after routing (optional)
- * Returns ORA_OK, ORA_EINVAL (arguments) or ORA_ENOMEM.
+ * The method with a given way of running the per-processor steps (see
+ * ora_sort for the arguments).
  */
-int ora_sort(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t seed,
-             int64_t* perm, int64_t* B_idx_out, uint64_t* smp_key, int64_t* smp_pos,
-             uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out) {
+int ora_sort_driver(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t seed,
+                    int64_t* perm, int64_t* B_idx_out, uint64_t* smp_key, int64_t* smp_pos,
+                    uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out,
+                    ora_each_fn each, void* ctx) {
     int rc = ora_validate(n, p, s, variant);
     if (rc) return rc;
     if (n <= 1) {
@@ -238,9 +364,9 @@ int ora_sort(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t 
         return ORA_OK;
     }
     int64_t ns = ora_sample_size(p, s, variant);
+    size_t scr = ora_step_scratch_bytes(n, p);
     uint64_t* B_key = (uint64_t*)malloc(sizeof(uint64_t) * n);
     int64_t* B_idx = (int64_t*)malloc(sizeof(int64_t) * n);
-    item_t* tmp = (item_t*)malloc(sizeof(item_t) * ((n + p - 1) / p));
     rec_t* smp = (rec_t*)malloc(sizeof(rec_t) * (ns > 0 ? ns : 1));
     rec_t* S = (rec_t*)malloc(sizeof(rec_t) * p);
     int64_t* C = (int64_t*)calloc((size_t)p * p, sizeof(int64_t));
@@ -248,13 +374,18 @@ int ora_sort(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t 
     int64_t* Z_idx = (int64_t*)malloc(sizeof(int64_t) * n);
     uint64_t* Z_key = (uint64_t*)malloc(sizeof(uint64_t) * n);
     int64_t* bucket = (int64_t*)malloc(sizeof(int64_t) * n);
-    if (!B_key || !B_idx || !tmp || !smp || !S || !C || !off || !Z_idx || !Z_key || !bucket) {
+    ora_run_t R;
+    memset(&R, 0, sizeof(R));
+    if (!B_key || !B_idx || !smp || !S || !C || !off || !Z_idx || !Z_key || !bucket) {
         rc = ORA_ENOMEM;
         goto done;
     }
+    R.ok = ok; R.n = n; R.p = p; R.B_key = B_key; R.B_idx = B_idx; R.S = S; R.bucket = bucket;
+    R.C = C; R.off = off; R.Z_key = Z_key; R.Z_idx = Z_idx; R.perm = perm;
 
     /* O2: every processor sorts its share (stable). */
-    local_sort(ok, n, p, B_key, B_idx, tmp);
+    rc = each(&R, p, ora_step_local_sort, scr, ctx);
+    if (rc) goto done;
     if (B_idx_out) memcpy(B_idx_out, B_idx, sizeof(int64_t) * n);
 
     /* O3: sample. O4: sort it by (key, tag). */
@@ -274,20 +405,10 @@ int ora_sort(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t 
         if (spl_pos) spl_pos[i - 1] = S[i - 1].pos;
     }
 
-    /* O6: partition each processor's sorted keys by the splitters
-     * (Figure SortD step 9) and count C[k][i]. */
-    for (int k = 0; k < p; k++) {
-        int64_t a = ora_block_start(n, p, k), b = ora_block_start(n, p, k + 1);
-        int64_t prev = 0;
-        for (int64_t g = a; g < b; g++) {
-            rec_t r = {B_key[g], g};
-            int64_t bk = bucket_of(r, S, p - 1);
-            if (bk < prev) { rc = ORA_EINVAL; goto done; }  /* cannot happen: block is sorted */
-            prev = bk;
-            bucket[g] = bk;
-            C[(int64_t)k * p + bk]++;
-        }
-    }
+    /* O6: partition each processor's sorted keys by the splitters and count. */
+    rc = each(&R, p, step_partition, 64, ctx);
+    if (rc) goto done;
+    if (R.bad) { rc = ORA_EINVAL; goto done; }  /* cannot happen: blocks are sorted */
     if (C_out) memcpy(C_out, C, sizeof(int64_t) * p * p);
 
     /* O7: the p independent prefix computations: bucket i starts after all
@@ -305,80 +426,37 @@ int ora_sort(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t 
         }
     }
 
-    /* O8: routing, order preserving (Figure SortD steps 10-11). */
-    {
-        int64_t* cur = (int64_t*)malloc(sizeof(int64_t) * p * p);
-        if (!cur) { rc = ORA_ENOMEM; goto done; }
-        memcpy(cur, off, sizeof(int64_t) * p * p);
-        for (int k = 0; k < p; k++) {
-            int64_t a = ora_block_start(n, p, k), b = ora_block_start(n, p, k + 1);
-            for (int64_t g = a; g < b; g++) {
-                int64_t d = cur[(int64_t)k * p + bucket[g]]++;
-                Z_key[d] = B_key[g];
-                Z_idx[d] = B_idx[g];
-            }
-        }
-        free(cur);
-    }
+    /* O8: routing, order preserving. */
+    rc = each(&R, p, ora_step_route, scr, ctx);
+    if (rc) goto done;
     if (Z_idx_out) memcpy(Z_idx_out, Z_idx, sizeof(int64_t) * n);
 
-    /* O9: every processor merges the sorted runs it received; on equal keys
-     * the run from the lower-numbered processor goes first (Section 5.1.1).
-     * A binary heap over the p run heads, ordered by (key, source). */
-    {
-        int* heap = (int*)malloc(sizeof(int) * p);
-        int64_t* head = (int64_t*)malloc(sizeof(int64_t) * p);
-        int64_t* end = (int64_t*)malloc(sizeof(int64_t) * p);
-        if (!heap || !head || !end) { free(heap); free(head); free(end); rc = ORA_ENOMEM; goto done; }
-        int64_t outpos = 0;
-        for (int i = 0; i < p; i++) {
-            int hn = 0;
-            for (int k = 0; k < p; k++) {
-                head[k] = off[(int64_t)k * p + i];
-                end[k] = head[k] + C[(int64_t)k * p + i];
-                if (head[k] < end[k]) {
-                    /* sift up */
-                    int c = hn++;
-                    heap[c] = k;
-                    while (c > 0) {
-                        int par = (c - 1) / 2;
-                        int u = heap[c], v = heap[par];
-                        int less = Z_key[head[u]] < Z_key[head[v]] ||
-                                   (Z_key[head[u]] == Z_key[head[v]] && u < v);
-                        if (!less) break;
-                        heap[c] = v; heap[par] = u; c = par;
-                    }
-                }
-            }
-            while (hn > 0) {
-                int k = heap[0];
-                perm[outpos++] = Z_idx[head[k]];
-                head[k]++;
-                if (head[k] == end[k]) heap[0] = heap[--hn];
-                /* sift down */
-                int c = 0;
-                for (;;) {
-                    int l = 2 * c + 1, r = l + 1, m = c;
-                    if (l < hn) {
-                        int u = heap[l], v = heap[m];
-                        if (Z_key[head[u]] < Z_key[head[v]] || (Z_key[head[u]] == Z_key[head[v]] && u < v)) m = l;
-                    }
-                    if (r < hn) {
-                        int u = heap[r], v = heap[m];
-                        if (Z_key[head[u]] < Z_key[head[v]] || (Z_key[head[u]] == Z_key[head[v]] && u < v)) m = r;
-                    }
-                    if (m == c) break;
-                    int t = heap[c]; heap[c] = heap[m]; heap[m] = t; c = m;
-                }
-            }
-        }
-        free(heap); free(head); free(end);
-    }
+    /* O9: every processor merges the runs it received. */
+    rc = each(&R, p, ora_step_merge, scr, ctx);
 
 done:
-    free(B_key); free(B_idx); free(tmp); free(smp); free(S); free(C); free(off);
+    free(B_key); free(B_idx); free(smp); free(S); free(C); free(off);
     free(Z_idx); free(Z_key); free(bucket);
     return rc;
+}
+
+/*
+ * ora_sort: sorts n order keys with p simulated processors and oversampling
+ * parameter s (the splitter stride of the sorted sample), the processors
+ * simulated one after the other.
+ *   perm[j]     original index of output element j (required)
+ *   B_idx[g]    original index of the block-sorted array element g (optional)
+ *   smp_key/pos sorted sample records (optional, ora_sample_size entries)
+ *   spl_key/pos the p-1 splitters (optional)
+ *   C[k*p+i]    keys of processor k that fall in bucket i (optional)
+ *   Z_idx[j]    original index of element j after routing (optional)
+ * Returns ORA_OK, ORA_EINVAL (arguments) or ORA_ENOMEM.
+ */
+int ora_sort(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t seed,
+             int64_t* perm, int64_t* B_idx_out, uint64_t* smp_key, int64_t* smp_pos,
+             uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out) {
+    return ora_sort_driver(ok, n, p, s, variant, seed, perm, B_idx_out, smp_key, smp_pos, spl_key, spl_pos,
+                           C_out, Z_idx_out, each_sequential, NULL);
 }
 
 /* Bucket of each record (key, g) of a block-sorted array against given

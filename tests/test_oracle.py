@@ -466,3 +466,19 @@ def test_rmi_fit_equally_spaced_is_exact(ora, k):
     assert ora.rmi_predict(m, sk).tolist() == (t // s).tolist()
     mid = (1000 + 7 * t[:-1] + 4).astype(np.uint64)
     assert ora.rmi_predict(m, mid).tolist() == ((t[:-1] + 1) // s).tolist()
+
+
+# ----------------------------------------------------------------- threaded driver
+
+@pytest.mark.parametrize("dtype,variant,p,s,n", [("int32", 0, 16, 8, 100003), ("int64", 1, 64, 16, 70001),
+                                                 ("float32", 0, 7, 3, 5000), ("int32", 1, 128, 32, 1 << 18)])
+def test_threaded_driver_is_byte_identical(ora, dtype, variant, p, s, n):
+    """The per-processor steps on host threads give exactly the single-thread
+    oracle's output and every intermediate (ties included)."""
+    keys = W.random_keys(n, dtype, seed=n, distinct=n // 7)
+    vals = np.arange(n, dtype=np.uint32)
+    a = ora.sort(keys, p, s, variant, 3, vals)
+    for threads in (2, 5):
+        b = ora.sort(keys, p, s, variant, 3, vals, threads=threads)
+        for k in ("perm", "B_perm", "sample_key", "sample_pos", "spl_key", "spl_pos", "C", "Z_perm"):
+            assert np.array_equal(a[k], b[k]), (k, threads)
