@@ -169,3 +169,78 @@ def test_learned_large_segments(ora, dev):
         st2 = _check(ora, dev, k2, offs, values=vals, tuning=on, table=table)
         assert st2["learned_segments"] > 0
     del torch
+
+
+def test_learned_training_matches_oracle(ora, dev):
+    """The batched training kernels of the large segments (x, centres, forward,
+    backward, Newton update; root then 64 leaves, one step each) against the
+    oracle: for every large segment of a C5-like batch, the model's range and
+    root equal the oracle's fit of the oracle's own sample of that segment, and
+    every leaf whose membership both sides decide alike has the oracle's
+    centre, leaf-stage gradient and Gram sums (at c = d = 0) and Newton step.
+
+    A leaf is decided alike when no sample's L r(x) lies within 2e-4 leaf
+    widths of either of its boundaries: the FP32 root and x differ from FP64 by
+    about 2e-5 leaf widths at L = 64 (see the design notes)."""
+    import torch
+    import paper_1408_6729_amd as bsps
+    sizes = W.segment_sizes(48, 14, 19, seed=17)
+    keys, offs = W.segmented_int32(sizes, seed=17)
+    table = _default_table()
+    classes = [{"max_log2": a, "block": b, "s": c} for a, b, c in table]
+    on = json.dumps({"learned_above_log2": 16, "classes": classes})
+    prm = _params("int32", table)
+    large = [i for i, n in enumerate(sizes) if n > (1 << 16) and prm(i, int(n))[0] >= 2]
+    assert len(large) >= 5
+    t = torch.from_numpy(keys.copy()).to(dev)
+    st = bsps.sort_segmented_(t, offs, tuning=on, stats=True, models=len(large))
+    torch.cuda.synchronize()
+    assert st["learned_segments"] == len(large)
+    Lf = bsps.SEG_LEAVES
+    mb = bsps.model_bytes(Lf)
+    eps = 2.0 ** -23
+    compared = leaves_used = 0
+    for j, i in enumerate(large):
+        seg = keys[offs[i]:offs[i + 1]]
+        p, s, _, _ = prm(i, seg.size)
+        sk = ora.sort(seg, p, s, ora.DET)["sample_key"]
+        m = ora.rmi_fit(sk, p, s, Lf, 1)
+        hdr, leaf = bsps.model_fields(st["models"][j * mb:(j + 1) * mb])
+        assert (hdr["L"], hdr["p"], hdr["s"]) == (Lf, p, s)
+        assert (hdr["lo"], hdr["hi"]) == tuple(m["lohi"])
+        assert np.allclose([hdr["a"], hdr["b"], hdr["mur"]], m["root"], rtol=1e-4, atol=1e-6), (i, hdr, m["root"])
+        lo, hi = m["lohi"]
+        x = (sk.astype(np.float64) - lo) / (hi - lo)
+        v = (m["root"][0] * (x - m["root"][2]) + m["root"][1]) * Lf
+        lid = np.clip(np.floor(v), 0, Lf - 1).astype(np.int64)
+        near = (np.abs(v - np.round(v)) < 2e-4) & (v > 0.5) & (v < Lf - 0.5)
+        dirty = np.zeros(Lf, dtype=bool)
+        for bnd in np.round(v[near]).astype(np.int64):
+            dirty[max(bnd - 1, 0)] = dirty[min(bnd, Lf - 1)] = True
+        y = (np.arange(sk.size) + 0.5) / (p * s)
+        _, g64, h64 = ora.rmi_grad(x, y, lid.astype(np.int32), np.zeros(Lf), np.zeros(Lf), m["mu"])
+        g = st["grad"][j * Lf * 2:(j + 1) * Lf * 2].astype(np.float64)
+        h = st["gram"][j * Lf * 3:(j + 1) * Lf * 3].astype(np.float64)
+        cnt = np.bincount(lid, minlength=Lf)
+        sx = np.bincount(lid, weights=x, minlength=Lf)
+        sxx = np.bincount(lid, weights=x * x, minlength=Lf)
+        sig = np.sqrt(np.maximum(sxx / np.maximum(cnt, 1) - (sx / np.maximum(cnt, 1)) ** 2, 0))
+        used = cnt > 0
+        leaves_used += int(used.sum())
+        for l in np.nonzero(used & ~dirty)[0]:
+            compared += 1
+            gs = np.abs(g64).max()
+            assert np.all(np.abs(g[2 * l:2 * l + 2] - g64[2 * l:2 * l + 2]) <= 1e-4 * gs), (i, l)
+            assert np.allclose(h[3 * l:3 * l + 3], h64[3 * l:3 * l + 3], rtol=1e-4,
+                               atol=1e-6 * np.abs(h64).max()), (i, l)
+            c, d, mu = (float(leaf[l, q]) for q in range(3))
+            assert abs(mu - m["mu"][l]) <= 4 * eps + 1e-5 * abs(m["mu"][l]), (i, l)
+            assert abs(d - m["d"][l]) <= 2e-5, (i, l, d, m["d"][l])
+            if cnt[l] >= 2 and sig[l] > 2.0 ** -16:
+                tol = abs(m["c"][l]) * (1e-4 + 8 * eps / sig[l]) + 1e-6
+                assert abs(c - m["c"][l]) <= tol, (i, l, c, m["c"][l])
+        # empty leaves predict the samples below them
+        below = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+        for l in np.nonzero(~used & ~dirty)[0]:
+            assert leaf[l, 0] == 0.0 and leaf[l, 1] == np.float32(below[l] / (p * s)), (i, l)
+    assert compared >= 0.8 * leaves_used, (compared, leaves_used)

@@ -1,22 +1,38 @@
 """Parity at the full workload sizes, in the launch configurations the
 benchmark times.
 
-The headline sort (2^28 int32, p = 256, s = 64, DET) is compared with the
-oracle itself, element by element, together with its sample, splitters and
-count matrix; for RAN the sample positions are the oracle's. The other
-full-size workloads are too large for the single-thread oracle inside a test; there the checks are properties that fix the result
-exactly at any size: a stable sort's output is unique, and an output that is
-ordered, is a permutation of the input and (for key-value sorts) keeps equal
-keys in increasing original position is that output. The paper's DET
-bucket-size bound (Lemma balance) and the all-equal closed form are checked
-on the GPU's count matrices.
+Every full-size workload is compared with the oracle itself, element by
+element: the output (and payload), the sample and splitter tags and the count
+matrix, for both variants. The oracle runs with its per-processor steps on
+the host cores (oracle.sort(threads=...), byte-identical to the single-thread
+oracle). The invariants that fix a stable sort at any size (ordered, a
+permutation, equal keys in increasing original position) are checked on the
+GPU as well, together with the paper's DET bucket-size bound (Lemma balance)
+and the all-equal closed form.
 """
+import functools
 import numpy as np
 import pytest
 
 import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+
+def _threads():
+    """Host threads of the oracle (the CPU share of one GPU)."""
+    import oracle
+    return oracle.default_threads()
+
+
+@functools.lru_cache(maxsize=1)
+def _c3_input():
+    return W.zipf_int64_kv(1 << 28)
+
+
+@functools.lru_cache(maxsize=1)
+def _c4_input():
+    return W.lognormal_f32(1 << 28)
 
 
 @pytest.fixture(scope="module")
@@ -72,7 +88,7 @@ def test_headline_det_2e28_against_oracle(ora, dev):
     st = bsps.sort_(t, p, s, bsps.DET, stats=True)
     out = _to_host(t)
     del t
-    ref = ora.sort(keys, p, s, ora.DET)
+    ref = ora.sort(keys, p, s, ora.DET, threads=_threads())
     assert np.array_equal(out, ref["keys"])
     assert np.array_equal(st["sample_pos"], ref["sample_pos"])
     assert np.array_equal(st["splitter_pos"], ref["spl_pos"])
@@ -82,38 +98,41 @@ def test_headline_det_2e28_against_oracle(ora, dev):
 
 @pytest.mark.timeout(300)
 def test_headline_ran_2e28(ora, dev):
-    """The same input, RAN (seed 1): output equals the sorted input, and the
-    sample is exactly the oracle's keyed-permutation positions."""
-    import torch
+    """The same input, RAN (seed 1): output, sample tags (the oracle's keyed
+    permutation positions), splitter tags and count matrix equal the
+    oracle's."""
     import paper_1408_6729_amd as bsps
     n, p, s = 1 << 28, 256, 64
     keys = W.int32_keys(n, p, "uniform")
     t = _to_dev(keys, dev)
     st = bsps.sort_(t, p, s, bsps.RAN, seed=1, stats=True)
-    assert np.array_equal(_to_host(t), np.sort(keys))
-    ns = s * p - 1
-    pos = np.array([ora.feistel(1, n, j) for j in range(ns)], dtype=np.int64)
-    assert np.array_equal(np.sort(st["sample_pos"]), np.sort(pos))
-    assert np.array_equal(st["splitter_pos"], st["sample_pos"][s - 1:(p - 1) * s:s])
-    assert st["count_matrix"].sum() == n
+    out = _to_host(t)
+    del t
+    ref = ora.sort(keys, p, s, ora.RAN, 1, threads=_threads())
+    assert np.array_equal(out, ref["keys"])
+    assert np.array_equal(st["sample_pos"], ref["sample_pos"])
+    assert np.array_equal(st["splitter_pos"], ref["spl_pos"])
+    assert np.array_equal(st["count_matrix"], ref["C"])
 
 
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("dist", W.DISTRIBUTIONS)
-def test_c2_distributions_full(dev, dist):
+def test_c2_distributions_full(ora, dev, dist):
     """2^26 int32 keys, p = 128, s = 32, both variants, each of the seven
-    distributions: output equals the sorted input; DET buckets obey Lemma
-    balance; all-equal keys give the diagonal count matrix."""
-    import torch
+    distributions: output, splitter tags and count matrix equal the oracle's;
+    DET buckets obey Lemma balance; all-equal keys give the diagonal count
+    matrix."""
     import paper_1408_6729_amd as bsps
     n, p, s = 1 << 26, 128, 32
     keys = W.int32_keys(n, p, dist)
-    want = np.sort(keys)
     base = _to_dev(keys, dev)
     for variant in (bsps.DET, bsps.RAN):
         t = base.clone()
         st = bsps.sort_(t, p, s, variant, seed=1, stats=True)
-        assert np.array_equal(_to_host(t), want), (dist, variant)
+        ref = ora.sort(keys, p, s, variant, 1, threads=_threads())
+        assert np.array_equal(_to_host(t), ref["keys"]), (dist, variant)
+        assert np.array_equal(st["splitter_pos"], ref["spl_pos"]), (dist, variant)
+        assert np.array_equal(st["count_matrix"], ref["C"]), (dist, variant)
         C = st["count_matrix"]
         assert C.sum() == n
         if variant == bsps.DET:
@@ -124,18 +143,21 @@ def test_c2_distributions_full(dev, dist):
 
 
 @pytest.mark.timeout(300)
-def test_int64_kv_duplicates_2e28(dev):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_int64_kv_duplicates_2e28(ora, dev, variant):
     """2^28 int64 Zipf keys + 25% equal block, uint32 payload = original
-    index, p = 256, s = 64: ordered, keys[payload] = output keys, and payload
-    strictly increasing inside every run of equal keys (the paper's tie rule)."""
+    index, p = 256, s = 64, DET and RAN: keys, payloads, sample and splitter
+    tags and count matrix equal the oracle's; on the GPU also: ordered,
+    keys[payload] = output keys, and payload strictly increasing inside every
+    run of equal keys (the paper's tie rule)."""
     import torch
     import paper_1408_6729_amd as bsps
     n, p, s = 1 << 28, 256, 64
-    k, v = W.zipf_int64_kv(n)
+    k, v = _c3_input()
     base = _to_dev(k, dev)
     t = base.clone()
     vt = _to_dev(v.view(np.int32), dev)
-    bsps.sort_(t, p, s, bsps.DET, values=vt)
+    st = bsps.sort_(t, p, s, variant, seed=1, values=vt, stats=True)
     torch.cuda.synchronize()
     pay = vt.to(torch.int64) & 0xFFFFFFFF
     assert bool(torch.all(t[1:] >= t[:-1]))
@@ -143,33 +165,49 @@ def test_int64_kv_duplicates_2e28(dev):
     tie = t[1:] == t[:-1]
     assert bool(torch.all(pay[1:][tie] > pay[:-1][tie]))
     assert int(tie.sum()) > n // 4  # the duplicate stress is real
+    del tie, pay, base
+    out, outv = _to_host(t), _to_host(vt).view(np.uint32)
+    del t, vt
+    ref = ora.sort(k, p, s, variant, 1, v, threads=_threads())
+    assert np.array_equal(out, ref["keys"])
+    assert np.array_equal(outv, ref["values"])
+    assert np.array_equal(st["sample_pos"], ref["sample_pos"])
+    assert np.array_equal(st["splitter_pos"], ref["spl_pos"])
+    assert np.array_equal(st["count_matrix"], ref["C"])
 
 
 @pytest.mark.timeout(300)
-def test_learned_2e28_float32(dev):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_learned_2e28_float32(ora, dev, variant):
     """2^28 float32 lognormal-mixture keys with -0.0/+0.0, p = 1024, s = 64,
-    4096 leaves: the learned route's output and count matrix equal the
-    splitter route's and the fused route's; the output is the totalOrder sort
-    of the input; the model predicts most keys exactly."""
+    4096 leaves, DET and RAN: the learned route's output, splitter tags and
+    count matrix equal the oracle's; for DET the splitter and fused routes give
+    the same output and count matrix; the model predicts most keys exactly."""
     import torch
     import paper_1408_6729_amd as bsps
     n, p, s, L = 1 << 28, 1024, 64, 4096
-    keys = W.lognormal_f32(n)
+    keys = _c4_input()
     base = _to_dev(keys, dev)
+    routes = ((bsps.LEARNED, bsps.ROUTE_SCATTER),)
+    if variant == bsps.DET:
+        routes += ((bsps.SPLITTER, bsps.ROUTE_SCATTER), (bsps.SPLITTER, bsps.ROUTE_FUSED))
     outs, cms = [], []
-    for bucketing, route in ((bsps.LEARNED, bsps.ROUTE_SCATTER), (bsps.SPLITTER, bsps.ROUTE_SCATTER),
-                             (bsps.SPLITTER, bsps.ROUTE_FUSED)):
+    for bucketing, route in routes:
         t = base.clone()
-        st = bsps.sort_(t, p, s, bsps.DET, bucketing=bucketing, route=route, leaves=L, stats=True)
+        st = bsps.sort_(t, p, s, variant, seed=1, bucketing=bucketing, route=route, leaves=L, stats=True)
         if bucketing == bsps.LEARNED:
             learned = st
         outs.append(_to_host(t.view(torch.int32)))
         cms.append(st["count_matrix"])
         del t
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
-    assert np.array_equal(cms[0], cms[1]) and np.array_equal(cms[0], cms[2])
-    want = np.sort(_order_np(keys))
-    assert np.array_equal(_order_np(outs[0].view(np.float32)), want)
+    for o, c in zip(outs[1:], cms[1:]):
+        assert np.array_equal(outs[0], o) and np.array_equal(cms[0], c)
+    del base
+    ref = ora.sort(keys, p, s, variant, 1, threads=_threads())
+    assert np.array_equal(outs[0], ref["keys"].view(np.int32))
+    assert np.array_equal(learned["splitter_pos"], ref["spl_pos"])
+    assert np.array_equal(learned["sample_pos"], ref["sample_pos"])
+    assert np.array_equal(cms[0], ref["C"])
     assert learned["mispredict_rate"] < 0.25, learned["mispredict_rate"]
 
 
