@@ -6,24 +6,33 @@ processor with the paper's seeding (Section 6.3), p = 256 virtual processors,
 oversampling s = 64, the deterministic variant Sort_Det_BSP (Figure SortD),
 keys only. One step = one complete sort of one staged copy of the input
 (local block sort, sample, splitters, bucket boundaries, prefix sums,
-per-bucket merge), with the input already resident in HBM. The randomized
-variant (Figure SortRI) is timed on the same input.
+per-bucket merge), with the input already resident in HBM: before every step
+the pristine input is copied into the work buffer outside the timed region,
+and the step itself is timed with HIP events on the stream the sort runs on.
+The reported time is the median over the timed steps (min and max beside it).
+The randomized variant (Figure SortRI) is timed on the same input.
 
 Beside it (in "detail"), each timed the same way:
-  learned    2^28 float32 keys (mixture of three lognormals), p = 1024, s = 64:
-             per-key ranking by the learned CDF model against plain splitter
-             search, the scatter routing, identical outputs required
-  int64_kv   2^28 int64 keys, Zipf(1.2) over 2^16 values + 25% equal block,
-             uint32 payload, p = 256, s = 64
-  segmented  4096 int32 segments, log-uniform sizes in [2^8, 2^20], one
-             graph launch per step
+  learned      2^28 float32 keys (mixture of three lognormals), p = 1024,
+               s = 64: per-key ranking by the learned CDF model against plain
+               splitter search on the scatter route, and the fused route;
+               identical outputs required
+  int64_kv     2^28 int64 keys, Zipf(1.2) over 2^16 values + 25% equal block,
+               uint32 payload, p = 256, s = 64, DET and RAN
+  segmented    4096 int32 segments, log-uniform sizes in [2^8, 2^20], one
+               graph launch per step (the cached graph of one fixed buffer)
+  operating    the paper's own oversampling (Section 6.1) on the mid-size
+               workload: 2^26 int32 keys, p = 128, DET s = ceil(lg lg n) p and
+               RAN s = 2 ceil(lg n)^2, with the largest bucket over n/p
+Per-stage times come from one extra, separately run sort with the library's
+stage timer on (HIP events between the stages), never from the timed steps.
 
 Prints one JSON line: throughput in keys/s, the roofline of the dominant
-kernel (algorithmic bytes over its HIP-event-timed duration against the
-8 TB/s HBM peak, and against the rate the library's reference copy kernel
-attains on the same array), and the CPU oracle timed on a bounded sample.
+kernel (algorithmic bytes of one launch over its HIP-event-timed duration,
+against the 8 TB/s HBM peak and against the rate the library's reference copy
+kernel attains on the same array), and the CPU oracle timed on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c0,learned,int64_kv,segmented]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c0,learned,int64_kv,segmented,operating]
 """
 from __future__ import annotations
 
@@ -32,7 +41,9 @@ import ctypes as ct
 import glob
 import hashlib
 import json
+import math
 import os
+import subprocess
 import sys
 import time
 
@@ -41,8 +52,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 STAGES = ["tile_sort", "block_merge", "sample_splitters", "bucket_ranking", "prefix_routing",
-          "bucket_merge", "k_mwm_merge(block)", "k_mwm_merge(bucket)", "k_rank"]
-ALL = ("c0", "learned", "int64_kv", "segmented")
+          "bucket_merge", "k_mwm_merge(block)", "k_mwm_merge(bucket)", "k_rank", "k_lsd_pass"]
+# kernels that move every record once per launch (a permuting pass: 2 w bytes per key)
+PERMUTING = ("tile_sort", "k_lsd_pass", "k_mwm_merge(block)", "k_mwm_merge(bucket)")
+ALL = ("c0", "learned", "int64_kv", "segmented", "operating")
 
 
 def log(msg):
@@ -71,18 +84,39 @@ def stored_traffic(kernel: str, workload: str):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(log2n: int, p: int, s: int):
-    """The oracle (plain single-thread C) on a bounded sample of the workload."""
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return "unknown"
+
+
+def cpu_baseline(keys, p: int, s: int, log2_one: int):
+    """The oracle (plain C) on the host cores: its per-processor steps on all
+    the cores this process may use (at most 16, the CPU share of one GPU) for
+    the full headline input, and on one core for a bounded prefix sample."""
     import oracle
     import workloads as W
-    n = 1 << log2n
-    keys = W.int32_keys(n, p, "uniform")
+    threads = oracle.default_threads()
+    n = keys.size
     t0 = time.perf_counter()
-    oracle.sort(keys, p, s, oracle.DET, intermediates=False)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": f"2^{log2n} int32 uniform keys of the same distribution, p={p}, s={s}, DET, "
-                      f"one thread, {dt:.1f} s"}
+    oracle.sort(keys, p, s, oracle.DET, intermediates=False, threads=threads)
+    dt_all = time.perf_counter() - t0
+    n1 = 1 << log2_one
+    k1 = W.int32_keys(n1, p, "uniform")
+    t0 = time.perf_counter()
+    oracle.sort(k1, p, s, oracle.DET, intermediates=False)
+    dt_one = time.perf_counter() - t0
+    return {"value": n / dt_all, "unit": "keys/s", "cores": threads, "kind": "oracle",
+            "sample": f"the full headline input (2^{int(math.log2(n))} int32 keys, p={p}, s={s}, DET) with the "
+                      f"oracle's per-processor steps on {threads} host threads: {dt_all:.1f} s",
+            "one_core": {"value": n1 / dt_one, "unit": "keys/s", "cores": 1,
+                         "sample": f"2^{log2_one} int32 uniform keys, p={p}, s={s}, DET, one thread: {dt_one:.1f} s"},
+            "host_cpu": cpu_model(), "host_cpu_count": os.cpu_count()}
 
 
 def to_dev(torch, a):
@@ -93,70 +127,77 @@ def to_dev(torch, a):
     return pin.to("cuda:0")
 
 
-class Timer:
-    """The library's per-stage HIP-event timing (events on the stream the
-    kernels run on)."""
-
-    def __init__(self, bsps):
-        self.lib = bsps.lib
-
-    def start(self):
-        ms = (ct.c_double * len(STAGES))()
-        cnt = (ct.c_int64 * len(STAGES))()
-        self.lib.bsps_timing_read(ms, cnt, len(STAGES), 1)
-        self.lib.bsps_timing(1)
-
-    def stop(self, steps: int):
-        self.lib.bsps_timing(0)
-        ms = (ct.c_double * len(STAGES))()
-        cnt = (ct.c_int64 * len(STAGES))()
-        self.lib.bsps_timing_read(ms, cnt, len(STAGES), 1)
-        return {STAGES[i]: {"ms_per_launch": ms[i] / cnt[i], "launches_per_step": cnt[i] / steps}
-                for i in range(len(STAGES)) if cnt[i]}
+def stage_times(bsps, run, restage, torch):
+    """One extra run with the library's stage timer on (HIP events recorded
+    between the stages on the sort's stream): per-stage ms and launches."""
+    ms = (ct.c_double * len(STAGES))()
+    cnt = (ct.c_int64 * len(STAGES))()
+    restage()
+    torch.cuda.synchronize()
+    bsps.lib.bsps_timing_read(ms, cnt, len(STAGES), 1)
+    bsps.lib.bsps_timing(1)
+    run()
+    torch.cuda.synchronize()
+    bsps.lib.bsps_timing(0)
+    bsps.lib.bsps_timing_read(ms, cnt, len(STAGES), 1)
+    return {STAGES[i]: {"ms_per_launch": ms[i] / cnt[i], "launches_per_step": int(cnt[i])}
+            for i in range(len(STAGES)) if cnt[i]}
 
 
-def time_sort(bsps, torch, base, K, Wm, p, s, variant=0, bucketing=0, route=0, leaves=0, vbase=None,
-              timer=None):
-    """K timed sorts (after Wm untimed) of fresh device copies of `base`;
-    returns (ms per step, stage timings, last output keys, last output values)."""
-    dev = base.device
+def time_steps(torch, run, restage, K, Wm):
+    """Wm untimed steps, then K timed ones; before each step the input is
+    restaged (untimed), and the step is bracketed by synchronizations and
+    timed with HIP events on the current stream. Returns per-step ms."""
+    for _ in range(Wm):
+        restage()
+        run()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(K):
+        restage()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def summary(ts, n):
+    ts = sorted(ts)
+    med = ts[len(ts) // 2] if len(ts) % 2 else 0.5 * (ts[len(ts) // 2 - 1] + ts[len(ts) // 2])
+    return {"ms": med, "ms_min": ts[0], "ms_max": ts[-1], "steps": len(ts), "keys_per_s": n / (med / 1e3)}
+
+
+def bench_sort(bsps, torch, base, K, Wm, p, s, variant=0, bucketing=0, route=0, leaves=0, vbase=None):
+    """K timed sorts of the staged input (median); then one stage-timed run."""
     n = base.numel()
-    copies = torch.empty((K + Wm, n), dtype=base.dtype, device=dev)
-    vcopies = None if vbase is None else torch.empty((K + Wm, n), dtype=vbase.dtype, device=dev)
-    for i in range(K + Wm):
-        copies[i].copy_(base)
-        if vcopies is not None:
-            vcopies[i].copy_(vbase)
+    work = torch.empty_like(base)
+    vwork = None if vbase is None else torch.empty_like(vbase)
     dt = {torch.int32: bsps.I32, torch.int64: bsps.I64, torch.float32: bsps.F32}[base.dtype]
     prm = bsps.make_params(p, s, variant, 1, bucketing, route, leaves)
-    ws = torch.empty(bsps.workspace_bytes(n, dt, vbase is not None, prm), dtype=torch.uint8, device=dev)
+    ws = torch.empty(bsps.workspace_bytes(n, dt, vbase is not None, prm), dtype=torch.uint8, device=base.device)
 
-    def run(i):
-        bsps.sort_(copies[i], p, s, variant, values=None if vcopies is None else vcopies[i], bucketing=bucketing,
-                   route=route, leaves=leaves, workspace=ws)
+    def restage():
+        work.copy_(base)
+        if vwork is not None:
+            vwork.copy_(vbase)
 
-    for i in range(Wm):
-        run(i)
-    torch.cuda.synchronize()
-    if timer:
-        timer.start()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(K):
-        run(Wm + i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    stages = timer.stop(K) if timer else {}
-    out = copies[Wm + K - 1].clone()
-    vout = None if vcopies is None else vcopies[Wm + K - 1].clone()
-    del copies, vcopies, ws
-    torch.cuda.empty_cache()
-    return (t1 - t0) * 1e3 / K, stages, out, vout
+    def run():
+        bsps.sort_(work, p, s, variant, values=vwork, bucketing=bucketing, route=route, leaves=leaves, workspace=ws)
+
+    ts = time_steps(torch, run, restage, K, Wm)
+    res = summary(ts, n)
+    res["stages"] = stage_times(bsps, run, restage, torch)
+    del ws
+    return res, work, vwork
 
 
 def order_u32(torch, t):
-    """Order-preserving unsigned image of int32 / float32 keys (int64 for
-    comparison on the device), used only to check that outputs are sorted."""
+    """Order-preserving image of int32 / float32 keys as int64 (device), used
+    only to check that outputs are sorted."""
     if t.dtype == torch.float32:
         b = t.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
         neg = b >= (1 << 31)
@@ -169,18 +210,19 @@ def is_sorted(torch, t):
     return bool(torch.all(u[1:] >= u[:-1]).item())
 
 
-def bench_c0(bsps, torch, W, args, timer):
-    n, p, s = 1 << args.log2n, 256, 64
-    log(f"c0: generating 2^{args.log2n} int32 keys")
-    base = to_dev(torch, W.int32_keys(n, p, "uniform"))
+def bench_c0(bsps, torch, W, args, keys):
+    n, p, s = keys.size, 256, 64
+    base = to_dev(torch, keys)
     res = {}
     for variant, name in ((bsps.DET, "det"), (bsps.RAN, "ran")):
-        ms, stages, out, _ = time_sort(bsps, torch, base, args.steps, args.warmup, p, s, variant, timer=timer)
-        ok = is_sorted(torch, out)
-        res[name] = {"ms": ms, "keys_per_s": n / (ms / 1e3), "sorted": ok, "stages": stages}
-        log(f"c0 {name}: {ms:.3f} ms/step, {n / ms / 1e6:.2f} Gkeys/s, sorted={ok}")
+        r, out, _ = bench_sort(bsps, torch, base, args.steps, args.warmup, p, s, variant)
+        r["sorted"] = is_sorted(torch, out)
+        res[name] = r
+        del out
+        log(f"c0 {name}: median {r['ms']:.3f} ms (min {r['ms_min']:.3f}, max {r['ms_max']:.3f}), "
+            f"{r['keys_per_s'] / 1e9:.2f} Gkeys/s, sorted={r['sorted']}")
     # attainable bandwidth: the library's reference copy kernel on the same
-    # 2^28-key array, HIP events on the stream it runs on
+    # array, HIP events on the stream it runs on
     dst = torch.empty_like(base)
     for _ in range(3):
         bsps.stream_copy(base, dst)
@@ -196,72 +238,93 @@ def bench_c0(bsps, torch, W, args, timer):
     ok = bool(torch.equal(dst, base))
     res["stream_copy"] = {"ms": cms, "gbs": cbytes / (cms / 1e3) / 1e9, "bytes_moved": cbytes, "exact": ok}
     log(f"c0 stream copy: {cms:.3f} ms, {cbytes / cms / 1e6:.0f} GB/s, exact={ok}")
-    del dst
+    del dst, base
+    torch.cuda.empty_cache()
     return n, p, s, res
 
 
-def bench_learned(bsps, torch, W, args, timer):
+def bench_learned(bsps, torch, W, args):
     n, p, s, L = 1 << args.log2n, 1024, 64, 4096
     log(f"learned: generating 2^{args.log2n} float32 lognormal-mixture keys")
     base = to_dev(torch, W.lognormal_f32(n))
-    K, Wm = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
+    K, Wm = max(20, args.steps), max(2, args.warmup)
     out = {"workload": f"2^{args.log2n} float32, mixture of 3 lognormals with 1024 -0.0 and 1024 +0.0, "
-                       f"p={p}, s={s}, Sort_Det_BSP, leaves={L}", "steps": K}
-    ref = None
-    for name, bucketing, route in (("fused", bsps.SPLITTER, bsps.ROUTE_FUSED),
-                                   ("scatter_splitter", bsps.SPLITTER, bsps.ROUTE_SCATTER),
-                                   ("scatter_learned", bsps.LEARNED, bsps.ROUTE_SCATTER)):
-        ms, stages, o, _ = time_sort(bsps, torch, base, K, Wm, p, s, bsps.DET, bucketing, route, L, timer=timer)
-        same = True if ref is None else bool(torch.equal(o.view(torch.int32), ref.view(torch.int32)))
-        if ref is None:
-            ref = o
-        e = {"ms": ms, "keys_per_s": n / (ms / 1e3), "sorted": is_sorted(torch, o), "identical_output": same,
-             "stages": stages}
-        if "k_rank" in stages:
-            e["rank_kernel_keys_per_s"] = n / (stages["k_rank"]["ms_per_launch"] / 1e3)
-        out[name] = e
-        log(f"learned/{name}: {ms:.3f} ms, rank {e.get('rank_kernel_keys_per_s', 0) / 1e9:.1f} Gkeys/s, "
-            f"identical={same}")
-    # misprediction statistics of one diagnostic run (outside the timed region)
-    t = base.clone()
-    st = bsps.sort_(t, p, s, bsps.DET, bucketing=bsps.LEARNED, route=bsps.ROUTE_SCATTER, leaves=L, stats=True)
-    out["mispredict_rate"] = st["mispredict_rate"]
-    out["mean_fix_dist"] = st["mean_fix_dist"]
-    out["max_bucket_ratio"] = st["max_bucket_ratio"]
-    sl, ss = out["scatter_learned"], out["scatter_splitter"]
-    out["learned_speedup_rank_kernel"] = sl.get("rank_kernel_keys_per_s", 0) / max(ss.get("rank_kernel_keys_per_s", 1), 1)
-    out["learned_speedup_end_to_end"] = sl["keys_per_s"] / ss["keys_per_s"]
+                       f"p={p}, s={s}, leaves={L}"}
+    for variant, vname in ((bsps.DET, "det"), (bsps.RAN, "ran")):
+        ref = None
+        e_all = {}
+        for name, bucketing, route in (("fused", bsps.SPLITTER, bsps.ROUTE_FUSED),
+                                       ("scatter_splitter", bsps.SPLITTER, bsps.ROUTE_SCATTER),
+                                       ("scatter_learned", bsps.LEARNED, bsps.ROUTE_SCATTER)):
+            if variant == bsps.RAN and name == "scatter_splitter":
+                continue
+            r, o, _ = bench_sort(bsps, torch, base, K, Wm, p, s, variant, bucketing, route, L)
+            same = True if ref is None else bool(torch.equal(o.view(torch.int32), ref.view(torch.int32)))
+            if ref is None:
+                ref = o.clone()
+            r["sorted"] = is_sorted(torch, o)
+            r["identical_output"] = same
+            if "k_rank" in r["stages"]:
+                r["rank_kernel_keys_per_s"] = n / (r["stages"]["k_rank"]["ms_per_launch"] / 1e3)
+            e_all[name] = r
+            del o
+            log(f"learned/{vname}/{name}: median {r['ms']:.3f} ms [{r['ms_min']:.3f}, {r['ms_max']:.3f}], "
+                f"rank {r.get('rank_kernel_keys_per_s', 0) / 1e9:.1f} Gkeys/s, identical={same}")
+        # misprediction statistics of one diagnostic run (outside the timed region)
+        t = base.clone()
+        st = bsps.sort_(t, p, s, variant, bucketing=bsps.LEARNED, route=bsps.ROUTE_SCATTER, leaves=L, stats=True)
+        e_all["mispredict_rate"] = st["mispredict_rate"]
+        e_all["mean_fix_dist"] = st["mean_fix_dist"]
+        e_all["max_bucket_ratio"] = st["max_bucket_ratio"]
+        del t, ref
+        if "scatter_splitter" in e_all:
+            sl, ss = e_all["scatter_learned"], e_all["scatter_splitter"]
+            e_all["learned_speedup_rank_kernel"] = (sl.get("rank_kernel_keys_per_s", 0) /
+                                                    max(ss.get("rank_kernel_keys_per_s", 1), 1))
+            e_all["learned_speedup_end_to_end"] = ss["ms"] / sl["ms"]
+            # the spread of the timed steps: learned wins beyond it when its
+            # slowest step beats the splitter route's fastest
+            e_all["learned_faster_than_spread"] = sl["ms_max"] < ss["ms_min"]
+        out[vname] = e_all
+    torch.cuda.empty_cache()
     return out
 
 
-def bench_int64_kv(bsps, torch, W, args, timer):
+def bench_int64_kv(bsps, torch, W, args):
     n, p, s = 1 << args.log2n, 256, 64
     log(f"int64_kv: generating 2^{args.log2n} Zipf int64 keys with payload")
     k, v = W.zipf_int64_kv(n)
     base = to_dev(torch, k)
     vbase = to_dev(torch, v.view("int32"))
-    K, Wm = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
-    ms, stages, o, vo = time_sort(bsps, torch, base, K, Wm, p, s, bsps.DET, vbase=vbase, timer=timer)
-    ok = is_sorted(torch, o) and bool(torch.equal(base[vo.to(torch.int64) & 0xFFFFFFFF], o))
-    log(f"int64_kv: {ms:.3f} ms, {n / ms / 1e6:.2f} Gkeys/s, ok={ok}")
-    return {"workload": f"2^{args.log2n} int64 Zipf(1.2) over 2^16 values + 25% equal block, uint32 payload, "
-                        f"p={p}, s={s}, Sort_Det_BSP", "ms": ms, "keys_per_s": n / (ms / 1e3),
-            "sorted_and_payload_consistent": ok, "steps": K, "stages": stages,
-            "floor_fraction_6w": 6 * 12 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    K, Wm = max(5, min(args.steps, 10)), max(1, min(args.warmup, 2))
+    out = {"workload": f"2^{args.log2n} int64 Zipf(1.2) over 2^16 values + 25% equal block, uint32 payload, "
+                       f"p={p}, s={s}"}
+    for variant, vname in ((bsps.DET, "det"), (bsps.RAN, "ran")):
+        r, o, vo = bench_sort(bsps, torch, base, K, Wm, p, s, variant, vbase=vbase)
+        ok = is_sorted(torch, o) and bool(torch.equal(base[vo.to(torch.int64) & 0xFFFFFFFF], o))
+        r["sorted_and_payload_consistent"] = ok
+        r["floor_fraction_6w"] = 6 * 12 * n / (r["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
+        out[vname] = r
+        del o, vo
+        log(f"int64_kv/{vname}: median {r['ms']:.3f} ms, {n / r['ms'] / 1e6:.2f} Gkeys/s, ok={ok}")
+    del base, vbase
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_segmented(bsps, torch, W, args):
-    """The batch with the package's size-class table, learned bucketing on the
-    segments above 2^16 keys (as the table says) and, for comparison, with
-    splitter search everywhere."""
+    """The batch with the package's size-class table, timed as repeated sorts
+    of one fixed buffer (its graph is captured once and then replayed from the
+    cache), learned bucketing on the large segments as the table says and,
+    for comparison, with splitter search everywhere."""
     import numpy as np
     log("segmented: generating 4096 segments")
     sizes = W.segment_sizes(4096, 8, 20)
     keys, offs = W.segmented_int32(sizes)
     n = keys.size
     base = to_dev(torch, keys)
-    K, Wm = max(1, min(args.steps, 5)), max(1, min(args.warmup, 2))
-    copies = torch.empty((K + Wm, n), dtype=torch.int32, device="cuda:0")
+    work = torch.empty_like(base)
+    K, Wm = max(10, args.steps), max(2, args.warmup)
     table = json.loads(bsps.default_tuning() or json.dumps(
         {"classes": [{"max_log2": 14, "block": 16384, "s": 1}, {"max_log2": 17, "block": 16384, "s": 32},
                      {"max_log2": 20, "block": 16384, "s": 16}, {"max_log2": 40, "block": 16384, "s": 8}]}))
@@ -269,39 +332,73 @@ def bench_segmented(bsps, torch, W, args):
     cut = torch.zeros(n, dtype=torch.bool, device="cuda:0")
     cut[inner[(inner > 0) & (inner < n)]] = True
     res = {"workload": f"4096 int32 segments, log-uniform sizes in [2^8, 2^20], {n} keys; even segments "
-                       "uniform, odd 2^8-distinct", "steps": K, "tuning": table}
-    for name, lg in (("learned", 16), ("splitter", 40)):
+                       "uniform, odd 2^8-distinct", "tuning": table}
+    default_lg = int(table.get("learned_above_log2", 16))
+    for name, lg in (("default_table", default_lg), ("learned", 16), ("splitter", 40)):
         tj = json.dumps(dict(table, learned_above_log2=lg))
-        for i in range(K + Wm):
-            copies[i].copy_(base)
         ws = torch.empty(bsps.segmented_workspace_bytes(offs, bsps.I32, False, tj), dtype=torch.uint8,
                          device="cuda:0")
-        for i in range(Wm):
-            bsps.sort_segmented_(copies[i], offs, tuning=tj, workspace=ws)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(K):
-            bsps.sort_segmented_(copies[Wm + i], offs, tuning=tj, workspace=ws)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / K
-        out = copies[Wm + K - 1]
-        ok = not bool(((out[1:] < out[:-1]) & ~cut[1:]).any().item())
-        st = bsps.sort_segmented_(copies[0].copy_(base), offs, tuning=tj, workspace=ws, stats=True)
-        e = {"ms": ms, "keys_per_s": n / (ms / 1e3), "segments_sorted": ok, "graph": st["graph"],
-             "blocks": st["blocks"], "merged_segments": st["merged_segments"],
-             "learned_segments": st["learned_segments"], "mispredict_rate": st["mispredict_rate"],
-             "floor_fraction_6w": 6 * 4 * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+        def restage():
+            work.copy_(base)
+
+        def run():
+            bsps.sort_segmented_(work, offs, tuning=tj, workspace=ws)
+
+        ts = time_steps(torch, run, restage, K, Wm)
+        e = summary(ts, n)
+        ok = not bool(((work[1:] < work[:-1]) & ~cut[1:]).any().item())
+        restage()
+        st = bsps.sort_segmented_(work, offs, tuning=tj, workspace=ws, stats=True)
+        e.update({"segments_sorted": ok, "graph_replayed_from_cache": st["graph_cached"], "blocks": st["blocks"],
+                  "merged_segments": st["merged_segments"], "learned_segments": st["learned_segments"],
+                  "learned_above_log2": lg, "mispredict_rate": st["mispredict_rate"],
+                  "floor_fraction_6w": 6 * 4 * n / (e["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS})
         res[name] = e
-        log(f"segmented/{name}: {ms:.3f} ms, {n / ms / 1e6:.2f} Gkeys/s, sorted={ok}, "
-            f"learned segments {e['learned_segments']}, mispredict {e['mispredict_rate']:.4f}")
+        log(f"segmented/{name}: median {e['ms']:.3f} ms [{e['ms_min']:.3f}, {e['ms_max']:.3f}], "
+            f"{n / e['ms'] / 1e6:.2f} Gkeys/s, sorted={ok}, cached graph={st['graph_cached']}")
         del ws
+    del base, work, cut
+    torch.cuda.empty_cache()
     return res
+
+
+def bench_operating(bsps, torch, W, args):
+    """Section 6.1's oversampling on the mid-size uniform workload: DET
+    s = ceil(lg lg n) p, RAN s = 2 ceil(lg n)^2; the largest bucket over n/p
+    against the paper's observed imbalance (below 15%, Section 6.4)."""
+    n, p = 1 << 26, 128
+    lg = math.log2(n)
+    s_det = math.ceil(math.log2(lg)) * p
+    s_ran = 2 * math.ceil(lg) ** 2
+    keys = W.int32_keys(n, p, "uniform")
+    base = to_dev(torch, keys)
+    out = {"workload": f"2^26 int32 uniform, p={p}", "s_det": s_det, "s_ran": s_ran}
+    for variant, vname, s in ((bsps.DET, "det", s_det), (bsps.RAN, "ran", s_ran)):
+        r, o, _ = bench_sort(bsps, torch, base, max(5, min(args.steps, 10)), 1, p, s, variant)
+        r["sorted"] = is_sorted(torch, o)
+        t = base.clone()
+        st = bsps.sort_(t, p, s, variant, seed=1, stats=True)
+        r["max_bucket_ratio"] = st["max_bucket_ratio"]
+        out[vname] = r
+        del o, t
+        log(f"operating/{vname} s={s}: median {r['ms']:.3f} ms, largest bucket {st['max_bucket_ratio']:.3f} n/p")
+    del base
+    torch.cuda.empty_cache()
+    return out
+
+
+def dominant(stages):
+    """The permuting kernel with the largest total time per step."""
+    cand = {k: v for k, v in stages.items() if k in PERMUTING and not (
+        k == "tile_sort" and "k_lsd_pass" in stages)}
+    return max(cand, key=lambda k: cand[k]["ms_per_launch"] * cand[k]["launches_per_step"])
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--cpu-log2n", type=int, default=25)
@@ -322,34 +419,39 @@ def main():
     import paper_1408_6729_amd as bsps
     import workloads as W
 
-    timer = Timer(bsps)
-    n, p, s, c0 = bench_c0(bsps, torch, W, args, timer)
+    log(f"c0: generating 2^{args.log2n} int32 keys")
+    keys = W.int32_keys(1 << args.log2n, 256, "uniform")
+    n, p, s, c0 = bench_c0(bsps, torch, W, args, keys)
     det = c0["det"]
     detail = {"det": det, "ran": c0["ran"], "stream_copy": c0["stream_copy"]}
     if "learned" in only:
-        detail["learned_vs_splitter"] = bench_learned(bsps, torch, W, args, timer)
+        detail["learned_vs_splitter"] = bench_learned(bsps, torch, W, args)
     if "int64_kv" in only:
-        detail["int64_kv"] = bench_int64_kv(bsps, torch, W, args, timer)
+        detail["int64_kv"] = bench_int64_kv(bsps, torch, W, args)
     if "segmented" in only:
         detail["segmented"] = bench_segmented(bsps, torch, W, args)
+    if "operating" in only:
+        detail["paper_operating_point"] = bench_operating(bsps, torch, W, args)
 
-    # dominant kernel of the timed DET steps: a permuting pass reads and writes
+    # dominant kernel of the headline sort: a permuting pass reads and writes
     # every key once, 2 * 4 bytes per int32 key
-    cand = {k: v for k, v in det["stages"].items() if k in ("tile_sort", "k_mwm_merge(block)", "k_mwm_merge(bucket)")}
-    dom = max(cand, key=lambda k: cand[k]["ms_per_launch"] * cand[k]["launches_per_step"])
+    dom = dominant(det["stages"])
     alg_bytes = 2 * 4 * n
-    achieved = alg_bytes / (cand[dom]["ms_per_launch"] / 1e3) / 1e9
+    achieved = alg_bytes / (det["stages"][dom]["ms_per_launch"] / 1e3) / 1e9
     workload = "C0"
+    passes = sum(det["stages"][k]["launches_per_step"] for k in det["stages"] if k in PERMUTING and not (
+        k == "tile_sort" and "k_lsd_pass" in det["stages"]))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom, workload), "kernel": dom,
                 "alg_bytes_per_launch": alg_bytes, "attainable_copy_gbs": c0["stream_copy"]["gbs"],
-                "frac_of_attainable": achieved / c0["stream_copy"]["gbs"]}
-    detail["floor_fraction_6w"] = (6 * 4 * n) / (det["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
-    detail["floor_note"] = "6 * 4 bytes per key (three permuting passes) / time / 8 TB/s"
+                "frac_of_attainable": achieved / c0["stream_copy"]["gbs"],
+                "pipeline": {"permuting_passes": passes,
+                             "frac": passes * alg_bytes / (det["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+                             "floor_frac_6w": 6 * 4 * n / (det["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS}}
     cpu = None
     if not args.no_cpu:
-        log(f"timing the CPU oracle on 2^{args.cpu_log2n} keys")
-        cpu = cpu_baseline(args.cpu_log2n, p, s)
+        log(f"timing the CPU oracle on the headline input and on 2^{args.cpu_log2n} keys")
+        cpu = cpu_baseline(keys, p, s, args.cpu_log2n)
     line = {
         "metric": "keys/s and % HBM roofline, 2^28 int32; learned vs splitter bucketing",
         "value": det["keys_per_s"], "unit": "keys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

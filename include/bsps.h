@@ -70,6 +70,16 @@ typedef enum {
     BSPS_ROUTE_SCATTER = 1
 } bsps_route;
 
+/* How every virtual processor sorts its block (Figure SortD step 3; any stable
+ * sequential sort may be used). Both give the same block-sorted array. */
+typedef enum {
+    BSPS_LOCAL_AUTO = 0,   /* the faster one on MI355X: tiles + merge */
+    BSPS_LOCAL_MERGE = 1,  /* stable LDS sort of every tile, then a sample-guided multiway merge of
+                              the block's tiles, chunk by chunk */
+    BSPS_LOCAL_LSD = 2     /* stable LSD radix sort of every block through HBM, 8-bit digits, one
+                              pass per digit position at which the block's keys differ */
+} bsps_local_sort;
+
 typedef struct bsps_params {
     int32_t p;          /* virtual processors = blocks = buckets; 1 <= p <= max(n, 1) */
     int32_t s;          /* oversampling: sample records per bucket, i.e. the splitter
@@ -83,7 +93,8 @@ typedef struct bsps_params {
     int32_t chunk_cap;  /* 0 = default. Largest merge chunk sorted in LDS; a smaller
                            value routes more chunks through the global-memory path
                            (used to test that path). */
-    int32_t reserved[7];/* must be zero */
+    int32_t local_sort; /* bsps_local_sort: how each block is sorted (step 3) */
+    int32_t reserved[6];/* must be zero */
 } bsps_params;
 
 /*
@@ -109,7 +120,16 @@ typedef struct bsps_stats {
     int64_t oversize_chunks;   /* merge chunks sorted by the global-memory path */
     int64_t reserved_i[4];     /* bsps_sort: [0] oversize chunks of the block merge, [1] of the
                                   bucket merge, [2] keys in the largest one. bsps_sort_segmented:
-                                  [0] blocks, [1] merged segments, [2] 1 if the graph was used */
+                                  [0] blocks, [1] merged segments, [2] 1 if the graph was captured
+                                  and launched by this call, 2 if a cached graph was launched,
+                                  [3] segments with learned bucketing (NL) */
+    /* bsps_sort_segmented only: the training state of the learned models of its NL
+     * large segments, in segment order, for checking the batched training kernels.
+     * Filled when non-NULL and seg_capacity >= NL (else left untouched). */
+    void* seg_models;          /* NL models of bsps_model_bytes(64) bytes each (layout of bsps_fit_model) */
+    float* seg_grad;           /* NL * 64 * 2: leaf-stage gradient (dLoss/dc, dLoss/dd) at c = d = 0 */
+    float* seg_gram;           /* NL * 64 * 3: leaf-stage Gram sums, as bsps_model_grad's out_gram */
+    int64_t seg_capacity;      /* models the three buffers hold */
 } bsps_stats;
 
 /* Bytes of device workspace a sort of n keys needs (values: 0 or 1). Returns
@@ -200,9 +220,11 @@ size_t bsps_rank_workspace_bytes(int64_t n, int32_t p);
  * of L linear leaf models of the cumulative distribution, trained on the
  * sorted sample by the library's forward, backward (gradient and Gram sums)
  * and Newton-update kernels. Layout of the device model buffer
- * (bsps_model_bytes(L) bytes, float32 unless noted):
- *   [0] lo, [1] hi as float64 (order-key range of the sample, 16 bytes)
- *   then root a, b, mu_r, inv_range (4 floats), then L triples (c, d, mu).
+ * (bsps_model_bytes(L) = 48 + 12 L bytes, float32 unless noted):
+ *   bytes  0..15  lo, hi as float64 (order-key range of the sample)
+ *   bytes 16..31  root a, b, mu_r and inv_range = 1 / (hi - lo) (4 floats)
+ *   bytes 32..47  L, p, s and a zero pad (4 int32)
+ *   bytes 48..    L leaf triples (c, d, mu), 12 bytes each.
  * A leaf predicts c * (x - mu) + d for x = (u - lo) * inv_range.
  *  smp_keys  device, N sorted keys of dtype (the sorted sample)
  *  N, p, s   sample size and sort parameters (targets y_t = (t + 0.5) / (p s))
@@ -235,6 +257,28 @@ bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int3
  * misaligned pointers or sizes (checked on the host before any HIP call);
  * EUNSUPPORTED above 2^31 workgroups (32 TiB). */
 bsps_status bsps_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
+/*
+ * Host dry runs of the sort and of the segmented sort: the call plans the work
+ * exactly as bsps_sort[_kv] / bsps_sort_segmented would for these sizes and
+ * parameters, with fake buffer addresses, and instead of launching each kernel
+ * it checks the launch: every pointer argument, and every table pointer inside
+ * the argument structs, must be null or lie inside the keys, payload or
+ * workspace buffer together with the whole extent the kernel indexes
+ * (e.g. G*R run entries of a merge, p*256 digit starts per position of the LSD
+ * passes), and grids must be non-empty. The segmented planner's host tables
+ * are checked for consistency (blocks inside their segments, groups naming a
+ * merged segment's bucket, prefix tables matching the sizes). No HIP call is
+ * made; this runs without a GPU.
+ *  report  HOST, report_len bytes (may be NULL): one line per finding, or
+ *          "ok: N launches checked"
+ * Returns the number of findings (0 = clean) or -status for arguments the real
+ * call would reject (as bsps_sort / bsps_sort_segmented).
+ */
+int64_t bsps_check_sort(int64_t n, int32_t dtype, int32_t with_values, const bsps_params* prm, char* report,
+                        size_t report_len);
+int64_t bsps_check_segmented(const int64_t* h_offsets, int32_t nseg, int32_t dtype, int32_t with_values,
+                             const char* tuning_json, char* report, size_t report_len);
 
 /* Human-readable name of a status code (static storage). */
 const char* bsps_status_string(int32_t status);

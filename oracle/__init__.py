@@ -64,6 +64,7 @@ def lib():
                                i64p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.ora_sort_mt.argtypes = L.ora_sort.argtypes + [ct.c_int]
+        L.ora_sort_untagged.argtypes = L.ora_sort.argtypes
         L.ora_rank.argtypes = [u64p, ct.c_int64, u64p, i64p, ct.c_int, i64p]
         L.ora_rmi_grad.restype = ct.c_double
         L.ora_rmi_grad.argtypes = [f64p, f64p, i32p, ct.c_int64, ct.c_int, f64p, f64p, f64p, f64p, f64p]
@@ -129,9 +130,11 @@ def default_threads() -> int:
 
 
 def sort(keys: np.ndarray, p: int, s: int, variant: int = DET, seed: int = 1,
-         values: np.ndarray | None = None, intermediates: bool = True, threads: int = 1) -> dict:
+         values: np.ndarray | None = None, intermediates: bool = True, threads: int = 1,
+         untagged: bool = False) -> dict:
     """Run the simulated BSP sort (threads > 1: the same per-processor steps
-    spread over that many host threads, byte-identical result). Returns a dict with
+    spread over that many host threads, byte-identical result; untagged: the
+    duplicate handling switched off, splitters compared by key alone). Returns a dict with
     keys, values (if given), perm, and when `intermediates`:
     B_keys/B_perm (block-sorted), sample_key/sample_pos (sorted sample, order keys
     and positions in the block-sorted array), spl_key/spl_pos (p-1 splitters),
@@ -156,7 +159,9 @@ def sort(keys: np.ndarray, p: int, s: int, variant: int = DET, seed: int = 1,
         Z = np.empty(max(n, 1), dtype=np.int64)
         args = [B.ctypes.data, sk.ctypes.data, sp.ctypes.data, pk.ctypes.data, pp.ctypes.data,
                 C.ctypes.data, Z.ctypes.data]
-    if threads > 1:
+    if untagged:
+        rc = lib().ora_sort_untagged(ok, n, p, s, variant, seed & 0xFFFFFFFFFFFFFFFF, perm, *args)
+    elif threads > 1:
         rc = lib().ora_sort_mt(ok, n, p, s, variant, seed & 0xFFFFFFFFFFFFFFFF, perm, *args, int(threads))
     else:
         rc = lib().ora_sort(ok, n, p, s, variant, seed & 0xFFFFFFFFFFFFFFFF, perm, *args)

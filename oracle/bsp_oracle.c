@@ -348,7 +348,7 @@ static void step_partition(ora_run_t* R, int k, void* scratch) { (void)scratch; 
 int ora_sort_driver(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t seed,
                     int64_t* perm, int64_t* B_idx_out, uint64_t* smp_key, int64_t* smp_pos,
                     uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out,
-                    ora_each_fn each, void* ctx) {
+                    int untagged, ora_each_fn each, void* ctx) {
     int rc = ora_validate(n, p, s, variant);
     if (rc) return rc;
     if (n <= 1) {
@@ -404,6 +404,12 @@ int ora_sort_driver(const uint64_t* ok, int64_t n, int p, int s, int variant, ui
         if (spl_key) spl_key[i - 1] = S[i - 1].key;
         if (spl_pos) spl_pos[i - 1] = S[i - 1].pos;
     }
+    /* Duplicate handling switched off (the ablation of Section 6.4): the
+     * splitters lose their tags, so a key equal to a splitter is never above
+     * it: every splitter compares as (key, +infinity) and buckets are decided
+     * by the key alone. */
+    if (untagged)
+        for (int i = 1; i < p; i++) S[i - 1].pos = INT64_MAX;
 
     /* O6: partition each processor's sorted keys by the splitters and count. */
     rc = each(&R, p, step_partition, 64, ctx);
@@ -456,7 +462,15 @@ int ora_sort(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t 
              int64_t* perm, int64_t* B_idx_out, uint64_t* smp_key, int64_t* smp_pos,
              uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out) {
     return ora_sort_driver(ok, n, p, s, variant, seed, perm, B_idx_out, smp_key, smp_pos, spl_key, spl_pos,
-                           C_out, Z_idx_out, each_sequential, NULL);
+                           C_out, Z_idx_out, 0, each_sequential, NULL);
+}
+
+/* ora_sort with the duplicate handling switched off (untagged splitters). */
+int ora_sort_untagged(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t seed,
+                      int64_t* perm, int64_t* B_idx_out, uint64_t* smp_key, int64_t* smp_pos,
+                      uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out) {
+    return ora_sort_driver(ok, n, p, s, variant, seed, perm, B_idx_out, smp_key, smp_pos, spl_key, spl_pos,
+                           C_out, Z_idx_out, 1, each_sequential, NULL);
 }
 
 /* Bucket of each record (key, g) of a block-sorted array against given

@@ -26,7 +26,7 @@ typedef int (*ora_each_fn)(struct ora_run* R, int count, ora_step_fn step, size_
 int ora_sort_driver(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64_t seed,
                     int64_t* perm, int64_t* B_idx_out, uint64_t* smp_key, int64_t* smp_pos,
                     uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out,
-                    ora_each_fn each, void* ctx);
+                    int untagged, ora_each_fn each, void* ctx);
 
 typedef struct {
     struct ora_run* R;
@@ -82,5 +82,5 @@ int ora_sort_mt(const uint64_t* ok, int64_t n, int p, int s, int variant, uint64
                 int64_t* perm, int64_t* B_idx_out, uint64_t* smp_key, int64_t* smp_pos,
                 uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out, int threads) {
     return ora_sort_driver(ok, n, p, s, variant, seed, perm, B_idx_out, smp_key, smp_pos, spl_key, spl_pos,
-                           C_out, Z_idx_out, each_threads, &threads);
+                           C_out, Z_idx_out, 0, each_threads, &threads);
 }

@@ -25,6 +25,7 @@ DET, RAN = 0, 1
 I32, I64, F32 = 0, 1, 2
 SPLITTER, LEARNED = 0, 1
 ROUTE_FUSED, ROUTE_SCATTER = 0, 1
+LOCAL_AUTO, LOCAL_MERGE, LOCAL_LSD = 0, 1, 2
 
 
 class BspsError(RuntimeError):
@@ -36,7 +37,7 @@ class BspsError(RuntimeError):
 class Params(ct.Structure):
     _fields_ = [("p", ct.c_int32), ("s", ct.c_int32), ("variant", ct.c_int32), ("bucketing", ct.c_int32),
                 ("route", ct.c_int32), ("leaves", ct.c_int32), ("seed", ct.c_uint64),
-                ("chunk_cap", ct.c_int32), ("reserved", ct.c_int32 * 7)]
+                ("chunk_cap", ct.c_int32), ("local_sort", ct.c_int32), ("reserved", ct.c_int32 * 6)]
 
 
 class Stats(ct.Structure):
@@ -44,7 +45,9 @@ class Stats(ct.Structure):
                 ("sample_pos", ct.c_void_p), ("bucket_sizes", ct.c_void_p), ("count_matrix", ct.c_void_p),
                 ("block_sorted", ct.c_void_p), ("block_sorted_values", ct.c_void_p), ("routed", ct.c_void_p),
                 ("buckets", ct.c_void_p), ("max_bucket_ratio", ct.c_double), ("mispredict_rate", ct.c_double),
-                ("mean_fix_dist", ct.c_double), ("oversize_chunks", ct.c_int64), ("reserved_i", ct.c_int64 * 4)]
+                ("mean_fix_dist", ct.c_double), ("oversize_chunks", ct.c_int64), ("reserved_i", ct.c_int64 * 4),
+                ("seg_models", ct.c_void_p), ("seg_grad", ct.c_void_p), ("seg_gram", ct.c_void_p),
+                ("seg_capacity", ct.c_int64)]
 
 
 def _load():
@@ -87,6 +90,10 @@ def _load():
     L.bsps_stream_copy.argtypes = [vp, vp, sz, vp]
     L.bsps_release_cache.restype = None
     L.bsps_release_cache.argtypes = []
+    L.bsps_check_sort.restype = i64
+    L.bsps_check_sort.argtypes = [i64, i32, i32, PP, ct.c_char_p, sz]
+    L.bsps_check_segmented.restype = i64
+    L.bsps_check_segmented.argtypes = [vp, i32, i32, i32, ct.c_char_p, ct.c_char_p, sz]
     L.bsps_timing.argtypes = [ct.c_int]
     L.bsps_timing_read.argtypes = [vp, vp, ct.c_int, ct.c_int]
     return L
@@ -106,10 +113,11 @@ def status_string(code: int) -> str:
 
 
 def make_params(p: int, s: int, variant: int = DET, seed: int = 1, bucketing: int = SPLITTER,
-                route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0) -> Params:
+                route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0, local_sort: int = LOCAL_AUTO) -> Params:
     prm = Params()
     prm.p, prm.s, prm.variant, prm.bucketing = p, s, variant, bucketing
     prm.route, prm.leaves, prm.seed, prm.chunk_cap = route, leaves, seed & 0xFFFFFFFFFFFFFFFF, chunk_cap
+    prm.local_sort = local_sort
     return prm
 
 
@@ -135,7 +143,7 @@ def _stream(t) -> int:
 
 def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, bucketing: int = SPLITTER,
           route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0, stats: bool = False, workspace=None,
-          stats_arrays: bool = False):
+          stats_arrays: bool = False, local_sort: int = LOCAL_AUTO):
     """Sorts `keys` (a contiguous int32/int64/float32 CUDA tensor) in place; with
     `values` (uint32 payload as an int32 tensor of the same length) a key-value
     sort. With stats=True the call synchronizes and returns the diagnostic
@@ -146,7 +154,7 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
     assert keys.is_cuda and keys.is_contiguous() and keys.dim() == 1
     n = keys.numel()
     dt = _dtype_code(keys)
-    prm = make_params(p, s, variant, seed, bucketing, route, leaves, chunk_cap)
+    prm = make_params(p, s, variant, seed, bucketing, route, leaves, chunk_cap, local_sort)
     hasv = values is not None
     if hasv:
         assert values.is_cuda and values.is_contiguous() and values.numel() == n and values.element_size() == 4
@@ -210,7 +218,7 @@ NOALLOC_SCRATCH_BYTES = 64 << 20  # BSPS_NOALLOC_SCRATCH_BYTES of bsps.h
 
 
 def sort_noalloc_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, bucketing: int = SPLITTER,
-                  route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0) -> None:
+                  route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0, local_sort: int = LOCAL_AUTO) -> None:
     """As sort_(), through bsps_sort_noalloc: no workspace is allocated, the
     library's per-GPU scratch array is used (sizes whose workspace exceeds
     NOALLOC_SCRATCH_BYTES are rejected with EUNSUPPORTED)."""
@@ -218,7 +226,7 @@ def sort_noalloc_(keys, p: int, s: int, variant: int = DET, seed: int = 1, value
     n = keys.numel()
     if values is not None:
         assert values.is_cuda and values.is_contiguous() and values.numel() == n and values.element_size() == 4
-    prm = make_params(p, s, variant, seed, bucketing, route, leaves, chunk_cap)
+    prm = make_params(p, s, variant, seed, bucketing, route, leaves, chunk_cap, local_sort)
     code = _lib.bsps_sort_noalloc(ct.c_void_p(keys.data_ptr()), _ptr(values), n, _dtype_code(keys), ct.byref(prm),
                                   ct.c_void_p(_stream(keys)))
     if code != OK:
@@ -284,8 +292,9 @@ def model_grad(sample_keys, p: int, s: int, leaves: int, model):
 
 
 def model_fields(model):
-    """Host view of a model buffer: header dict and (L, 3) float32 leaf table."""
-    raw = model.cpu().numpy()
+    """Host view of a model buffer (device tensor or host uint8 array): header
+    dict and (L, 3) float32 leaf table."""
+    raw = model if isinstance(model, np.ndarray) else model.cpu().numpy()
     lo, hi = np.frombuffer(raw[:16].tobytes(), dtype=np.float64)
     a, b, mur, inv = np.frombuffer(raw[16:32].tobytes(), dtype=np.float32)
     L, p, s, _ = np.frombuffer(raw[32:48].tobytes(), dtype=np.int32)
@@ -321,11 +330,17 @@ def segmented_workspace_bytes(offsets, dtype: int, with_values: bool, tuning: st
                                                    _tuning_arg(tuning)))
 
 
-def sort_segmented_(keys, offsets, values=None, tuning: str | None = None, stats: bool = False, workspace=None):
+SEG_LEAVES = 64  # leaves of a large segment's model
+
+
+def sort_segmented_(keys, offsets, values=None, tuning: str | None = None, stats: bool = False, workspace=None,
+                    models: int = 0):
     """Sorts every segment [offsets[i], offsets[i+1]) of `keys` (and `values`)
     in place, all segments in one captured graph launch. `offsets`: host array
     of nseg + 1 non-decreasing int64 starting at 0. `tuning`: a size-class
-    table (JSON, `tuning_format()`); default `default_tuning()`."""
+    table (JSON, `tuning_format()`); default `default_tuning()`. With stats and
+    models = capacity > 0, the result also holds the learned models of the
+    large segments and their leaf-stage gradient and Gram sums."""
     import torch
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     nseg = len(off) - 1
@@ -337,14 +352,22 @@ def sort_segmented_(keys, offsets, values=None, tuning: str | None = None, stats
         raise BspsError(code if code else EINVAL, "bsps_segmented_workspace_bytes")
     ws = workspace if workspace is not None else torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
     st = Stats() if stats else None
+    mbuf = gbuf = hbuf = None
+    if stats and models > 0:
+        mbuf = np.zeros(models * model_bytes(SEG_LEAVES), dtype=np.uint8)
+        gbuf = np.zeros(models * SEG_LEAVES * 2, dtype=np.float32)
+        hbuf = np.zeros(models * SEG_LEAVES * 3, dtype=np.float32)
+        st.seg_models, st.seg_grad, st.seg_gram = mbuf.ctypes.data, gbuf.ctypes.data, hbuf.ctypes.data
+        st.seg_capacity = models
     code = _lib.bsps_sort_segmented(_ptr(keys), _ptr(values), off.ctypes.data, nseg, dt, tj, _ptr(ws), ws.numel(),
                                     ct.c_void_p(_stream(keys)), ct.byref(st) if st is not None else None)
     if code != OK:
         raise BspsError(code, "bsps_sort_segmented")
     if stats:
         return {"oversize_chunks": st.oversize_chunks, "blocks": st.reserved_i[0], "merged_segments": st.reserved_i[1],
-                "graph": bool(st.reserved_i[2]), "learned_segments": st.reserved_i[3],
-                "mispredict_rate": st.mispredict_rate, "mean_fix_dist": st.mean_fix_dist}
+                "graph": bool(st.reserved_i[2]), "graph_cached": st.reserved_i[2] == 2, "learned_segments": st.reserved_i[3],
+                "mispredict_rate": st.mispredict_rate, "mean_fix_dist": st.mean_fix_dist,
+                "models": mbuf, "grad": gbuf, "gram": hbuf}
     return None
 
 
@@ -364,6 +387,22 @@ def stream_copy(src, dst) -> None:
                                  ct.c_void_p(torch.cuda.current_stream().cuda_stream))
     if code:
         raise BspsError(code, "bsps_stream_copy")
+
+
+def check_sort(n: int, dtype: int, with_values: bool, prm: Params) -> tuple[int, str]:
+    """Host dry run of a sort's plan (no GPU): (findings, report)."""
+    buf = ct.create_string_buffer(1 << 16)
+    k = int(_lib.bsps_check_sort(n, dtype, int(with_values), ct.byref(prm), buf, len(buf)))
+    return k, buf.value.decode()
+
+
+def check_segmented(offsets, dtype: int, with_values: bool, tuning: str | None = None) -> tuple[int, str]:
+    """Host dry run of a segmented sort's plan (no GPU): (findings, report)."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    buf = ct.create_string_buffer(1 << 16)
+    k = int(_lib.bsps_check_segmented(off.ctypes.data, len(off) - 1, dtype, int(with_values), _tuning_arg(tuning),
+                                      buf, len(buf)))
+    return k, buf.value.decode()
 
 
 def release_cache() -> None:

@@ -21,11 +21,13 @@
 #include "../../include/bsps.h"
 #include "bsps_kernels.h"
 #include "bsps_learned.h"
+#include "bsps_lsd.h"
 #include "bsps_segmented.h"
 
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 // Scratch memory of the allocation-free entry point (bsps_sort_noalloc): a
 // file-scope device array, one copy per GPU, held until the process ends.
@@ -56,9 +58,43 @@ bsps_status hip_fail(hipError_t e, const char* what, int line) {
     } while (0)
 #define LAUNCH_OK()                                                    \
     do {                                                               \
+        if (t_dry) break;                                              \
         const hipError_t e_ = hipGetLastError();                       \
         if (e_ != hipSuccess) return hip_fail(e_, "launch", __LINE__); \
     } while (0)
+
+// ------------------------------------------------------------------ host dry run
+//
+// With t_dry set (bsps_check_sort / bsps_check_segmented), the host pipeline
+// plans and "launches" every kernel without touching the GPU: each launch's
+// arguments are checked instead. Every pointer argument, and every pointer
+// inside the argument structs, must be null or lie inside the caller's
+// buffers or the workspace, and so must the whole extent of every table the
+// kernel indexes by its sizes. Plans are made with fake buffer addresses.
+struct DryRun {
+    struct Range { uintptr_t lo, hi; };
+    std::vector<Range> ranges;
+    std::vector<std::string> errors;
+    int launches = 0;
+    u64 grid = 0;
+    std::string kernel;
+    void add(const void* p, size_t bytes) { ranges.push_back({(uintptr_t)p, (uintptr_t)p + bytes}); }
+    void fail(const char* what, const void* p, size_t bytes) {
+        char buf[256];
+        std::snprintf(buf, sizeof(buf), "%s: %s = %p (+%zu bytes) outside every buffer", kernel.c_str(), what, p,
+                      bytes);
+        errors.push_back(buf);
+    }
+    // [p, p + bytes) inside one buffer (bytes 0: p may be one past the end)
+    void span(const char* what, const void* p, size_t bytes) {
+        if (!p) return;
+        const uintptr_t a = (uintptr_t)p;
+        for (auto& r : ranges)
+            if (a >= r.lo && a + bytes <= r.hi) return;
+        fail(what, p, bytes);
+    }
+};
+thread_local DryRun* t_dry = nullptr;
 
 inline u64 cdiv(u64 a, u64 b) { return (a + b - 1) / b; }
 // The learned-rank counters (two u64, updated by 64-bit atomics) follow the
@@ -85,6 +121,102 @@ struct Carver {
 
 int key_bytes(int dt) { return dt == BSPS_I64 ? 8 : 4; }
 
+// Argument checks of the dry run, by type: a plain pointer must lie inside a
+// buffer (its extent is not known here); an argument struct's tables must fit
+// inside a buffer at the extent the kernel indexes them with; scalars pass.
+template <typename T>
+void dry_check(T* p) {
+    t_dry->span("pointer argument", p, 0);
+}
+template <typename T>
+typename std::enable_if<std::is_arithmetic<T>::value || std::is_enum<T>::value>::type dry_check(T) {}
+template <typename T>
+void dry_span(const char* what, const T* p, u64 count) {
+    t_dry->span(what, p, (size_t)count * sizeof(T));
+}
+template <typename K>
+void dry_check(const TileArgs<K>& a) {
+    const u64 n = (u64)std::max<i64>(a.n, 0);
+    dry_span("TileArgs.in", a.in, n);
+    dry_span("TileArgs.inv", a.inv, n);
+    dry_span("TileArgs.out", a.out, n);
+    dry_span("TileArgs.outv", a.outv, n);
+    const u64 ntile = a.persist ? a.ntile : t_dry->grid;
+    if (a.btab) {
+        dry_span("TileArgs.btab", a.btab, 4 * ntile);
+        dry_span("TileArgs.dtab", a.dtab, 1);
+        dry_span("TileArgs.outd", a.outd, n);
+        dry_span("TileArgs.outdv", a.outdv, n);
+        dry_span("TileArgs.smp", a.smp, 1);
+    } else {
+        dry_span("TileArgs.smp", a.smp, (u64)a.p * a.tpb * a.spt);
+        if (a.dtab || a.outd || a.outdv) t_dry->fail("TileArgs: segment tables without btab", a.dtab, 0);
+    }
+}
+template <typename K>
+void dry_check(const MwmArgs<K>& a) {
+    const u64 G = (u64)a.G, R = (u64)a.R, S = a.S;
+    dry_span("MwmArgs.src", a.src, 0);
+    dry_span("MwmArgs.srcv", a.srcv, 0);
+    dry_span("MwmArgs.dst", a.dst, 0);
+    dry_span("MwmArgs.dstv", a.dstv, 0);
+    dry_span("MwmArgs.scr", a.scr, 0);
+    dry_span("MwmArgs.scrv", a.scrv, 0);
+    dry_span("MwmArgs.run_start", a.run_start, G * R);
+    dry_span("MwmArgs.run_len", a.run_len, G * R);
+    dry_span("MwmArgs.out_base", a.out_base, G);
+    dry_span("MwmArgs.sdesc", a.sdesc, G * R * 4);
+    dry_span("MwmArgs.smp", a.smp, 0);
+    dry_span("MwmArgs.counters", a.slot_count, 6);
+    dry_span("MwmArgs.slot_group", a.slot_group, S);
+    dry_span("MwmArgs.grp_base", a.grp_base, G);
+    dry_span("MwmArgs.grp_nb", a.grp_nb, G);
+    dry_span("MwmArgs.bkey", a.bkey, S);
+    dry_span("MwmArgs.bpos", a.bpos, S);
+    dry_span("MwmArgs.cuts", a.cuts, S * R);
+    dry_span("MwmArgs.below", a.below, S);
+    dry_span("MwmArgs.witem", a.witem, 2 * S);
+    dry_span("MwmArgs.heavy", a.heavy, G);
+    dry_span("MwmArgs.gpar", a.gpar, 2 * G);
+    dry_span("MwmArgs.osmp", a.osmp, G * a.ospb);
+    if (a.R > MAXR || a.G < 0) t_dry->fail("MwmArgs: more runs per group than the merge holds", nullptr, 0);
+}
+template <typename K>
+void dry_check(const LsdArgs<K>& a) {
+    const u64 n = (u64)a.n, p = (u64)a.p, DP = sizeof(K);
+    dry_span("LsdArgs.in", a.in, n);
+    dry_span("LsdArgs.inv", a.inv, n);
+    dry_span("LsdArgs.a", a.a, n);
+    dry_span("LsdArgs.av", a.av, n);
+    dry_span("LsdArgs.b", a.b, n);
+    dry_span("LsdArgs.bv", a.bv, n);
+    dry_span("LsdArgs.out", a.out, n);
+    dry_span("LsdArgs.outv", a.outv, n);
+    dry_span("LsdArgs.dbase", a.dbase, p * DP * LSD_RADIX);
+    dry_span("LsdArgs.plist", a.plist, p * (DP + 1));
+    dry_span("LsdArgs.smp", a.smp, p * a.spb);
+    if (!a.inv != !a.outv || !a.av != !a.outv || !a.bv != !a.outv)
+        t_dry->fail("LsdArgs: payload buffers given for some passes only", a.outv, 0);
+}
+template <typename... A>
+void dry_launch(const char* name, dim3 grid, dim3 block, const A&... args) {
+    t_dry->kernel = name;
+    t_dry->launches++;
+    t_dry->grid = (u64)grid.x * grid.y * grid.z;
+    if (grid.x == 0 || grid.y == 0 || grid.z == 0 || block.x == 0 || block.x > 1024)
+        t_dry->errors.push_back(std::string(name) + ": empty grid or bad workgroup size");
+    (dry_check(args), ...);
+}
+
+// A kernel launch, or its argument check in a dry run.
+#define LAUNCH(KER, GRID, BLOCK, SHMEM, STREAM, ...)                                    \
+    do {                                                                                \
+        if (t_dry)                                                                      \
+            dry_launch(#KER, dim3(GRID), dim3(BLOCK), __VA_ARGS__);                     \
+        else                                                                            \
+            hipLaunchKernelGGL(KER, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);           \
+    } while (0)
+
 // Optional per-stage timing with HIP events recorded on the caller's stream
 // around each stage (diagnostics and benchmarks only).
 enum Stage {
@@ -97,6 +229,7 @@ enum Stage {
     ST_BLOCK_MERGE_K,  // k_mwm_merge alone, block merge
     ST_BUCKET_MERGE_K, // k_mwm_merge alone, bucket merge
     ST_RANK_K,         // per-key rank kernel alone
+    ST_LSD_K,          // A1 by LSD radix: the pass kernels alone
     ST_N
 };
 struct StageTimer {
@@ -122,7 +255,8 @@ struct StageScope {
     hipStream_t st;
     hipEvent_t e0 = nullptr;
     StageScope(int s_, hipStream_t st_) : stage(s_), st(st_) {
-        if (stage < ST_N && g_timer.on && !t_no_events && (e0 = g_timer.get()) && hipEventRecord(e0, st) != hipSuccess)
+        if (stage < ST_N && g_timer.on && !t_no_events && !t_dry && (e0 = g_timer.get()) &&
+            hipEventRecord(e0, st) != hipSuccess)
             e0 = nullptr;
     }
     ~StageScope() {
@@ -187,6 +321,7 @@ MwmArgs<K> mwm_args(const MwmBufs<K>& m, const K* src, const u32* srcv, K* dst, 
 }
 
 int device_cus() {
+    if (t_dry) return 256;
     static int cus = 0;
     if (!cus) {
         int dev = 0;
@@ -205,7 +340,7 @@ bsps_status launch_rank(const K* B, i64 n, int p, const K* spk, const u32* spp, 
     typedef RankShape<LEARNED> RS;
     const int tpb = (int)cdiv(cdiv((u64)n, (u64)p), (u64)rank_tile<LEARNED>());
     const u32 grid = (u32)std::max<i64>(1, std::min<i64>((i64)p * tpb, (i64)device_cus() * RS::WG_PER_CU));
-    hipLaunchKernelGGL((k_rank<K, LEARNED>), dim3(grid), dim3(RS::NT), 0, st, B, n, p, tpb, spk, spp, dt, model,
+    LAUNCH((k_rank<K, LEARNED>), dim3(grid), dim3(RS::NT), 0, st, B, n, p, tpb, spk, spp, dt, model,
                        bucket, counts, lstats);
     LAUNCH_OK();
     return BSPS_OK;
@@ -215,23 +350,23 @@ template <typename K, bool HASV>
 bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     constexpr int NT = Shape<K>::NT;
     const int cus = device_cus();
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.slot_count, 8);
+    LAUNCH(k_zero_u32, dim3(1), dim3(64), 0, st, a.slot_count, 8);
     LAUNCH_OK();
-    hipLaunchKernelGGL((k_mwm_size<K>), dim3(a.G), dim3(SIZE_NT), 0, st, a);
+    LAUNCH((k_mwm_size<K>), dim3(a.G), dim3(SIZE_NT), 0, st, a);
     LAUNCH_OK();
     // the groups with boundaries only (listed by k_mwm_size), in loops
-    hipLaunchKernelGGL((k_mwm_pick<K>), dim3((u32)std::min<u64>(a.G, (u64)cus * 2)), dim3(NT), 0, st, a);
+    LAUNCH((k_mwm_pick<K>), dim3((u32)std::min<u64>(a.G, (u64)cus * 2)), dim3(NT), 0, st, a);
     LAUNCH_OK();
     // one wave per (group, run); with few runs the boundaries are split over
     // gridDim.y waves so that the launch still holds some 8K waves
     const u64 nwave = std::max<u64>(1, (u64)a.G * a.R);
     const u32 ysplit = (u32)std::min<u64>(64, std::max<u64>(1, cdiv(8192, nwave)));
-    hipLaunchKernelGGL((k_mwm_cuts<K>), dim3((u32)cdiv(nwave, CUT_NT / 64), ysplit), dim3(CUT_NT), 0, st, a);
+    LAUNCH((k_mwm_cuts<K>), dim3((u32)cdiv(nwave, CUT_NT / 64), ysplit), dim3(CUT_NT), 0, st, a);
     LAUNCH_OK();
-    hipLaunchKernelGGL((k_mwm_below<K>), dim3((u32)std::min<u64>(cdiv(a.S, 4), (u64)cus * 16)), dim3(256), 0, st,
+    LAUNCH((k_mwm_below<K>), dim3((u32)std::min<u64>(cdiv(a.S, 4), (u64)cus * 16)), dim3(256), 0, st,
                        a);
     LAUNCH_OK();
-    hipLaunchKernelGGL((k_mwm_plan<K>), dim3((u32)std::min<u64>(a.G, (u64)cus * 4)), dim3(PLAN_NT), 0, st, a);
+    LAUNCH((k_mwm_plan<K>), dim3((u32)std::min<u64>(a.G, (u64)cus * 4)), dim3(PLAN_NT), 0, st, a);
     LAUNCH_OK();
 #ifndef BSPS_MERGE_WGS_PER_CU
 #define BSPS_MERGE_WGS_PER_CU 2
@@ -239,7 +374,7 @@ bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     const u32 gmerge = BSPS_MERGE_WGS_PER_CU > 0 ? (u32)std::min<u64>(a.S, (u64)cus * BSPS_MERGE_WGS_PER_CU) : a.S;
     {
         StageScope sc(kstage, st);
-        hipLaunchKernelGGL((k_mwm_merge<K, HASV>), dim3(gmerge), dim3(NT), 0, st, a);
+        LAUNCH((k_mwm_merge<K, HASV>), dim3(gmerge), dim3(NT), 0, st, a);
     }
     LAUNCH_OK();
     return BSPS_OK;
@@ -288,11 +423,12 @@ u32 tile_grid(TileArgs<K>& ta, u32 ntile) {
     ta.ntile = ntile;
     if (HASV) return ntile;
     static int occ = -1;
-    if (occ < 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_tile_sort<K, HASV, TT>, NT, 0) != hipSuccess)
+    if (!t_dry && occ < 0 &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_tile_sort<K, HASV, TT>, NT, 0) != hipSuccess)
         occ = 0;
-    if (occ <= 0) return ntile;
+    if (!t_dry && occ <= 0) return ntile;
     ta.persist = 1;
-    return (u32)std::max<u64>(1, std::min<u64>(ntile, (u64)device_cus() * occ));
+    return (u32)std::max<u64>(1, std::min<u64>(ntile, (u64)device_cus() * std::max(occ, 1)));
 }
 
 // in (dtype in_dt) -> out (order keys, or raw keys of out_dt), every block of
@@ -309,7 +445,7 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
     if (b.tpb == 1) {
         ta.out = out; ta.outv = outv; ta.out_dt = out_dt; ta.smp = osmp; ta.ys = yb; ta.spt = spb;
         StageScope sc(tstage, st);
-        hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3(p), dim3(NT), 0, st, ta);
+        LAUNCH((k_tile_sort<K, HASV>), dim3(p), dim3(NT), 0, st, ta);
         LAUNCH_OK();
         return BSPS_OK;
     }
@@ -317,16 +453,48 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
     const u32 tgrid = tile_grid<K, HASV>(ta, (u32)(p * b.tpb));
     {
         StageScope sc(tstage, st);
-        hipLaunchKernelGGL((k_tile_sort<K, HASV>), dim3(tgrid), dim3(NT), 0, st, ta);
+        LAUNCH((k_tile_sort<K, HASV>), dim3(tgrid), dim3(NT), 0, st, ta);
     }
     LAUNCH_OK();
     StageScope sc(mstage, st);
     const u64 nrun = (u64)p * b.tpb;
-    hipLaunchKernelGGL((k_block_tables<K>), dim3((u32)cdiv(nrun, 256)), dim3(256), 0, st, n, p, b.tpb, T,
+    LAUNCH((k_block_tables<K>), dim3((u32)cdiv(nrun, 256)), dim3(256), 0, st, n, p, b.tpb, T,
                        kSampleStride, b.spt, b.mwm.run_start, b.mwm.run_len, b.mwm.out_base, b.mwm.sdesc);
     LAUNCH_OK();
     MwmArgs<K> a = mwm_args<K>(b.mwm, b.A, b.Av, out, outv, scr, scrv, b.tsmp, cap, tavg, out_dt, osmp, yb, spb);
     return mwm_run<K, HASV>(a, st, mkstage);
+}
+
+// ------------------------------------------------------------------ block sort by LSD radix (A1)
+
+// in (dtype in_dt, keys and payloads) -> out (order keys): every block of the
+// p-way split sorted stably by LSD passes through HBM. A/Av and in/inv itself
+// are the scratch of the passes in between (in is consumed). osmp: block
+// samples every yb-th key (slot stride spb).
+template <typename K, bool HASV>
+bsps_status lsd_block_sort(K* in, u32* inv, int in_dt, K* A, u32* Av, K* out, u32* outv, u32* dbase, u32* plist,
+                           i64 n, int p, int tpb, K* osmp, u32 yb, u32 spb, hipStream_t st) {
+    constexpr int NT = Shape<K>::NT;
+    LsdArgs<K> a{};
+    a.in = in; a.inv = inv; a.in_dt = in_dt;
+    a.a = A; a.av = Av; a.b = in; a.bv = inv;
+    a.out = out; a.outv = outv;
+    a.n = n; a.p = p; a.tpb = tpb;
+    a.dbase = dbase; a.plist = plist;
+    a.smp = osmp; a.ys = yb; a.spb = spb;
+    static int occ = -1;
+    if (!t_dry && occ < 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_lsd_pass<K, HASV>, NT, 0) != hipSuccess)
+        occ = 0;
+    const u32 grid = (u32)std::max<i64>(1, std::min<i64>(p, (i64)device_cus() * std::max(occ, 1)));
+    StageScope sc(ST_TILE, st);
+    LAUNCH((k_lsd_hist<K>), dim3((u32)p), dim3(LSD_HIST_NT), 0, st, a);
+    LAUNCH_OK();
+    StageScope sk(ST_LSD_K, st);
+    for (int pass = 0; pass < (int)sizeof(K); pass++) {
+        LAUNCH((k_lsd_pass<K, HASV>), dim3(grid), dim3(NT), 0, st, a, pass);
+        LAUNCH_OK();
+    }
+    return BSPS_OK;
 }
 
 // ------------------------------------------------------------------ learned model
@@ -362,33 +530,33 @@ bsps_status fit_model(const K* smp, i64 N, int dt, int p, int s, int L, int iter
     Carver c(ws);
     FitWs f = carve_fit(c, N, L);
     const u32 gN = (u32)std::max<u64>(1, cdiv((u64)N, 256));
-    hipLaunchKernelGGL((k_model_init<K>), dim3(1), dim3(64), 0, st, smp, N, dt, p, s, L, model);
+    LAUNCH((k_model_init<K>), dim3(1), dim3(64), 0, st, smp, N, dt, p, s, L, model);
     LAUNCH_OK();
     for (int stage = 0; stage < 2; stage++) {
         const int nmod = stage == 0 ? 1 : L;
         const u32 gM = (u32)cdiv((u64)nmod + 1, 256);
-        hipLaunchKernelGGL((k_model_x<K>), dim3(gN), dim3(256), 0, st, smp, N, dt, (const void*)model, stage, f.x,
+        LAUNCH((k_model_x<K>), dim3(gN), dim3(256), 0, st, smp, N, dt, (const void*)model, stage, f.x,
                            f.leafid);
         LAUNCH_OK();
-        hipLaunchKernelGGL(k_model_ranges, dim3(gM), dim3(256), 0, st, f.leafid, N, nmod, f.lo);
+        LAUNCH(k_model_ranges, dim3(gM), dim3(256), 0, st, f.leafid, N, nmod, f.lo);
         LAUNCH_OK();
         if (stage == 0)
-            hipLaunchKernelGGL(k_model_centres<1024>, dim3(1), dim3(1024), 0, st, f.x, f.lo, nmod, model, stage);
+            LAUNCH(k_model_centres<1024>, dim3(1), dim3(1024), 0, st, f.x, f.lo, nmod, model, stage);
         else
-            hipLaunchKernelGGL(k_model_centres<64>, dim3(nmod), dim3(64), 0, st, f.x, f.lo, nmod, model, stage);
+            LAUNCH(k_model_centres<64>, dim3(nmod), dim3(64), 0, st, f.x, f.lo, nmod, model, stage);
         LAUNCH_OK();
         for (int it = 0; it < iters; it++) {
-            hipLaunchKernelGGL(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, f.leafid, N, p, s,
+            LAUNCH(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, f.leafid, N, p, s,
                                (const void*)model, stage, f.r);
             LAUNCH_OK();
             if (stage == 0)
-                hipLaunchKernelGGL(k_model_backward<1024>, dim3(1), dim3(1024), 0, st, f.x, f.r, f.lo, nmod, N,
+                LAUNCH(k_model_backward<1024>, dim3(1), dim3(1024), 0, st, f.x, f.r, f.lo, nmod, N,
                                    (const void*)model, stage, f.g, f.hs, f.lossp);
             else
-                hipLaunchKernelGGL(k_model_backward<64>, dim3(nmod), dim3(64), 0, st, f.x, f.r, f.lo, nmod, N,
+                LAUNCH(k_model_backward<64>, dim3(nmod), dim3(64), 0, st, f.x, f.r, f.lo, nmod, N,
                                    (const void*)model, stage, f.g, f.hs, f.lossp);
             LAUNCH_OK();
-            hipLaunchKernelGGL(k_model_update, dim3(gM), dim3(256), 0, st, f.g, f.hs, f.lo, nmod, p, s, model,
+            LAUNCH(k_model_update, dim3(gM), dim3(256), 0, st, f.g, f.hs, f.lo, nmod, p, s, model,
                                stage);
             LAUNCH_OK();
         }
@@ -413,6 +581,9 @@ Opts opts_for(const bsps_params* prm) {
 
 template <typename K>
 struct Plan {
+    bool lsd;                // A1 by LSD radix through HBM (else tiles + multiway merge)
+    u32* dbase;              // LSD: digit starts [p][sizeof(K)][256]
+    u32* plist;              // LSD: passes of every block [p][sizeof(K) + 1]
     BlockSortBufs<K> bs;     // main block sort
     K* B;
     u32* Bv;
@@ -446,12 +617,34 @@ struct Plan {
     size_t fitws_bytes;
 };
 
+// Which local sort A1 uses (bsps_local_sort). Auto: the tile sort and merge,
+// measured faster than the LSD passes on every workload.
+template <typename K>
+bool use_lsd(i64 n, const bsps_params* prm) {
+    if (prm->local_sort == BSPS_LOCAL_LSD) return true;
+    if (prm->local_sort == BSPS_LOCAL_MERGE) return false;
+    (void)n;
+    return false;
+}
+
 template <typename K>
 size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* prm) {
     const int p = prm->p;
     const Opts o = opts_for<K>(prm);
     const bool scatter = prm->route == BSPS_ROUTE_SCATTER;
-    carve_block_sort<K>(c, P.bs, (u64)n, p, hasv, o.tavg, true);  // A doubles as merge scratch / routed array
+    P.lsd = use_lsd<K>(n, prm);
+    P.dbase = P.plist = nullptr;
+    if (P.lsd) {
+        // A: pass scratch, then merge scratch / routed array
+        std::memset(&P.bs, 0, sizeof(P.bs));
+        P.bs.tpb = (int)std::max<u64>(1, cdiv(cdiv((u64)n, (u64)p), tileT<K>()));
+        P.bs.A = c.take<K>(n);
+        P.bs.Av = hasv ? c.take<u32>(n) : nullptr;
+        P.dbase = c.take<u32>((u64)p * sizeof(K) * LSD_RADIX);
+        P.plist = c.take<u32>((u64)p * (sizeof(K) + 1));
+    } else {
+        carve_block_sort<K>(c, P.bs, (u64)n, p, hasv, o.tavg, true);  // A doubles as merge scratch / routed array
+    }
     P.B = c.take<K>(n);
     P.Bv = hasv ? c.take<u32>(n) : nullptr;
     const u64 m = cdiv((u64)n, (u64)p);
@@ -504,7 +697,8 @@ bsps_status validate(i64 n, int dtype, const bsps_params* prm) {
     if (prm->route != BSPS_ROUTE_FUSED && prm->route != BSPS_ROUTE_SCATTER) return BSPS_EINVAL;
     if (prm->bucketing != BSPS_SPLITTER && prm->bucketing != BSPS_LEARNED) return BSPS_EINVAL;
     if (prm->leaves < 0 || prm->leaves > MAX_LEAVES || prm->chunk_cap < 0) return BSPS_EINVAL;
-    for (int i = 0; i < 7; i++)
+    if (prm->local_sort < BSPS_LOCAL_AUTO || prm->local_sort > BSPS_LOCAL_LSD) return BSPS_EINVAL;
+    for (int i = 0; i < 6; i++)
         if (prm->reserved[i]) return BSPS_EINVAL;
     if (prm->variant == BSPS_RAN && (i64)prm->s * prm->p - 1 > n) return BSPS_EINVAL;
     if (n >= (i64)0xFFFFFFFFll || prm->p > kMaxP) return BSPS_EUNSUPPORTED;
@@ -608,9 +802,13 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
     K* io = (K*)keys;
     bsps_status rc;
     // A1: every virtual processor sorts its block (stable).
-    rc = block_sort<K, HASV>(P.bs, io, vals, dt, P.B, P.Bv, BSPS_DT_NONE, io, vals, n, p, o.cap, o.tavg, P.bsmp,
-                             kSampleStride, std::max<u32>(1, P.spb), st, ST_TILE, ST_BLOCK_MERGE,
-                             ST_BLOCK_MERGE_K);
+    if (P.lsd)
+        rc = lsd_block_sort<K, HASV>(io, vals, dt, P.bs.A, P.bs.Av, P.B, P.Bv, P.dbase, P.plist, n, p, P.bs.tpb,
+                                     P.bsmp, kSampleStride, P.spb, st);
+    else
+        rc = block_sort<K, HASV>(P.bs, io, vals, dt, P.B, P.Bv, BSPS_DT_NONE, io, vals, n, p, o.cap, o.tavg, P.bsmp,
+                                 kSampleStride, std::max<u32>(1, P.spb), st, ST_TILE, ST_BLOCK_MERGE,
+                                 ST_BLOCK_MERGE_K);
     if (rc) return rc;
     if (stats && stats->block_sorted) {
         rc = copy_keys_out<K>(stats->block_sorted, P.B, n, dt, st);
@@ -621,7 +819,7 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         if (rc) return rc;
     }
     if (p == 1) {
-        hipLaunchKernelGGL((k_copy_out<K>), dim3((u32)cdiv(n, 256)), dim3(256), 0, st, P.B, HASV ? P.Bv : nullptr, io,
+        LAUNCH((k_copy_out<K>), dim3((u32)cdiv(n, 256)), dim3(256), 0, st, P.B, HASV ? P.Bv : nullptr, io,
                            vals, n, dt);
         LAUNCH_OK();
         if (stats) {
@@ -637,18 +835,18 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         StageScope sc(ST_SAMPLE, st);
         // A2: sample records (key, position in B), in position order.
         if (prm->variant == BSPS_DET) {
-            hipLaunchKernelGGL((k_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, n, p, s, P.skey,
+            LAUNCH((k_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, n, p, s, P.skey,
                                P.spos);
             LAUNCH_OK();
         } else {
-            hipLaunchKernelGGL(k_ran_positions, dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, (u64)prm->seed, n, ns,
+            LAUNCH(k_ran_positions, dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, (u64)prm->seed, n, ns,
                                P.rpos);
             LAUNCH_OK();
             const Opts ou = opts_for<u32>(prm);
             rc = block_sort<u32, false>(P.rs, P.rpos, nullptr, BSPS_DT_NONE, P.spos, nullptr, BSPS_DT_NONE, P.rpos_scr,
                                         nullptr, ns, 1, ou.cap, ou.tavg, nullptr, 1, 1, st);
             if (rc) return rc;
-            hipLaunchKernelGGL((k_gather_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, P.spos, ns,
+            LAUNCH((k_gather_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, P.spos, ns,
                                P.skey);
             LAUNCH_OK();
         }
@@ -656,28 +854,27 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         rc = block_sort<K, true>(P.ss, P.skey, P.spos, BSPS_DT_NONE, P.ssk, P.ssp, BSPS_DT_NONE, P.sscr, P.sscrv, ns, 1,
                                  o.cap, o.tavg, nullptr, 1, 1, st);
         if (rc) return rc;
-        hipLaunchKernelGGL((k_splitters<K>), dim3((u32)cdiv(p, 256)), dim3(256), 0, st, P.ssk, P.ssp, p, s, P.pk, P.pp);
+        LAUNCH((k_splitters<K>), dim3((u32)cdiv(p, 256)), dim3(256), 0, st, P.ssk, P.ssp, p, s, P.pk, P.pp);
+        LAUNCH_OK();
+    }
+    // A4: bucket boundaries inside every sorted block (splitters searched into it).
+    {
+        StageScope sc(ST_COUNT, st);
+        const u64 ncnt = (u64)(p + 1) * p;
+        if (P.spb > 0 && P.spb <= (u32)COUNT_SMAX)
+            LAUNCH((k_count_staged<K>), dim3(p), dim3(COUNT_NT), 0, st, P.B, n, p, P.pk, P.pp, P.bsmp, P.spb,
+                   kSampleStride, P.cntT);
+        else
+            LAUNCH((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pp, P.cntT);
         LAUNCH_OK();
     }
     if (prm->route == BSPS_ROUTE_FUSED) {
-        // A4: bucket boundaries inside every sorted block (splitters searched into it).
-        {
-            StageScope sc(ST_COUNT, st);
-            const u64 ncnt = (u64)(p + 1) * p;
-            if (P.spb > 0 && P.spb <= (u32)COUNT_SMAX)
-                hipLaunchKernelGGL((k_count_staged<K>), dim3(p), dim3(COUNT_NT), 0, st, P.B, n, p, P.pk, P.pp, P.bsmp,
-                                   P.spb, kSampleStride, P.cntT);
-            else
-                hipLaunchKernelGGL((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pp,
-                                   P.cntT);
-            LAUNCH_OK();
-        }
         // A5: prefix sums -> runs of every bucket. A6: merge them (routing fused).
         {
             StageScope sc(ST_TABLES, st);
-            hipLaunchKernelGGL(k_bucket_tables, dim3(p), dim3(256), 0, st, n, p, P.cntT, kSampleStride,
-                               std::max<u32>(1, P.spb), (const u32*)nullptr, P.bm.run_start, P.bm.run_len,
-                               P.bm.out_base, P.bm.sdesc);
+            LAUNCH(k_bucket_tables, dim3(p), dim3(256), 0, st, n, p, P.cntT, kSampleStride,
+                   std::max<u32>(1, P.spb), (const u32*)nullptr, P.bm.run_start, P.bm.run_len, P.bm.out_base,
+                   P.bm.sdesc);
             LAUNCH_OK();
         }
         {
@@ -688,44 +885,44 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
             if (rc) return rc;
         }
     } else {
-        // A4: every key ranked on its own (splitter search or learned model).
-        {
+        // A5 with A4 per key: the p independent prefix computations, then the
+        // routing into Z (= A), every key ranked on its own (splitter search
+        // or the learned model with the exact check) as it is moved.
+        if (prm->bucketing == BSPS_LEARNED) {
             StageScope sc(ST_COUNT, st);
-            if (prm->bucketing == BSPS_LEARNED) {
-                const int L = prm->leaves > 0 ? prm->leaves : 4096;
-                // one Newton step per stage: the loss of each linear model is quadratic
-                rc = fit_model<K>(P.ssk, ns, BSPS_DT_NONE, p, s, L, 1, P.model, P.fitws, st);
-                if (rc) return rc;
-            }
-            hipLaunchKernelGGL(k_zero_u32, dim3((u32)cdiv(lstats_off(p) + 4, 256)), dim3(256), 0, st, P.C,
-                               (int)(lstats_off(p) + 4));
-            LAUNCH_OK();
-            StageScope sk(ST_RANK_K, st);
-            // per-key bucket ids only for the diagnostic copy: routing needs
-            // just the counts, since the runs of a sorted block are contiguous
-            u32* bids = (stats && stats->buckets) ? P.bucket : nullptr;
-            if (prm->bucketing == BSPS_LEARNED)
-                rc = launch_rank<K, true>(P.B, n, p, P.pk, P.pp, BSPS_DT_NONE, P.model, bids, P.C,
-                                          (unsigned long long*)(P.C + lstats_off(p)), st);
-            else
-                rc = launch_rank<K, false>(P.B, n, p, P.pk, P.pp, BSPS_DT_NONE, nullptr, bids, P.C, nullptr, st);
+            const int L = prm->leaves > 0 ? prm->leaves : 4096;
+            // one Newton step per stage: the loss of each linear model is quadratic
+            rc = fit_model<K>(P.ssk, ns, BSPS_DT_NONE, p, s, L, 1, P.model, P.fitws, st);
             if (rc) return rc;
         }
-        // A5: the p independent prefix computations, then routing into Z (= A).
         {
             StageScope sc(ST_TABLES, st);
-            hipLaunchKernelGGL(k_counts_to_cntT, dim3(p), dim3(256), 0, st, P.C, p, P.cntT);
+            LAUNCH(k_zero_u32, dim3(1), dim3(64), 0, st, P.C + lstats_off(p), 4);
             LAUNCH_OK();
-            hipLaunchKernelGGL(k_route_offsets, dim3(p), dim3(256), 0, st, P.C, P.cntT, p, P.off);
+            LAUNCH(k_route_offsets_T, dim3(p), dim3(256), 0, st, P.cntT, p, P.off);
             LAUNCH_OK();
-            // about 2048 workgroups in all, each taking a share of one block
-            const int wpb = (int)std::max<i64>(1, (2048 + p - 1) / p);
-            hipLaunchKernelGGL((k_scatter<K, HASV>), dim3((u32)(p * wpb)), dim3(SCAT_NT), 0, st, P.B, P.Bv, n, p, wpb,
-                               P.C, P.off, P.bs.A, P.bs.Av);
+            // per-key bucket ids only for the diagnostic copy
+            u32* bids = (stats && stats->buckets) ? P.bucket : nullptr;
+            unsigned long long* lst = (unsigned long long*)(P.C + lstats_off(p));
+            StageScope sk(ST_RANK_K, st);
+            if (prm->bucketing == BSPS_LEARNED) {
+                typedef RankShape<true> RS;
+                const int wpb = (int)std::max<i64>(1, cdiv((u64)device_cus() * RS::WG_PER_CU * 2, (u64)p));
+                LAUNCH((k_scatter_rank<K, true, HASV>), dim3((u32)(p * wpb)), dim3(RS::NT), 0, st, P.B, P.Bv, n, p,
+                       wpb, P.pk, P.pp, (const void*)P.model, P.cntT, P.off, P.bs.A, P.bs.Av, bids, lst);
+            } else {
+                typedef RankShape<false> RS;
+                const int wpb = (int)std::max<i64>(1, cdiv((u64)device_cus() * RS::WG_PER_CU * 2, (u64)p));
+                LAUNCH((k_scatter_rank<K, false, HASV>), dim3((u32)(p * wpb)), dim3(RS::NT), 0, st, P.B, P.Bv, n,
+                       p, wpb, P.pk, P.pp, (const void*)nullptr, P.cntT, P.off, P.bs.A, P.bs.Av, bids, lst);
+            }
             LAUNCH_OK();
-            hipLaunchKernelGGL(k_bucket_tables, dim3(p), dim3(256), 0, st, n, p, P.cntT, kSampleStride,
-                               std::max<u32>(1, P.spb), (const u32*)P.off, P.bm.run_start, P.bm.run_len,
-                               P.bm.out_base, P.bm.sdesc);
+        }
+        {
+            StageScope sc(ST_TABLES, st);
+            LAUNCH(k_bucket_tables, dim3(p), dim3(256), 0, st, n, p, P.cntT, kSampleStride,
+                   std::max<u32>(1, P.spb), (const u32*)P.off, P.bm.run_start, P.bm.run_len, P.bm.out_base,
+                   P.bm.sdesc);
             LAUNCH_OK();
         }
         if (stats && stats->routed) {
@@ -762,7 +959,7 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         rc = d2h(ctr, P.bm.counters, 16, st);
         if (rc) return rc;
         u32 ctr2[4] = {0, 0, 0, 0};
-        if (P.bs.tpb > 1) {
+        if (!P.lsd && P.bs.tpb > 1) {
             rc = d2h(ctr2, P.bs.mwm.counters, 16, st);
             if (rc) return rc;
         }
@@ -1068,14 +1265,14 @@ bsps_status enqueue_segmented(const SegPlan& P, const SegBufs<K>& b, K* io, u32*
     ta.btab = b.btab; ta.dtab = b.dtab; ta.outd = io; ta.outdv = vals;
     {
         StageScope sc(ST_TILE, st);
-        hipLaunchKernelGGL((k_tile_sort<K, HASV, true>), dim3(tile_grid<K, HASV, true>(ta, P.NB)), dim3(NT), 0, st, ta);
+        LAUNCH((k_tile_sort<K, HASV, true>), dim3(tile_grid<K, HASV, true>(ta, P.NB)), dim3(NT), 0, st, ta);
         LAUNCH_OK();
     }
     if (P.nmerged == 0) return BSPS_OK;
     const u32 ns = P.soff.back(), np = P.poff.back(), nc = P.coff.back();
     {
         StageScope sc(ST_SAMPLE, st);
-        hipLaunchKernelGGL((k_seg_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, b.B, b.seg, b.soff,
+        LAUNCH((k_seg_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, b.B, b.seg, b.soff,
                            P.nseg, b.skey, b.spos);
         LAUNCH_OK();
         TileArgs<K> tb{};
@@ -1083,49 +1280,49 @@ bsps_status enqueue_segmented(const SegPlan& P, const SegBufs<K>& b, K* io, u32*
         tb.in = b.skey; tb.inv = b.spos; tb.n = ns; tb.p = 1; tb.tpb = 1; tb.in_dt = BSPS_DT_NONE;
         tb.out = b.ssk; tb.outv = b.ssp; tb.out_dt = BSPS_DT_NONE; tb.smp = nullptr; tb.ys = 1;
         tb.btab = b.btab_s;
-        hipLaunchKernelGGL((k_tile_sort<K, true>), dim3(P.nmerged), dim3(NT), 0, st, tb);
+        LAUNCH((k_tile_sort<K, true>), dim3(P.nmerged), dim3(NT), 0, st, tb);
         LAUNCH_OK();
         if (np) {
-            hipLaunchKernelGGL((k_seg_splitters<K>), dim3((u32)cdiv(np, 256)), dim3(256), 0, st, b.ssk, b.ssp, b.seg,
+            LAUNCH((k_seg_splitters<K>), dim3((u32)cdiv(np, 256)), dim3(256), 0, st, b.ssk, b.ssp, b.seg,
                                b.soff, b.poff, P.nseg, b.pk, b.pp);
             LAUNCH_OK();
         }
     }
     {
         StageScope sc(ST_COUNT, st);
-        hipLaunchKernelGGL((k_seg_count<K>), dim3((u32)cdiv(nc, 256)), dim3(256), 0, st, b.B, b.seg, b.poff, b.coff,
+        LAUNCH((k_seg_count<K>), dim3((u32)cdiv(nc, 256)), dim3(256), 0, st, b.B, b.seg, b.poff, b.coff,
                            P.nseg, b.pk, b.pp, b.cntT);
         LAUNCH_OK();
         if (P.NL > 0) {
             // large segments: train their models on their sorted samples, then
             // rank every key (learned prediction + exact splitter check)
-            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (u32*)b.lst, 4);
+            LAUNCH(k_zero_u32, dim3(1), dim3(64), 0, st, (u32*)b.lst, 4);
             LAUNCH_OK();
-            hipLaunchKernelGGL((k_sl_init<K>), dim3((u32)cdiv(P.NL, 64)), dim3(64), 0, st, b.ssk, b.seg, b.soff,
+            LAUNCH((k_sl_init<K>), dim3((u32)cdiv(P.NL, 64)), dim3(64), 0, st, b.ssk, b.seg, b.soff,
                                b.lseg, P.NL, b.models);
             LAUNCH_OK();
             const u32 gq = (u32)std::max<u64>(1, cdiv(P.nls, 256));
             for (int stage = 0; stage < 2; stage++) {
                 const int nmod = stage == 0 ? P.NL : P.NL * SEG_LEAVES;
-                hipLaunchKernelGGL((k_sl_x<K>), dim3(gq), dim3(256), 0, st, b.ssk, b.soff, b.lseg, b.lcs, P.NL,
+                LAUNCH((k_sl_x<K>), dim3(gq), dim3(256), 0, st, b.ssk, b.soff, b.lseg, b.lcs, P.NL,
                                    b.models, stage, b.fx, b.fmid);
                 LAUNCH_OK();
-                hipLaunchKernelGGL(k_model_ranges, dim3((u32)cdiv((u64)nmod + 1, 256)), dim3(256), 0, st, b.fmid,
+                LAUNCH(k_model_ranges, dim3((u32)cdiv((u64)nmod + 1, 256)), dim3(256), 0, st, b.fmid,
                                    (i64)P.nls, nmod, b.flo);
                 LAUNCH_OK();
-                hipLaunchKernelGGL(k_sl_centres, dim3(nmod), dim3(64), 0, st, b.fx, b.flo, nmod, b.models, stage);
+                LAUNCH(k_sl_centres, dim3(nmod), dim3(64), 0, st, b.fx, b.flo, nmod, b.models, stage);
                 LAUNCH_OK();
-                hipLaunchKernelGGL(k_sl_forward, dim3(gq), dim3(256), 0, st, b.fx, b.fmid, b.lcs, P.NL, b.models,
+                LAUNCH(k_sl_forward, dim3(gq), dim3(256), 0, st, b.fx, b.fmid, b.lcs, P.NL, b.models,
                                    stage, b.fr);
                 LAUNCH_OK();
-                hipLaunchKernelGGL(k_sl_backward, dim3(nmod), dim3(64), 0, st, b.fx, b.fr, b.flo, nmod, b.lcs,
+                LAUNCH(k_sl_backward, dim3(nmod), dim3(64), 0, st, b.fx, b.fr, b.flo, nmod, b.lcs,
                                    b.models, stage, b.fg, b.fhs);
                 LAUNCH_OK();
-                hipLaunchKernelGGL(k_sl_update, dim3((u32)cdiv(nmod, 256)), dim3(256), 0, st, b.fg, b.fhs, b.flo,
+                LAUNCH(k_sl_update, dim3((u32)cdiv(nmod, 256)), dim3(256), 0, st, b.fg, b.fhs, b.flo,
                                    nmod, b.lcs, b.models, stage);
                 LAUNCH_OK();
             }
-            hipLaunchKernelGGL((k_sl_rank<K>), dim3((u32)(P.lblk.size() / 2)), dim3(SL_NT), 0, st, b.B, b.seg,
+            LAUNCH((k_sl_rank<K>), dim3((u32)(P.lblk.size() / 2)), dim3(SL_NT), 0, st, b.B, b.seg,
                                b.btab, b.lblk, b.poff, b.coff, b.pk, b.pp, b.models, b.cntT, b.lst);
             LAUNCH_OK();
         }
@@ -1134,7 +1331,7 @@ bsps_status enqueue_segmented(const SegPlan& P, const SegBufs<K>& b, K* io, u32*
         const int G = (int)(P.gtab[q].size() / 2);
         {
             StageScope sc(ST_TABLES, st);
-            hipLaunchKernelGGL(k_seg_bucket_tables, dim3(G), dim3(256), 0, st, b.gtab[q], P.cls_R[q], b.seg, b.coff,
+            LAUNCH(k_seg_bucket_tables, dim3(G), dim3(256), 0, st, b.gtab[q], P.cls_R[q], b.seg, b.coff,
                                b.cntT, b.btab, kSampleStride, b.mw[q].run_start, b.mw[q].run_len, b.mw[q].out_base,
                                b.mw[q].sdesc);
             LAUNCH_OK();
@@ -1203,6 +1400,55 @@ std::string graph_key(const void* a, const void* b, const void* c, const int64_t
     return k;
 }
 
+// Dry run: the segmented plan's tables are consistent (every block inside its
+// segment and the key array, every group naming a merged segment and one of
+// its buckets, every learned-bucketing entry naming a block of a large
+// segment, the prefix tables matching the per-segment sizes).
+void seg_plan_check(const SegPlan& P, u32 T) {
+    auto bad = [&](const char* what, i64 a, i64 b) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "segmented plan: %s (%lld, %lld)", what, (long long)a, (long long)b);
+        t_dry->errors.push_back(buf);
+    };
+    const i64 NB = P.NB;
+    if ((i64)P.btab.size() < 4 * NB) bad("block table too short", (i64)P.btab.size(), NB);
+    for (int i = 0; i < P.nseg; i++) {
+        const u32* d = &P.seg[(size_t)SEGW * i];
+        const i64 st = d[0], n = d[1], p = d[2], s = d[3], b0 = d[4];
+        if (st + n > P.n) bad("segment past the end", i, st + n);
+        if (p < 1 || p > MAXR || s < 1) bad("segment p or s out of range", p, s);
+        if (b0 + p > NB) bad("segment blocks past the block table", i, b0 + p);
+        i64 cover = st;
+        for (i64 k = 0; k < p && b0 + k < NB; k++) {
+            const u32* bt = &P.btab[(size_t)4 * (b0 + k)];
+            if (bt[0] != cover || bt[1] > T || bt[2] != (u32)i) bad("block not contiguous inside its segment", i, k);
+            cover = (i64)bt[0] + bt[1];
+            if (bt[3] + bt[1] / kSampleStride > P.nbsmp) bad("block samples past the sample array", i, k);
+        }
+        if (cover != st + n) bad("blocks do not cover the segment", i, cover);
+        const bool merged = p >= 2;
+        if (P.soff[i + 1] - P.soff[i] != (merged ? (u32)(p * s) : 0u)) bad("sample prefix", i, P.soff[i + 1]);
+        if (P.poff[i + 1] - P.poff[i] != (merged ? (u32)(p - 1) : 0u)) bad("splitter prefix", i, P.poff[i + 1]);
+        if (P.coff[i + 1] - P.coff[i] != (merged ? (u32)((p + 1) * p) : 0u)) bad("count prefix", i, P.coff[i + 1]);
+        if (P.dtab[i] != (merged ? 0u : 1u)) bad("direct flag", i, P.dtab[i]);
+        if (merged && p * s > (i64)T) bad("segment sample larger than one tile", i, p * s);
+    }
+    for (size_t q = 0; q < P.gtab.size(); q++) {
+        for (size_t e = 0; e + 1 < P.gtab[q].size(); e += 2) {
+            const u32 sg = P.gtab[q][e], bk = P.gtab[q][e + 1];
+            if ((int)sg >= P.nseg) { bad("group of a missing segment", (i64)q, sg); continue; }
+            const i64 p = P.seg[(size_t)SEGW * sg + 2];
+            if (p < 2 || bk >= p || p > P.cls_R[q]) bad("group bucket out of range", sg, bk);
+        }
+    }
+    for (int j = 0; j < P.NL; j++) {
+        const u32 sg = P.lseg[j];
+        if ((int)sg >= P.nseg || !P.seg[(size_t)SEGW * sg + 5]) bad("learned entry of a segment not marked large", j, sg);
+    }
+    for (size_t e = 0; e + 1 < P.lblk.size() && P.NL > 0; e += 2)
+        if ((i64)P.lblk[e] >= NB || (i64)P.lblk[e + 1] >= P.NL) bad("learned block entry out of range", (i64)P.lblk[e], P.lblk[e + 1]);
+}
+
 template <typename K, bool HASV>
 bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, int dt, const Tuning& tu, void* ws,
                           size_t ws_bytes, hipStream_t st, bsps_stats* stats) {
@@ -1217,6 +1463,14 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
     const size_t need = carve_seg<K>(c, P, HASV, b, o.tavg);
     if (!ws_ok(ws) || ws_bytes < need) return BSPS_EWORKSPACE;
     if (P.NB == 0) return BSPS_OK;
+    if (t_dry) {
+        // the plan's host tables index inside their arrays, the upload fits
+        // the workspace, and then every launch of the eager enqueue is checked
+        seg_plan_check(P, tileT<K>());
+        t_dry->kernel = "segment table upload";
+        t_dry->span("tables", b.tables, b.tables_bytes);
+        return enqueue_segmented<K, HASV>(P, b, (K*)keys, vals, dt, o, st);
+    }
     // tables -> workspace (pinned host staging in carve order, asynchronous)
     {
         char* stage = nullptr;
@@ -1237,13 +1491,14 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
     // capture every launch into one graph (on a private stream), launch it once
     (void)device_cus();  // device queries stay outside the graph capture
     const bool timed = g_timer.on;
-    bool launched = false;
+    bool launched = false, cached = false;
     if (!timed && getenv("BSPS_NO_GRAPH") == nullptr) {
         const std::string key = graph_key(keys, vals, ws, off, nseg, dt, HASV, tu);
         auto it = g_graphs.execs.find(key);
         hipGraphExec_t exec = nullptr;
         if (it != g_graphs.execs.end()) {
             exec = it->second;
+            cached = true;
         } else {
             if (!g_graphs.cap && hipStreamCreateWithFlags(&g_graphs.cap, hipStreamNonBlocking) != hipSuccess)
                 g_graphs.cap = nullptr;
@@ -1287,10 +1542,18 @@ bsps_status run_segmented(void* keys, u32* vals, const int64_t* off, int nseg, i
         stats->oversize_chunks = over;
         stats->reserved_i[0] = P.NB;
         stats->reserved_i[1] = P.nmerged;
-        stats->reserved_i[2] = launched ? 1 : 0;
+        stats->reserved_i[2] = launched ? (cached ? 2 : 1) : 0;
         stats->reserved_i[3] = P.NL;
         stats->mispredict_rate = 0.0;
         stats->mean_fix_dist = 0.0;
+        if (P.NL > 0 && stats->seg_capacity >= P.NL) {
+            rc = d2h(stats->seg_models, b.models, (size_t)P.NL * SEG_MODEL_BYTES, st);
+            if (rc) return rc;
+            rc = d2h(stats->seg_grad, b.fg, sizeof(float) * 2 * (size_t)P.NL * SEG_LEAVES, st);
+            if (rc) return rc;
+            rc = d2h(stats->seg_gram, b.fhs, sizeof(float) * 3 * (size_t)P.NL * SEG_LEAVES, st);
+            if (rc) return rc;
+        }
         if (P.NL > 0) {
             unsigned long long ls[2];
             rc = d2h(ls, b.lst, 16, st);
@@ -1393,10 +1656,10 @@ bsps_status bsps_rank(const void* keys, int64_t n, int32_t dtype, int32_t p, con
     if (n == 0) return BSPS_OK;
     hipStream_t s = (hipStream_t)stream;
     unsigned long long* lst = (unsigned long long*)ws;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, (u32*)ws, 4);
+    LAUNCH(k_zero_u32, dim3(1), dim3(64), 0, s, (u32*)ws, 4);
     LAUNCH_OK();
     if (out_counts) {
-        hipLaunchKernelGGL(k_zero_u32, dim3((u32)cdiv((u64)p * p, 256)), dim3(256), 0, s, out_counts, p * p);
+        LAUNCH(k_zero_u32, dim3((u32)cdiv((u64)p * p, 256)), dim3(256), 0, s, out_counts, p * p);
         LAUNCH_OK();
     }
     {
@@ -1454,20 +1717,20 @@ bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int3
     const u32 gN = (u32)std::max<u64>(1, cdiv((u64)N, 256));
     const u32 gM = (u32)cdiv((u64)leaves + 1, 256);
     if (dtype == BSPS_I64)
-        hipLaunchKernelGGL((k_model_x<u64>), dim3(gN), dim3(256), 0, st, (const u64*)smp_keys, N, dtype, model, 1,
+        LAUNCH((k_model_x<u64>), dim3(gN), dim3(256), 0, st, (const u64*)smp_keys, N, dtype, model, 1,
                            f.x, out_leaf);
     else
-        hipLaunchKernelGGL((k_model_x<u32>), dim3(gN), dim3(256), 0, st, (const u32*)smp_keys, N, dtype, model, 1,
+        LAUNCH((k_model_x<u32>), dim3(gN), dim3(256), 0, st, (const u32*)smp_keys, N, dtype, model, 1,
                            f.x, out_leaf);
     LAUNCH_OK();
-    hipLaunchKernelGGL(k_model_ranges, dim3(gM), dim3(256), 0, st, out_leaf, N, leaves, f.lo);
+    LAUNCH(k_model_ranges, dim3(gM), dim3(256), 0, st, out_leaf, N, leaves, f.lo);
     LAUNCH_OK();
-    hipLaunchKernelGGL(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, out_leaf, N, p, s, model, 1, f.r);
+    LAUNCH(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, out_leaf, N, p, s, model, 1, f.r);
     LAUNCH_OK();
-    hipLaunchKernelGGL(k_model_backward<64>, dim3(leaves), dim3(64), 0, st, f.x, f.r, f.lo, leaves, N, model, 1,
+    LAUNCH(k_model_backward<64>, dim3(leaves), dim3(64), 0, st, f.x, f.r, f.lo, leaves, N, model, 1,
                        out_grad, out_gram, f.lossp);
     LAUNCH_OK();
-    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, st, f.lossp, leaves, N, out_loss);
+    LAUNCH(k_sum_loss, dim3(1), dim3(256), 0, st, f.lossp, leaves, N, out_loss);
     LAUNCH_OK();
     return BSPS_OK;
 }
@@ -1524,10 +1787,75 @@ bsps_status bsps_stream_copy(const void* src, void* dst, size_t bytes, void* str
     const u64 n16 = bytes / 16;
     const u64 grid = cdiv(n16, (u64)COPY_NT * COPY_PER);
     if (grid > 0x7fffffffull) return BSPS_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_stream_copy, dim3((u32)grid), dim3(COPY_NT), 0, (hipStream_t)stream, (const v4u32*)src,
+    LAUNCH(k_stream_copy, dim3((u32)grid), dim3(COPY_NT), 0, (hipStream_t)stream, (const v4u32*)src,
                        (v4u32*)dst, n16);
     LAUNCH_OK();
     return BSPS_OK;
+}
+
+// Dry runs: report the checks' findings into `report` (HOST, may be NULL).
+static int64_t dry_finish(DryRun& d, bsps_status rc, char* report, size_t report_len) {
+    t_dry = nullptr;
+    if (rc != BSPS_OK) return -(int64_t)rc;
+    if (report && report_len) {
+        std::string r;
+        for (auto& e : d.errors) r += e + "\n";
+        if (d.errors.empty()) r = "ok: " + std::to_string(d.launches) + " launches checked\n";
+        std::snprintf(report, report_len, "%s", r.c_str());
+    }
+    return (int64_t)d.errors.size();
+}
+
+static void* const kFakeKeys = (void*)(uintptr_t)0x100000000000ull;
+static void* const kFakeVals = (void*)(uintptr_t)0x200000000000ull;
+static void* const kFakeWs = (void*)(uintptr_t)0x300000000000ull;
+
+int64_t bsps_check_sort(int64_t n, int32_t dtype, int32_t with_values, const bsps_params* prm, char* report,
+                        size_t report_len) {
+    bsps_status rc = validate(n, dtype, prm);
+    if (rc) return -(int64_t)rc;
+    DryRun d;
+    if (n <= 1) return dry_finish(d, BSPS_OK, report, report_len);
+    const size_t ws_bytes = bsps_workspace_bytes(n, dtype, with_values, prm);
+    d.add(kFakeKeys, (size_t)n * key_bytes(dtype));
+    if (with_values) d.add(kFakeVals, (size_t)n * 4);
+    d.add(kFakeWs, ws_bytes);
+    u32* vals = with_values ? (u32*)kFakeVals : nullptr;
+    t_dry = &d;
+    if (dtype == BSPS_I64)
+        rc = with_values ? run_sort<u64, true>(kFakeKeys, vals, n, dtype, prm, kFakeWs, ws_bytes, nullptr, nullptr)
+                         : run_sort<u64, false>(kFakeKeys, vals, n, dtype, prm, kFakeWs, ws_bytes, nullptr, nullptr);
+    else
+        rc = with_values ? run_sort<u32, true>(kFakeKeys, vals, n, dtype, prm, kFakeWs, ws_bytes, nullptr, nullptr)
+                         : run_sort<u32, false>(kFakeKeys, vals, n, dtype, prm, kFakeWs, ws_bytes, nullptr, nullptr);
+    return dry_finish(d, rc, report, report_len);
+}
+
+int64_t bsps_check_segmented(const int64_t* h_offsets, int32_t nseg, int32_t dtype, int32_t with_values,
+                             const char* tuning_json, char* report, size_t report_len) {
+    Tuning tu;
+    bsps_status rc = validate_segments(h_offsets, nseg, dtype, tuning_json, tu);
+    if (rc) return -(int64_t)rc;
+    DryRun d;
+    if (nseg == 0 || h_offsets[nseg] == 0) return dry_finish(d, BSPS_OK, report, report_len);
+    const i64 n = h_offsets[nseg];
+    const size_t ws_bytes = bsps_segmented_workspace_bytes(h_offsets, nseg, dtype, with_values, tuning_json);
+    d.add(kFakeKeys, (size_t)n * key_bytes(dtype));
+    if (with_values) d.add(kFakeVals, (size_t)n * 4);
+    d.add(kFakeWs, ws_bytes);
+    u32* vals = with_values ? (u32*)kFakeVals : nullptr;
+    t_dry = &d;
+    if (dtype == BSPS_I64)
+        rc = with_values ? run_segmented<u64, true>(kFakeKeys, vals, h_offsets, nseg, dtype, tu, kFakeWs, ws_bytes,
+                                                    nullptr, nullptr)
+                         : run_segmented<u64, false>(kFakeKeys, vals, h_offsets, nseg, dtype, tu, kFakeWs, ws_bytes,
+                                                     nullptr, nullptr);
+    else
+        rc = with_values ? run_segmented<u32, true>(kFakeKeys, vals, h_offsets, nseg, dtype, tu, kFakeWs, ws_bytes,
+                                                    nullptr, nullptr)
+                         : run_segmented<u32, false>(kFakeKeys, vals, h_offsets, nseg, dtype, tu, kFakeWs, ws_bytes,
+                                                     nullptr, nullptr);
+    return dry_finish(d, rc, report, report_len);
 }
 
 void bsps_release_cache(void) {

@@ -360,18 +360,19 @@ __device__ __forceinline__ void radix_rank4(DF digf, u32 (&rank)[IT], u64* ws) {
 #ifndef BSPS_SMALLPASS
 #define BSPS_SMALLPASS 1
 #endif
+// sh0: the sort key is bits [sh0, sh0 + nbits) of sk (0: the low nbits).
 template <int NT, int IT, typename SK, bool HASV, bool SMALLPASS = (bool)BSPS_SMALLPASS, bool SEP = false>
 __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&rank)[IT], int nbits, SK* exch,
-                                             u32* cnt, u32* wsum) {
+                                             u32* cnt, u32* wsum, int sh0 = 0) {
     const int t = threadIdx.x;
     u32* vex = reinterpret_cast<u32*>(exch);
     // all sort keys equal (nbits = 0): one pass over the all-zero digit, which
     // ranks every item at its own position
     const int npass = nbits <= 0 ? 1 : (nbits + RB - 1) / RB;
     for (int pass = 0; pass < npass; pass++) {
-        const int sh = pass * RB;
+        const int sh = sh0 + pass * RB;
         const bool last = pass == npass - 1;
-        if (SMALLPASS && nbits - sh <= 2) {
+        if (SMALLPASS && nbits - pass * RB <= 2) {
             // a last pass of at most 2 bits (or all keys equal)
             radix_rank4<NT, IT, SEP>([&](int j) { return (u32)(sk[j] >> sh) & 3u; }, rank,
                                      reinterpret_cast<u64*>(cnt));

@@ -387,3 +387,119 @@ __global__ __launch_bounds__(RankShape<LEARNED>::NT) void k_rank(const K* B, i64
         }
     }
 }
+
+// Routing with per-key ranking (the scatter route, Figure SortD steps 9-11):
+// every key of the block-sorted array B is given its bucket, by the branch-free
+// splitter search or by the learned model with the exact check, and is copied
+// to its run's destination, order kept. The run boundaries inside each sorted
+// block come from the splitter searches into the blocks (cntT), so the keys
+// are read once, by this kernel. Each workgroup takes a share of one block and
+// holds the block's run starts (rs) and destinations (od) in LDS with the
+// splitters (and the leaf table): key at block position c of bucket b goes to
+// od[b] + (c - rs[b]). The loads of RG keys are issued before they are ranked.
+template <typename K, bool LEARNED, bool HASV>
+__global__ __launch_bounds__(RankShape<LEARNED>::NT) void k_scatter_rank(
+    const K* B, const u32* Bv, i64 n, int p, int wpb, const K* spk, const u32* spp, const void* model,
+    const u32* cntT, const u32* off, K* Z, u32* Zv, u32* bucket, unsigned long long* lstats) {
+    constexpr int NT = RankShape<LEARNED>::NT;
+    constexpr int RG = sizeof(K) == 8 ? 4 : 8;
+    __shared__ SplitLds<K> S;
+    __shared__ u32 rs[MAXR], od[MAXR];
+    __shared__ float2 lf2[LEARNED ? MAX_LEAVES : 1];
+    __shared__ unsigned long long wst[2];
+    const int t = threadIdx.x;
+    const int k = blockIdx.x / wpb, w = blockIdx.x % wpb;
+    int P2 = 1;
+    while (P2 < p) P2 <<= 1;
+    for (int i = t; i < P2; i += NT) {
+        if (i < p - 1) S.set(i, spk[i], spp[i]);
+        else S.set_inf(i);
+        if (i < p) {
+            rs[i] = cntT[(i64)i * p + k];
+            od[i] = off[(i64)k * p + i];
+        }
+    }
+    if (t == 0) wst[0] = wst[1] = 0;
+    ModelHdr mh;
+    if (LEARNED) {
+        mh = *(const ModelHdr*)model;
+        mh.L = mh.L < 1 ? 1 : (mh.L > MAX_LEAVES ? MAX_LEAVES : mh.L);  // leaf ids stay inside the table
+        const float* lf = (const float*)((const ModelHdr*)model + 1);
+        for (int l = t; l < mh.L; l += NT) {
+            const float c = lf[3 * l], d = lf[3 * l + 1], mu = lf[3 * l + 2];
+            lf2[l] = make_float2(c, d - c * mu);
+        }
+    }
+    __syncthreads();
+    const i64 st = (i64)(((u64)k * (u64)n) / (u64)p), m = (i64)(((u64)(k + 1) * (u64)n) / (u64)p) - st;
+    const i64 lo = m * w / wpb, hi = m * (w + 1) / wpb;
+    unsigned long long miss = 0, dist = 0;
+    for (i64 c0 = lo; c0 < hi; c0 += (i64)NT * RG) {
+        K kg[RG];
+        u32 vg[RG];
+#pragma unroll
+        for (int u = 0; u < RG; u++) {
+            const i64 c = c0 + (i64)u * NT + t;
+            kg[u] = c < hi ? B[st + c] : (K)0;
+            vg[u] = (HASV && c < hi) ? Bv[st + c] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < RG; u++) {
+            const i64 c = c0 + (i64)u * NT + t;
+            if (c >= hi) continue;
+            const K key = kg[u];
+            const typename SplitLds<K>::Q q = SplitLds<K>::query(key, (u32)(st + c));
+            int b;
+            if (!LEARNED) {
+                b = 0;
+                for (int h = P2 >> 1; h >= 1; h >>= 1) b += S.lt(b + h - 1, q) ? h : 0;
+            } else {
+                const float x = model_x<K>(key, mh);
+                const float2 ce = lf2[model_leaf(x, mh)];
+                const float f = fminf(fmaxf((ce.x * x + ce.y) * (float)p, 0.0f), (float)(p - 1));
+                const int pred = (int)f;
+                b = pred;
+                while (b > 0 && !S.lt(b - 1, q)) b--;
+                while (b < p - 1 && S.lt(b, q)) b++;
+                miss += b != pred;
+                dist += (unsigned long long)(b > pred ? b - pred : pred - b);
+            }
+            const u32 dst = od[b] + ((u32)c - rs[b]);
+            Z[dst] = key;
+            if (HASV) Zv[dst] = vg[u];
+            if (bucket) bucket[st + c] = (u32)b;
+        }
+    }
+    if (LEARNED) {
+        atomicAdd(&wst[0], miss);
+        atomicAdd(&wst[1], dist);
+        __syncthreads();
+        if (t == 0 && lstats) {
+            atomicAdd(&lstats[0], wst[0]);
+            atomicAdd(&lstats[1], wst[1]);
+        }
+    }
+}
+
+// Routing offsets from the bucket boundaries of every sorted block (cntT, row
+// i = keys of each block below bucket i): bucket i starts after all smaller
+// buckets, and within it the keys of block k follow those of blocks 0..k-1:
+// off[k*p + i]. One workgroup per bucket.
+__global__ __launch_bounds__(256) void k_route_offsets_T(const u32* cntT, int p, u32* off) {
+    __shared__ u32 wsum[8];
+    const int i = blockIdx.x, t = threadIdx.x;
+    const int per = (p + 255) / 256;
+    u32 loc = 0, lb = 0;
+    for (int k = t * per; k < (t + 1) * per && k < p; k++) {
+        loc += cntT[(i64)(i + 1) * p + k] - cntT[(i64)i * p + k];
+        lb += cntT[(i64)i * p + k];
+    }
+    u32 tot, base;
+    u32 ex = block_excl_scan<256>(loc, tot, wsum);
+    __syncthreads();
+    (void)block_excl_scan<256>(lb, base, wsum);
+    for (int k = t * per; k < (t + 1) * per && k < p; k++) {
+        off[(i64)k * p + i] = base + ex;
+        ex += cntT[(i64)(i + 1) * p + k] - cntT[(i64)i * p + k];
+    }
+}

@@ -117,3 +117,52 @@ def test_stream_copy_checked_before_device(bsps):
     assert f(ct.c_void_p(4096), ct.c_void_p(8192 + 8), 4096, None) == bsps.EINVAL  # destination misaligned
     assert f(None, ct.c_void_p(8192), 4096, None) == bsps.EINVAL
     assert f(ct.c_void_p(4096), ct.c_void_p(8192), 0, None) == bsps.OK  # nothing to copy, no device call
+
+
+# ----------------------------------------------------------------- host dry runs of the plans
+
+@pytest.mark.parametrize("dtype", [0, 1, 2])
+@pytest.mark.parametrize("kv", [False, True])
+@pytest.mark.parametrize("route,bucketing", [(0, 0), (1, 0), (1, 1)])
+@pytest.mark.parametrize("local_sort", [0, 1, 2])
+def test_dry_run_sort_plans(bsps, dtype, kv, route, bucketing, local_sort):
+    """Every kernel launch of the sort, planned with fake buffers and checked
+    on the host: pointers inside the caller's buffers or the workspace, tables
+    inside at their full extent, grids non-empty. Sizes from the workloads
+    (2^28 keys, p up to 1024) down to ragged small ones, both variants."""
+    cases = [(1 << 28, 256, 64), (1 << 28, 1024, 64), (1 << 20, 16, 8), (5_000_003, 61, 8), (123457, 7, 3),
+             (2 * 16384 + 1, 2, 8), (1000, 1000, 1), (3, 1, 1)]
+    for n, p, s in cases:
+        for variant in (0, 1):
+            if variant == 1 and s * p - 1 > n:
+                continue
+            prm = bsps.make_params(p, s, variant, 1, bucketing, route, 0, 0, local_sort)
+            k, rep = bsps.check_sort(n, dtype, kv, prm)
+            assert k == 0, (n, p, s, variant, rep)
+
+
+@pytest.mark.parametrize("dtype", [0, 1, 2])
+@pytest.mark.parametrize("kv", [False, True])
+def test_dry_run_segmented_plans(bsps, dtype, kv):
+    """The segmented planner: the 4096-segment batch, edge segments and the
+    learned path on and off, all launches and host tables checked."""
+    import json
+    import numpy as np
+    import workloads as W
+    sizes = W.segment_sizes(4096, 8, 20)
+    batches = [sizes, np.array([0, 1, 2, 16383, 16384, 16385, 70000, 0, 3 << 16]), np.array([5])]
+    for lg in (16, 40):
+        tj = json.dumps({"learned_above_log2": lg, "classes": [{"max_log2": 14, "block": 16384, "s": 1},
+                                                               {"max_log2": 20, "block": 4096, "s": 16},
+                                                               {"max_log2": 40, "block": 16384, "s": 8}]})
+        for sz in batches:
+            off = np.zeros(len(sz) + 1, dtype=np.int64)
+            np.cumsum(sz, out=off[1:])
+            k, rep = bsps.check_segmented(off, dtype, kv, tj)
+            assert k == 0, rep
+
+
+def test_dry_run_rejects_like_the_call(bsps):
+    prm = bsps.make_params(0, 1)
+    assert bsps.check_sort(10, 0, False, prm)[0] == -bsps.EINVAL
+    assert bsps.check_segmented([0, 5, 3], 0, False)[0] == -bsps.EINVAL

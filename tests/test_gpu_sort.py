@@ -26,12 +26,13 @@ def _torch_keys(keys, dev):
     return torch.from_numpy(np.ascontiguousarray(keys)).to(dev)
 
 
-def _run(dev, keys, p, s, variant, seed=1, values=None, chunk_cap=0):
+def _run(dev, keys, p, s, variant, seed=1, values=None, chunk_cap=0, local_sort=0):
     import torch
     import paper_1408_6729_amd as bsps
     t = _torch_keys(keys, dev)
     v = None if values is None else torch.from_numpy(values.view(np.int32)).to(dev)
-    st = bsps.sort_(t, p, s, variant, seed, values=v, chunk_cap=chunk_cap, stats=True, stats_arrays=True)
+    st = bsps.sort_(t, p, s, variant, seed, values=v, chunk_cap=chunk_cap, stats=True, stats_arrays=True,
+                    local_sort=local_sort)
     torch.cuda.synchronize()
     out = t.cpu().numpy()
     outv = None if v is None else v.cpu().numpy().view(np.uint32)
@@ -42,10 +43,10 @@ def _bits(a):
     return a.view(np.uint32) if a.dtype == np.float32 else a
 
 
-def _check(ora, dev, keys, p, s, variant, seed=1, kv=False, chunk_cap=0, check_B=True):
+def _check(ora, dev, keys, p, s, variant, seed=1, kv=False, chunk_cap=0, check_B=True, local_sort=0):
     vals = np.arange(keys.size, dtype=np.uint32) if kv else None
     ref = ora.sort(keys, p, s, variant, seed, vals)
-    out, outv, st = _run(dev, keys, p, s, variant, seed, vals, chunk_cap)
+    out, outv, st = _run(dev, keys, p, s, variant, seed, vals, chunk_cap, local_sort)
     assert np.array_equal(_bits(out), _bits(ref["keys"])), "sorted keys differ"
     if kv:
         assert np.array_equal(outv, ref["values"]), "payload order differs"
@@ -186,3 +187,59 @@ def test_stream_copy_exact(dev):
         bsps.stream_copy(src, dst)
         torch.cuda.synchronize()
         assert torch.equal(src, dst), n
+
+
+# ----------------------------------------------------------------- the two local sorts
+
+LOCAL = [1, 2]  # tiles + multiway merge, LSD radix passes through HBM
+
+
+@pytest.mark.parametrize("local_sort", LOCAL)
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("kv", [False, True])
+def test_local_sorts_multi_tile_blocks(ora, dev, local_sort, dtype, kv):
+    """Blocks of several tiles, ragged sizes (n not a multiple of p, block
+    starts not 16-byte aligned, partial last tiles), many equal keys: the
+    block-sorted array, sample, splitters, count matrix and output equal the
+    oracle's with either local sort."""
+    n = 7 * 16384 + 12345
+    keys = W.random_keys(n, dtype, seed=31, distinct=3000)
+    _check(ora, dev, keys, 3, 16, ora.DET, kv=kv, local_sort=local_sort)
+    keys = W.random_keys(n, dtype, seed=32)
+    _check(ora, dev, keys, 5, 8, ora.RAN, seed=4, kv=kv, local_sort=local_sort)
+
+
+@pytest.mark.parametrize("dist", W.DISTRIBUTIONS)
+def test_lsd_distributions(ora, dev, dist):
+    """The seven distributions at 2^22 keys, p = 128 (two tiles per block),
+    through the LSD local sort: positions where a block's keys share a digit
+    are skipped (all-zero keys: one copying pass), so blocks run different
+    numbers of passes."""
+    keys = W.int32_keys(1 << 22, 128, dist)
+    for variant in (0, 1):
+        _check(ora, dev, keys, 128, 32, variant, local_sort=2)
+
+
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("span_bits", [0, 1, 8, 9, 20])
+def test_lsd_digit_positions(ora, dev, dtype, span_bits):
+    """Keys spanning 2^span_bits consecutive order-key values, key-value,
+    through the LSD local sort: 0 to 3 digit positions differ inside a block."""
+    rng = np.random.default_rng(span_bits + 100)
+    n = 4 * 16384 + 999
+    off = rng.integers(0, 1 << span_bits, size=n) if span_bits else np.zeros(n, dtype=np.int64)
+    if dtype == "int32":
+        keys = (np.int64(-(1 << 24)) + off).astype(np.int32)
+    elif dtype == "int64":
+        keys = (np.int64(1 << 44) + off).astype(np.int64)
+    else:
+        keys = (np.uint32(0x3f800000) + off.astype(np.uint32)).view(np.float32)
+    _check(ora, dev, keys, 2, 4, ora.DET, kv=True, local_sort=2)
+
+
+def test_lsd_many_blocks(ora, dev):
+    """More blocks than resident workgroups (each workgroup walks several
+    blocks), one tile per block plus a few keys."""
+    n = 1100 * 16390
+    keys = W.random_keys(n, "int32", seed=77, distinct=n // 2)
+    _check(ora, dev, keys, 1024, 8, ora.DET, local_sort=2)

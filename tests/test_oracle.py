@@ -482,3 +482,44 @@ def test_threaded_driver_is_byte_identical(ora, dtype, variant, p, s, n):
         b = ora.sort(keys, p, s, variant, 3, vals, threads=threads)
         for k in ("perm", "B_perm", "sample_key", "sample_pos", "spl_key", "spl_pos", "C", "Z_perm"):
             assert np.array_equal(a[k], b[k]), (k, threads)
+
+
+# ----------------------------------------------------------------- duplicate handling switched off
+
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_untagged_still_sorts_stably(ora, dtype, variant):
+    """Without tags the buckets may be uneven, but routing and the stable merge
+    still give the stable sort."""
+    for seed, distinct in ((1, None), (2, 7), (3, 300)):
+        keys = W.random_keys(20011, dtype, seed=seed, distinct=distinct)
+        r = ora.sort(keys, 13, 5, variant, 3, untagged=True)
+        assert np.array_equal(r["perm"], _stable_ref(keys))
+
+
+def test_untagged_buckets_by_key_alone(ora):
+    """Bucket of a key = number of splitter keys strictly below it (the
+    definition, counted directly); for distinct keys the count matrix equals
+    the tagged one; all-equal keys all fall in bucket 0 (closed form, where the
+    tagged method gives the diagonal)."""
+    keys = W.random_keys(5003, "int32", seed=4, distinct=40)
+    p, s = 9, 4
+    r = ora.sort(keys, p, s, ora.DET, untagged=True)
+    spl = r["spl_key"].astype(np.uint64)
+    okB = ora.order_keys(r["B_keys"])
+    C = np.zeros((p, p), dtype=np.int64)
+    for k in range(p):
+        a, b = ora.block_start(keys.size, p, k), ora.block_start(keys.size, p, k + 1)
+        for u in okB[a:b]:
+            C[k, int((spl < u).sum())] += 1
+    assert np.array_equal(r["C"], C)
+    distinct = W.random_keys(5003, "int32", seed=5)
+    assert np.unique(distinct).size == distinct.size
+    t, u = ora.sort(distinct, p, s, ora.RAN), ora.sort(distinct, p, s, ora.RAN, untagged=True)
+    assert np.array_equal(t["C"], u["C"]) and np.array_equal(t["spl_pos"], u["spl_pos"])
+    zero = np.zeros(1000, dtype=np.int32)
+    z = ora.sort(zero, 8, 3, ora.DET, untagged=True)
+    m = [ora.block_start(1000, 8, k + 1) - ora.block_start(1000, 8, k) for k in range(8)]
+    want = np.zeros((8, 8), dtype=np.int64)
+    want[:, 0] = m
+    assert np.array_equal(z["C"], want)
