@@ -65,6 +65,8 @@ def lib():
                                ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.ora_sort_mt.argtypes = L.ora_sort.argtypes + [ct.c_int]
         L.ora_sort_untagged.argtypes = L.ora_sort.argtypes
+        L.ora_sort_sr.argtypes = [u64p, ct.c_int64, ct.c_int, ct.c_int, ct.c_uint64, i64p, ct.c_void_p,
+                                  ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.ora_rank.argtypes = [u64p, ct.c_int64, u64p, i64p, ct.c_int, i64p]
         L.ora_rmi_grad.restype = ct.c_double
         L.ora_rmi_grad.argtypes = [f64p, f64p, i32p, ct.c_int64, ct.c_int, f64p, f64p, f64p, f64p, f64p]
@@ -186,6 +188,37 @@ def sort(keys: np.ndarray, p: int, s: int, variant: int = DET, seed: int = 1,
         res["bucket_sizes"] = res["C"].sum(axis=0)
         res["Z_perm"] = Z
         res["Z_keys"] = keys[Z]
+    return res
+
+
+def sort_sr(keys: np.ndarray, p: int, s: int, seed: int = 1, values: np.ndarray | None = None) -> dict:
+    """Sort_Ran_BSP (Figure SortR): sample of the unsorted input, route, then
+    sort every bucket. Returns keys, values (if given), perm, sample_key /
+    sample_pos (sorted sample, order keys and INPUT positions), spl_key /
+    spl_pos, C (p x p, row = input block), bucket_sizes, Z_perm (routed)."""
+    keys = np.ascontiguousarray(keys)
+    n = keys.size
+    ok = order_keys(keys)
+    if validate(n, p, s, RAN):
+        raise OracleError(f"invalid arguments n={n} p={p} s={s}")
+    ns = max(s * p - 1, 1)
+    perm = np.empty(max(n, 1), dtype=np.int64)
+    sk = np.empty(ns, dtype=np.uint64)
+    sp = np.empty(ns, dtype=np.int64)
+    pk = np.empty(max(p - 1, 1), dtype=np.uint64)
+    pp = np.empty(max(p - 1, 1), dtype=np.int64)
+    C = np.zeros(p * p, dtype=np.int64)
+    Z = np.empty(max(n, 1), dtype=np.int64)
+    rc = lib().ora_sort_sr(ok, n, p, s, seed & 0xFFFFFFFFFFFFFFFF, perm, sk.ctypes.data, sp.ctypes.data,
+                           pk.ctypes.data, pp.ctypes.data, C.ctypes.data, Z.ctypes.data)
+    if rc:
+        raise OracleError(f"oracle failed rc={rc}")
+    perm, Z = perm[:n], Z[:n]
+    res = {"perm": perm, "keys": keys[perm], "sample_key": sk[:s * p - 1], "sample_pos": sp[:s * p - 1],
+           "spl_key": pk[:p - 1], "spl_pos": pp[:p - 1], "C": C.reshape(p, p), "Z_perm": Z, "Z_keys": keys[Z]}
+    res["bucket_sizes"] = res["C"].sum(axis=0)
+    if values is not None:
+        res["values"] = np.ascontiguousarray(values)[perm]
     return res
 
 

@@ -473,6 +473,118 @@ int ora_sort_untagged(const uint64_t* ok, int64_t n, int p, int s, int variant, 
                            C_out, Z_idx_out, 1, each_sequential, NULL);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Sort_Ran_BSP (Figure SortR): sample, route, then sort locally             */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * ora_sort_sr: the sample-sort ordering of Section 5.2, Figure SortR, with the
+ * duplicate handling of Section 5.1.1, for p simulated processors holding
+ * the contiguous blocks of the UNSORTED input:
+ *   R1 (step 2)    a sample of s*p - 1 input positions drawn uniformly without
+ *                  replacement: the images of 0..s*p-2 under the keyed
+ *                  permutation of [0, n); each is the record (key, g) with g its
+ *                  input position, which orders like the tag (processor, local
+ *                  index) since there is no local sort before the sample.
+ *   R2 (steps 5-6) the sample sorted by (key, g); splitters at 1-based ranks
+ *                  s, 2s, ..., (p-1)s.
+ *   R3 (step 9)    the bucket of every input record: the number of splitters
+ *                  strictly below it; C[k][i] counts processor k's records of
+ *                  bucket i.
+ *   R4 (steps 10-11) routing, order preserving: bucket i gathers processor 0's
+ *                  records of bucket i in input order, then processor 1's, ...
+ *   R5 (step 12)   every processor sorts what it received, stably by key, so
+ *                  equal keys keep the routed order, which is input order.
+ * The output is therefore the stable sort of the input. Outputs as ora_sort
+ * (perm, sample records, splitters, C, Z_idx); the sample positions and
+ * Z_idx are input positions.
+ */
+int ora_sort_sr(const uint64_t* ok, int64_t n, int p, int s, uint64_t seed,
+                int64_t* perm, uint64_t* smp_key, int64_t* smp_pos,
+                uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* Z_idx_out) {
+    int rc = ora_validate(n, p, s, ORA_RAN);
+    if (rc) return rc;
+    if (n <= 1) {
+        if (n == 1) perm[0] = 0;
+        if (n == 1 && Z_idx_out) Z_idx_out[0] = 0;
+        if (C_out) C_out[0] = n;
+        return ORA_OK;
+    }
+    int64_t ns = (int64_t)s * p - 1;
+    rec_t* smp = (rec_t*)malloc(sizeof(rec_t) * (ns > 0 ? ns : 1));
+    rec_t* S = (rec_t*)malloc(sizeof(rec_t) * p);
+    int64_t* C = (int64_t*)calloc((size_t)p * p, sizeof(int64_t));
+    int64_t* off = (int64_t*)malloc(sizeof(int64_t) * p * p);
+    int64_t* bucket = (int64_t*)malloc(sizeof(int64_t) * n);
+    int64_t* Z_idx = (int64_t*)malloc(sizeof(int64_t) * n);
+    item_t* tmp = (item_t*)malloc(sizeof(item_t) * n);
+    if (!smp || !S || !C || !off || !bucket || !Z_idx || !tmp) { rc = ORA_ENOMEM; goto done_sr; }
+
+    /* R1, R2 */
+    for (int64_t t = 0; t < ns; t++) {
+        int64_t g = ora_feistel(seed, n, t);
+        smp[t].pos = g;
+        smp[t].key = ok[g];
+    }
+    qsort(smp, (size_t)ns, sizeof(rec_t), rec_cmp);
+    for (int64_t t = 0; t < ns; t++) {
+        if (smp_key) smp_key[t] = smp[t].key;
+        if (smp_pos) smp_pos[t] = smp[t].pos;
+    }
+    for (int i = 1; i < p; i++) {
+        S[i - 1] = smp[(int64_t)i * s - 1];
+        if (spl_key) spl_key[i - 1] = S[i - 1].key;
+        if (spl_pos) spl_pos[i - 1] = S[i - 1].pos;
+    }
+
+    /* R3 */
+    for (int k = 0; k < p; k++) {
+        int64_t a = ora_block_start(n, p, k), b = ora_block_start(n, p, k + 1);
+        for (int64_t g = a; g < b; g++) {
+            rec_t r = {ok[g], g};
+            bucket[g] = bucket_of(r, S, p - 1);
+            C[(int64_t)k * p + bucket[g]]++;
+        }
+    }
+    if (C_out) memcpy(C_out, C, sizeof(int64_t) * p * p);
+
+    /* R4: offsets as in Figure SortD step 9, then the order-preserving route */
+    {
+        int64_t base = 0;
+        for (int i = 0; i < p; i++) {
+            int64_t run = base;
+            for (int k = 0; k < p; k++) {
+                off[(int64_t)k * p + i] = run;
+                run += C[(int64_t)k * p + i];
+            }
+            base = run;
+        }
+        for (int k = 0; k < p; k++) {
+            int64_t a = ora_block_start(n, p, k), b = ora_block_start(n, p, k + 1);
+            for (int64_t g = a; g < b; g++) Z_idx[off[(int64_t)k * p + bucket[g]]++] = g;
+        }
+    }
+    if (Z_idx_out) memcpy(Z_idx_out, Z_idx, sizeof(int64_t) * n);
+
+    /* R5: bucket i now spans [base_i, base_i + size_i) of Z (off[k][i] has
+     * advanced to the end of processor k's run): sort it stably by key. */
+    {
+        int64_t lo = 0;
+        for (int i = 0; i < p; i++) {
+            int64_t hi = off[(int64_t)(p - 1) * p + i];
+            for (int64_t j = lo; j < hi; j++) { tmp[j - lo].key = ok[Z_idx[j]]; tmp[j - lo].idx = j; }
+            /* ties by routed position: the stable order */
+            qsort(tmp, (size_t)(hi - lo), sizeof(item_t), item_cmp);
+            for (int64_t j = lo; j < hi; j++) perm[j] = Z_idx[tmp[j - lo].idx];
+            lo = hi;
+        }
+    }
+
+done_sr:
+    free(smp); free(S); free(C); free(off); free(bucket); free(Z_idx); free(tmp);
+    return rc;
+}
+
 /* Bucket of each record (key, g) of a block-sorted array against given
  * splitters: the definition used by step O6, exported so that a per-key GPU
  * ranking can be compared against it. */

@@ -523,3 +523,60 @@ def test_untagged_buckets_by_key_alone(ora):
     want = np.zeros((8, 8), dtype=np.int64)
     want[:, 0] = m
     assert np.array_equal(z["C"], want)
+
+
+# ----------------------------------------------------------------- Sort_Ran_BSP (Figure SortR)
+
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+def test_sr_output_is_stable_sort(ora, dtype):
+    rng = np.random.default_rng(11)
+    for trial in range(5):
+        n = int(rng.integers(2, 40000))
+        p = int(rng.integers(1, min(n, 64) + 1))
+        s = max(1, min(int(rng.integers(1, 20)), (n + 1) // p))
+        keys = W.random_keys(n, dtype, seed=trial + 40, distinct=None if trial % 2 else 9)
+        r = ora.sort_sr(keys, p, s, seed=trial)
+        assert np.array_equal(r["perm"], _stable_ref(keys)), (n, p, s)
+
+
+def test_sr_exhaustive_tiny(ora):
+    for n in range(1, 7):
+        for keys in itertools.product(range(3), repeat=n):
+            k = np.array(keys, dtype=np.int32)
+            for p in range(1, n + 1):
+                for s in range(1, (n + 1) // p + 1):
+                    r = ora.sort_sr(k, p, s, seed=n)
+                    assert np.array_equal(r["perm"], _stable_ref(k))
+
+
+def test_sr_steps_by_definition(ora):
+    """The sample is the keyed permutation's image over INPUT positions, the
+    splitters are its records at ranks i*s - 1, the bucket of every input record
+    counts the splitters below it, and routing puts the records in (bucket,
+    input position) order; computed here directly from those definitions."""
+    keys = W.random_keys(3001, "int64", seed=3, distinct=60)
+    n, p, s, seed = keys.size, 7, 5, 9
+    r = ora.sort_sr(keys, p, s, seed=seed)
+    ok = [int(u) for u in ora.order_keys(keys)]
+    pos = [ora.feistel(seed, n, t) for t in range(s * p - 1)]
+    assert sorted(pos) == sorted(r["sample_pos"].tolist())
+    recs = sorted((ok[g], g) for g in pos)
+    assert [g for _, g in recs] == r["sample_pos"].tolist()
+    spl = [recs[i * s - 1] for i in range(1, p)]
+    assert [g for _, g in spl] == r["spl_pos"].tolist()
+    bucket = [sum(1 for sp in spl if sp < (ok[g], g)) for g in range(n)]
+    C = np.zeros((p, p), dtype=np.int64)
+    for g in range(n):
+        k = next(k for k in range(p) if ora.block_start(n, p, k) <= g < ora.block_start(n, p, k + 1))
+        C[k, bucket[g]] += 1
+    assert np.array_equal(r["C"], C)
+    assert r["Z_perm"].tolist() == sorted(range(n), key=lambda g: (bucket[g], g))
+
+
+def test_sr_all_equal_closed_form(ora):
+    """All keys equal: every record is compared by position alone, so bucket i
+    holds exactly the input positions between splitter tags i-1 and i."""
+    n, p, s = 10000, 16, 8
+    r = ora.sort_sr(np.zeros(n, dtype=np.int32), p, s, seed=5)
+    edges = np.concatenate([[-1], r["spl_pos"], [n - 1]])
+    assert np.array_equal(r["bucket_sizes"], np.diff(edges))
