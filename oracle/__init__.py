@@ -67,6 +67,10 @@ def lib():
         L.ora_sort_untagged.argtypes = L.ora_sort.argtypes
         L.ora_sort_sr.argtypes = [u64p, ct.c_int64, ct.c_int, ct.c_int, ct.c_uint64, i64p, ct.c_void_p,
                                   ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]
+        L.ora_iter_k.argtypes = [ct.c_int, ct.c_int]
+        L.ora_iter_k.restype = ct.c_int
+        L.ora_sort_iter.argtypes = [u64p, ct.c_int64, ct.c_int, ct.c_int, ct.c_int, i64p, ct.c_void_p,
+                                    ct.c_void_p, ct.c_void_p, ct.c_void_p]
         L.ora_rank.argtypes = [u64p, ct.c_int64, u64p, i64p, ct.c_int, i64p]
         L.ora_rmi_grad.restype = ct.c_double
         L.ora_rmi_grad.argtypes = [f64p, f64p, i32p, ct.c_int64, ct.c_int, f64p, f64p, f64p, f64p, f64p]
@@ -217,6 +221,45 @@ def sort_sr(keys: np.ndarray, p: int, s: int, seed: int = 1, values: np.ndarray 
     res = {"perm": perm, "keys": keys[perm], "sample_key": sk[:s * p - 1], "sample_pos": sp[:s * p - 1],
            "spl_key": pk[:p - 1], "spl_pos": pp[:p - 1], "C": C.reshape(p, p), "Z_perm": Z, "Z_keys": keys[Z]}
     res["bucket_sizes"] = res["C"].sum(axis=0)
+    if values is not None:
+        res["values"] = np.ascontiguousarray(values)[perm]
+    return res
+
+
+def iter_k(p: int, m: int) -> int:
+    """k with k^m = p (0 when p is not an m-th power)."""
+    return int(lib().ora_iter_k(p, m))
+
+
+def sort_iter(keys: np.ndarray, p: int, s: int, m: int, values: np.ndarray | None = None,
+              rounds: bool = False) -> dict:
+    """Iterative Sort_Det_BSP (Section 5.1): local sort, then m rounds of
+    k-way partitioning and merging, p = k^m. Returns keys, values (if
+    given), perm, k, spl_key / spl_pos (p-1: round 1's k-1 splitters, then
+    round 2's, group by group ...; order keys, positions in the round's input
+    array), C (m x p x k: round, processor, bucket); with
+    rounds=True also A_perm (m x n: original index of every element after
+    each round)."""
+    keys = np.ascontiguousarray(keys)
+    n = keys.size
+    ok = order_keys(keys)
+    k = iter_k(p, m)
+    if validate(n, p, s, DET) or k == 0:
+        raise OracleError(f"invalid arguments n={n} p={p} s={s} m={m}")
+    perm = np.empty(max(n, 1), dtype=np.int64)
+    pk = np.empty(max(p - 1, 1), dtype=np.uint64)
+    pp = np.empty(max(p - 1, 1), dtype=np.int64)
+    C = np.zeros(m * p * k, dtype=np.int64)
+    A = np.empty(max(m * n, 1), dtype=np.int64) if rounds else None
+    rc = lib().ora_sort_iter(ok, n, p, s, m, perm, pk.ctypes.data, pp.ctypes.data, C.ctypes.data,
+                             None if A is None else A.ctypes.data)
+    if rc:
+        raise OracleError(f"oracle failed rc={rc}")
+    perm = perm[:n]
+    res = {"perm": perm, "keys": keys[perm], "k": k, "spl_key": pk[:p - 1], "spl_pos": pp[:p - 1],
+           "C": C.reshape(m, p, k)}
+    if A is not None:
+        res["A_perm"] = A[:m * n].reshape(m, n)
     if values is not None:
         res["values"] = np.ascontiguousarray(values)[perm]
     return res

@@ -585,6 +585,203 @@ done_sr:
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Iterative Sort_Det_BSP: m rounds of partitioning and merging               */
+/* ------------------------------------------------------------------------ */
+
+/* k with k^m = p (k >= 2 unless p = 1), or 0 when p is not an m-th power. */
+int ora_iter_k(int p, int m) {
+    if (p < 1 || m < 1) return 0;
+    if (p == 1) return 1;
+    for (int k = 2; k <= p; k++) {
+        int64_t v = 1;
+        for (int r = 0; r < m && v <= p; r++) v *= k;
+        if (v == p) return k;
+        if (v > p) return 0;
+    }
+    return 0;
+}
+
+/*
+ * ora_sort_iter: the iterative version of Sort_Det_BSP (Section 5.1): the
+ * local sort, then m iterations of partitioning and merging; each iteration
+ * splits every current bucket into k further buckets, p = k^m processors,
+ * regular oversampling s. The paper describes the iteration in words only;
+ * this is the reading implemented here (m = 1 is exactly ora_sort, DET):
+ *   I0 (phase 1)  every processor sorts its block stably (as O2): array A;
+ *                 one group, the whole array, held by all p processors.
+ * Round r = 1..m, for every group g (its segment of A, z records, held by q
+ * processors; processor j owns the share [ora_block_start(z, q, j),
+ * ora_block_start(z, q, j + 1)) of the segment, sorted):
+ *   I1 (phase 2)  regular sample of each share, as O3 with the share length
+ *                 bound ceil(z/q). No share is ever empty: a record fills at
+ *                 most s sample slots (the clamped last position of its
+ *                 share), and a sub-bucket takes at least t - (s - 1) of the
+ *                 t sample ranks between its splitters (only copies of the
+ *                 lower splitter are lost), so it holds at least
+ *                 ceil((t - s + 1) / s) = q/k records, one per processor of
+ *                 the next round; round 1 has p <= n.
+ *   I2            the q*s sample records of the group sorted by (key, tag);
+ *                 k-1 splitters at the 1-based ranks t, 2t, ..., (k-1)t,
+ *                 t = q*s/k (for m = 1: t = s, as O5).
+ *   I3            every processor partitions its share by the splitters,
+ *                 ties decided by the tag (as O6), and counts.
+ *   I4            routing, order preserving (as O7-O8 inside the group):
+ *                 sub-bucket b gathers the processors' runs of bucket b in
+ *                 processor order; the sub-buckets follow each other in b
+ *                 order in the group's segment; sub-bucket b becomes group
+ *                 g*k + b, held by q/k processors.
+ *   I5 (phase 3)  every processor of a new group takes its even share of the
+ *                 routed sequence and merges the sorted pieces it holds, the
+ *                 earlier piece first on equal keys (a stable sort of the
+ *                 share, which is the same thing since the pieces are sorted).
+ * Tags are positions in the current array: every round keeps equal keys in
+ * input order, so they order exactly like the original (processor, index).
+ * Outputs (optional unless stated):
+ *   perm[j]                original index of output element j (required)
+ *   spl_key/spl_pos[p-1]   the splitters of round 1 (k-1), then of the k groups
+ *                          of round 2 (k-1 each, in group order), ...; pos is
+ *                          the position in the round's input array
+ *   C[m*p*k]               round r, processor (global number g*q + j), bucket b
+ *   A_idx[m*n]             original index of every element after round r
+ * Returns ORA_OK, ORA_EINVAL (arguments) or ORA_ENOMEM.
+ */
+int ora_sort_iter(const uint64_t* ok, int64_t n, int p, int s, int m, int64_t* perm,
+                  uint64_t* spl_key, int64_t* spl_pos, int64_t* C_out, int64_t* A_idx_out) {
+    int rc = ora_validate(n, p, s, ORA_DET);
+    if (rc) return rc;
+    const int k = ora_iter_k(p, m);
+    if (k == 0) return ORA_EINVAL;
+    if (n <= 1 || p == 1) {
+        /* one processor: its local sort is the output */
+        item_t* tmp = (item_t*)malloc(sizeof(item_t) * (size_t)(n > 0 ? n : 1));
+        if (!tmp) return ORA_ENOMEM;
+        for (int64_t g = 0; g < n; g++) { tmp[g].key = ok[g]; tmp[g].idx = g; }
+        qsort(tmp, (size_t)n, sizeof(item_t), item_cmp);
+        for (int64_t g = 0; g < n; g++) perm[g] = tmp[g].idx;
+        for (int r = 0; r < m && A_idx_out; r++) memcpy(A_idx_out + (int64_t)r * n, perm, sizeof(int64_t) * n);
+        if (C_out)
+            for (int r = 0; r < m; r++)
+                for (int64_t e = 0; e < (int64_t)p * k; e++) C_out[(int64_t)r * p * k + e] = e == 0 ? n : 0;
+        free(tmp);
+        return ORA_OK;
+    }
+    uint64_t* A_key = (uint64_t*)malloc(sizeof(uint64_t) * n);
+    int64_t* A_idx = (int64_t*)malloc(sizeof(int64_t) * n);
+    uint64_t* Z_key = (uint64_t*)malloc(sizeof(uint64_t) * n);
+    int64_t* Z_idx = (int64_t*)malloc(sizeof(int64_t) * n);
+    item_t* tmp = (item_t*)malloc(sizeof(item_t) * n);
+    int64_t* gst = (int64_t*)malloc(sizeof(int64_t) * ((size_t)p + 1));   /* group starts */
+    int64_t* ngst = (int64_t*)malloc(sizeof(int64_t) * ((size_t)p + 1));
+    rec_t* smp = (rec_t*)malloc(sizeof(rec_t) * (size_t)p * s);
+    rec_t* S = (rec_t*)malloc(sizeof(rec_t) * (size_t)k);
+    int64_t* C = (int64_t*)malloc(sizeof(int64_t) * (size_t)p * k);      /* one group: q x k */
+    int64_t* rs = (int64_t*)malloc(sizeof(int64_t) * (size_t)p * k);     /* run starts in Z */
+    if (!A_key || !A_idx || !Z_key || !Z_idx || !tmp || !gst || !ngst || !smp || !S || !C || !rs) {
+        rc = ORA_ENOMEM;
+        goto done_it;
+    }
+    /* I0: local sort of the p blocks */
+    for (int j = 0; j < p; j++) {
+        int64_t a = ora_block_start(n, p, j), b = ora_block_start(n, p, j + 1);
+        for (int64_t g = a; g < b; g++) { tmp[g - a].key = ok[g]; tmp[g - a].idx = g; }
+        qsort(tmp, (size_t)(b - a), sizeof(item_t), item_cmp);
+        for (int64_t g = a; g < b; g++) { A_key[g] = tmp[g - a].key; A_idx[g] = tmp[g - a].idx; }
+    }
+    int G = 1, q = p;
+    int64_t nspl = 0;
+    gst[0] = 0;
+    gst[1] = n;
+    for (int r = 0; r < m; r++) {
+        const int q2 = q / k;
+        for (int g = 0; g < G; g++) {
+            const int64_t gs = gst[g], z = gst[g + 1] - gs;
+            /* I1: regular sample of every share */
+            const int64_t xm = (z + q - 1) / q, x = (xm + s - 1) / s;
+            int64_t t = 0;
+            for (int j = 0; j < q; j++) {
+                const int64_t a = gs + ora_block_start(z, q, j), mj = ora_block_start(z, q, j + 1) - (a - gs);
+                if (mj == 0) { rc = ORA_EINVAL; goto done_it; }  /* cannot happen (I1) */
+                for (int64_t i = 1; i <= s; i++) {
+                    const int64_t qq = i * x < mj ? i * x : mj;
+                    smp[t].key = A_key[a + qq - 1];
+                    smp[t].pos = a + qq - 1;
+                    t++;
+                }
+            }
+            /* I2: sort, splitters */
+            qsort(smp, (size_t)t, sizeof(rec_t), rec_cmp);
+            const int64_t stride = (int64_t)q * s / k;
+            for (int i = 1; i < k; i++) {
+                S[i - 1] = smp[(int64_t)i * stride - 1];
+                if (spl_key) spl_key[nspl] = S[i - 1].key;
+                if (spl_pos) spl_pos[nspl] = S[i - 1].pos;
+                nspl++;
+            }
+            /* I3: partition every share, count */
+            memset(C, 0, sizeof(int64_t) * (size_t)q * k);
+            for (int j = 0; j < q; j++) {
+                const int64_t a = gs + ora_block_start(z, q, j), b = gs + ora_block_start(z, q, j + 1);
+                int64_t prev = 0;
+                for (int64_t x2 = a; x2 < b; x2++) {
+                    rec_t rr = {A_key[x2], x2};
+                    int64_t bk = bucket_of(rr, S, k - 1);
+                    if (bk < prev) { rc = ORA_EINVAL; goto done_it; }  /* cannot happen: shares are sorted */
+                    prev = bk;
+                    C[(int64_t)j * k + bk]++;
+                }
+            }
+            if (C_out)
+                for (int64_t e = 0; e < (int64_t)q * k; e++) C_out[(int64_t)r * p * k + (int64_t)g * q * k + e] = C[e];
+            /* I4: route, order preserving; sub-bucket b = new group g*k + b */
+            {
+                int64_t base = gs;
+                for (int b = 0; b < k; b++) {
+                    ngst[(int64_t)g * k + b] = base;
+                    for (int j = 0; j < q; j++) {
+                        rs[(int64_t)j * k + b] = base;
+                        base += C[(int64_t)j * k + b];
+                    }
+                }
+                for (int j = 0; j < q; j++) {
+                    const int64_t a = gs + ora_block_start(z, q, j), b = gs + ora_block_start(z, q, j + 1);
+                    for (int64_t x2 = a; x2 < b; x2++) {
+                        rec_t rr = {A_key[x2], x2};
+                        const int64_t bk = bucket_of(rr, S, k - 1);
+                        const int64_t d = rs[(int64_t)j * k + bk]++;
+                        Z_key[d] = A_key[x2];
+                        Z_idx[d] = A_idx[x2];
+                    }
+                }
+            }
+        }
+        ngst[(int64_t)G * k] = n;
+        /* I5: every processor of every new group merges its share */
+        for (int g2 = 0; g2 < G * k; g2++) {
+            const int64_t us = ngst[g2], z2 = ngst[g2 + 1] - us;
+            for (int j = 0; j < q2; j++) {
+                const int64_t a = us + ora_block_start(z2, q2, j), b = us + ora_block_start(z2, q2, j + 1);
+                for (int64_t x2 = a; x2 < b; x2++) { tmp[x2 - a].key = Z_key[x2]; tmp[x2 - a].idx = x2; }
+                qsort(tmp, (size_t)(b - a), sizeof(item_t), item_cmp);
+                for (int64_t x2 = a; x2 < b; x2++) {
+                    A_key[x2] = tmp[x2 - a].key;
+                    A_idx[x2] = Z_idx[tmp[x2 - a].idx];
+                }
+            }
+        }
+        if (A_idx_out) memcpy(A_idx_out + (int64_t)r * n, A_idx, sizeof(int64_t) * n);
+        G *= k;
+        q = q2;
+        memcpy(gst, ngst, sizeof(int64_t) * ((size_t)G + 1));
+    }
+    memcpy(perm, A_idx, sizeof(int64_t) * n);
+
+done_it:
+    free(A_key); free(A_idx); free(Z_key); free(Z_idx); free(tmp); free(gst); free(ngst);
+    free(smp); free(S); free(C); free(rs);
+    return rc;
+}
+
 /* Bucket of each record (key, g) of a block-sorted array against given
  * splitters: the definition used by step O6, exported so that a per-key GPU
  * ranking can be compared against it. */

@@ -580,3 +580,229 @@ def test_sr_all_equal_closed_form(ora):
     r = ora.sort_sr(np.zeros(n, dtype=np.int32), p, s, seed=5)
     edges = np.concatenate([[-1], r["spl_pos"], [n - 1]])
     assert np.array_equal(r["bucket_sizes"], np.diff(edges))
+
+
+# ----------------------------------------------------------------- iterative Sort_Det_BSP (m rounds)
+
+ITER_SHAPES = [(4, 2), (8, 3), (9, 2), (16, 2), (16, 4), (27, 3), (64, 2), (64, 3)]
+
+
+def test_iter_k(ora):
+    assert [ora.iter_k(p, m) for p, m in ITER_SHAPES] == [2, 2, 3, 4, 2, 3, 8, 4]
+    assert ora.iter_k(12, 2) == 0 and ora.iter_k(8, 2) == 0 and ora.iter_k(1, 3) == 1 and ora.iter_k(7, 1) == 7
+
+
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+def test_iter_one_round_is_sort_det(ora, dtype):
+    """m = 1 is Sort_Det_BSP itself: same output, splitters and count matrix."""
+    rng = np.random.default_rng(5)
+    for trial in range(10):
+        n = int(rng.integers(1, 4000))
+        p = int(rng.integers(1, min(n, 40) + 1))
+        s = int(rng.integers(1, 30))
+        keys = W.random_keys(n, dtype, seed=trial, distinct=None if trial % 2 else 9)
+        a = ora.sort(keys, p, s, ora.DET)
+        b = ora.sort_iter(keys, p, s, 1)
+        assert np.array_equal(a["perm"], b["perm"])
+        assert np.array_equal(a["spl_key"], b["spl_key"]) and np.array_equal(a["spl_pos"], b["spl_pos"])
+        assert np.array_equal(a["C"], b["C"][0])
+
+
+def test_iter_exhaustive_tiny(ora):
+    """Every key sequence over {0,1,2} of length 4..8, p in {4, 8, 9} (m = 2,
+    3, 2), s in 1..3: the output is the stable sort."""
+    count = 0
+    for n in range(4, 9):
+        for seq in itertools.product((0, 1, 2), repeat=n):
+            keys = np.array(seq, dtype=np.int32)
+            ref = _stable_ref(keys)
+            for p, m in ((4, 2), (8, 3), (9, 2)):
+                if p > n:
+                    continue
+                for s in (1, 2, 3):
+                    r = ora.sort_iter(keys, p, s, m)
+                    assert np.array_equal(r["perm"], ref), (seq, p, m, s)
+                    count += 1
+    assert count > 20000
+
+
+def _iter_groups(ora, r, n, p, m):
+    """Group segments after every round, from the count matrices: round r's
+    group g (q processors) splits into k sub-buckets, sizes = column sums."""
+    k = r["k"]
+    segs = [[(0, n)]]
+    q = p
+    for rr in range(m):
+        nxt = []
+        for g, (gs, ge) in enumerate(segs[-1]):
+            C = r["C"][rr][g * q:(g + 1) * q]
+            assert C.sum() == ge - gs
+            for j in range(q):  # row j sums to share j of the group
+                z = ge - gs
+                assert C[j].sum() == ora.block_start(z, q, j + 1) - ora.block_start(z, q, j)
+            base = gs
+            for b in range(k):
+                nxt.append((base, base + int(C[:, b].sum())))
+                base += int(C[:, b].sum())
+        segs.append(nxt)
+        q //= k
+    return segs
+
+
+@pytest.mark.parametrize("p,m", ITER_SHAPES)
+@pytest.mark.parametrize("dist", ["uniform", "dup7", "zipf"])
+def test_iter_rounds_invariants(ora, p, m, dist):
+    """After every round: each group segment holds exactly the records whose
+    final ranks fall in it (groups are intervals of the sorted order), and
+    every processor's share is sorted stably; the output is the stable sort."""
+    n = 3001
+    if dist == "uniform":
+        keys = W.random_keys(n, "int32", seed=p + m)
+    elif dist == "dup7":
+        keys = W.random_keys(n, "int64", seed=p + m, distinct=7)
+    else:
+        keys = (np.random.default_rng(p).zipf(1.3, n) % 97).astype(np.int32)
+    s = 3
+    r = ora.sort_iter(keys, p, s, m, rounds=True)
+    ref = _stable_ref(keys)
+    assert np.array_equal(r["perm"], ref)
+    segs = _iter_groups(ora, r, n, p, m)
+    ok = ora.order_keys(keys)
+    q = p
+    for rr in range(m):
+        q //= r["k"]
+        A = r["A_perm"][rr]
+        assert sorted(A.tolist()) == list(range(n))
+        for gs, ge in segs[rr + 1]:
+            assert set(A[gs:ge].tolist()) == set(ref[gs:ge].tolist())
+            z = ge - gs
+            for j in range(q):
+                a, b = gs + ora.block_start(z, q, j), gs + ora.block_start(z, q, j + 1)
+                sh = A[a:b]
+                assert all((ok[u], u) < (ok[v], v) for u, v in zip(sh[:-1], sh[1:]))
+
+
+def test_iter_splitters_bound_buckets(ora):
+    """Round r's splitters (tags are positions in the round's input array)
+    bound its sub-buckets: every record of sub-bucket b is above splitter b-1
+    and at or below splitter b under the (key, tag) order."""
+    n, p, m, s = 2500, 27, 3, 2
+    keys = W.random_keys(n, "int32", seed=4, distinct=40)
+    r = ora.sort_iter(keys, p, s, m, rounds=True)
+    k = r["k"]
+    segs = _iter_groups(ora, r, n, p, m)
+    ok = ora.order_keys(keys)
+    # original index at each position of round 1's input: every block sorted stably
+    prev = np.concatenate([ora.block_start(n, p, j) + np.argsort(ok[ora.block_start(n, p, j):
+                                                                    ora.block_start(n, p, j + 1)], kind="stable")
+                           for j in range(p)])
+    spl = 0
+    for rr in range(m):
+        pos_of = np.empty(n, dtype=np.int64)
+        pos_of[prev] = np.arange(n)
+        A = r["A_perm"][rr]
+        for g, (gs, ge) in enumerate(segs[rr]):
+            sp = [(int(r["spl_key"][spl + i]), int(r["spl_pos"][spl + i])) for i in range(k - 1)]
+            spl += k - 1
+            for b in range(k):
+                lo, hi = segs[rr + 1][g * k + b]
+                for u in A[lo:hi]:
+                    rec = (int(ok[u]), int(pos_of[u]))
+                    if b > 0:
+                        assert rec > sp[b - 1]
+                    if b < k - 1:
+                        assert rec <= sp[b]
+        prev = A
+    assert spl == p - 1
+
+
+@pytest.mark.parametrize("p,m", ITER_SHAPES)
+def test_iter_balance_bound_per_round(ora, p, m):
+    """Lemma `balance` inside every group of every round: a group of z records
+    held by q processors, t = q*s/k sample ranks per sub-bucket and segments
+    of x = ceil(ceil(z/q)/s) keys, gives sub-buckets of at most (t + q - 1) x."""
+    rng = np.random.default_rng(p * 10 + m)
+    worst = 0.0
+    for trial in range(20):
+        n = int(rng.integers(p, 6000))
+        s = int(rng.integers(1, 12))
+        kind = trial % 3
+        if kind == 0:
+            keys = W.random_keys(n, "int32", seed=trial)
+        elif kind == 1:
+            keys = W.random_keys(n, "int32", seed=trial, distinct=int(rng.integers(1, 5)))
+        else:
+            keys = np.sort(W.random_keys(n, "int32", seed=trial))[::-1].copy()
+        r = ora.sort_iter(keys, p, s, m)
+        segs = _iter_groups(ora, r, n, p, m)
+        k, q = r["k"], p
+        for rr in range(m):
+            t = q * s // k
+            for g, (gs, ge) in enumerate(segs[rr]):
+                z = ge - gs
+                x = -(-(-(-z // q)) // s)
+                for b in range(k):
+                    lo, hi = segs[rr + 1][g * k + b]
+                    bound = (t + q - 1) * x
+                    assert hi - lo <= bound, (n, p, m, s, rr, g, b, hi - lo, bound)
+                    if z >= q * s:
+                        worst = max(worst, (hi - lo) / bound)
+            q //= k
+    assert worst > 0.4
+
+
+@pytest.mark.parametrize("p,m,s", [(4, 2, 1), (16, 2, 3), (27, 3, 2), (64, 3, 5)])
+def test_iter_all_equal_closed_form(ora, p, m, s):
+    """All keys equal: records compare by tag alone, the sample ranks close
+    whole shares, and round r's sub-bucket b of a group is exactly the shares
+    b*q/k .. (b+1)*q/k - 1 of that group (q processors): the count matrix is
+    block diagonal with the share sizes, and the output is the identity."""
+    for n in (p, 5 * p + 3, 4000):
+        r = ora.sort_iter(np.zeros(n, dtype=np.int32), p, s, m)
+        assert np.array_equal(r["perm"], np.arange(n))
+        k, q = r["k"], p
+        segs = [(0, n)]
+        for rr in range(m):
+            want = np.zeros((p, k), dtype=np.int64)
+            nxt = []
+            for g, (gs, ge) in enumerate(segs):
+                z = ge - gs
+                for j in range(q):
+                    want[g * q + j, j // (q // k)] = ora.block_start(z, q, j + 1) - ora.block_start(z, q, j)
+                for b in range(k):
+                    nxt.append((gs + ora.block_start(z, q, b * (q // k)), gs + ora.block_start(z, q, (b + 1) * (q // k))))
+            assert np.array_equal(r["C"][rr], want), (n, rr)
+            segs = nxt
+            q //= k
+
+
+def test_iter_groups_never_smaller_than_processors(ora):
+    """A record fills at most s sample slots, so every sub-bucket keeps at least
+    q/k records and no processor of the next round is left empty. Checked on
+    inputs built to crowd the sample with clamped copies: blocks of one or two
+    records, large s, few distinct keys, and sorted runs."""
+    cases = 0
+    for p, m in ((16, 2), (64, 3), (64, 2), (27, 3), (8, 3)):
+        for s in (1, 2, 3, 5, 8):
+            for n in (p, p + 1, p + p // 2, 2 * p - 1, 3 * p):
+                for seed in range(4):
+                    for d in (None, 1, 2, 5):
+                        keys = W.random_keys(n, "int32", seed=seed, distinct=d)
+                        if seed == 3:
+                            keys = np.sort(keys)
+                        r = ora.sort_iter(keys, p, s, m)
+                        assert np.array_equal(r["perm"], _stable_ref(keys))
+                        segs = _iter_groups(ora, r, n, p, m)
+                        k, q = r["k"], p
+                        for rr in range(1, m):
+                            q //= k
+                            assert min(ge - gs for gs, ge in segs[rr]) >= q, (p, m, s, n, seed, d, rr)
+                        cases += 1
+    assert cases > 1500
+
+
+def test_iter_validation(ora):
+    with pytest.raises(ora.OracleError):
+        ora.sort_iter(np.zeros(100, np.int32), 12, 2, 2)
+    with pytest.raises(ora.OracleError):
+        ora.sort_iter(np.zeros(10, np.int32), 16, 2, 2)
