@@ -13,10 +13,15 @@ The reported time is the median over the timed steps (min and max beside it).
 The randomized variant (Figure SortRI) is timed on the same input.
 
 Beside it (in "detail"), each timed the same way:
+  variants     the same input sorted by Sort_Ran_BSP (Figure SortR), by the
+               iterative Sort_Det_BSP (m = 2, 4, 8 rounds, Section 5.1), and
+               with the duplicate handling switched off (Section 6.4), the
+               latter also on 2^28 keys over 2^10 distinct values
   learned      2^28 float32 keys (mixture of three lognormals), p = 1024,
                s = 64: per-key ranking by the learned CDF model against plain
-               splitter search on the scatter route, and the fused route;
-               identical outputs required
+               splitter search on the scatter route and in Sort_Ran_BSP's
+               ranking of the unsorted input, and the fused route; identical
+               outputs required
   int64_kv     2^28 int64 keys, Zipf(1.2) over 2^16 values + 25% equal block,
                uint32 payload, p = 256, s = 64, DET and RAN
   segmented    4096 int32 segments, log-uniform sizes in [2^8, 2^20], one
@@ -32,7 +37,7 @@ kernel (algorithmic bytes of one launch over its HIP-event-timed duration,
 against the 8 TB/s HBM peak and against the rate the library's reference copy
 kernel attains on the same array), and the CPU oracle timed on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c0,learned,int64_kv,segmented,operating]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c0,variants,learned,int64_kv,segmented,operating]
 """
 from __future__ import annotations
 
@@ -55,7 +60,7 @@ STAGES = ["tile_sort", "block_merge", "sample_splitters", "bucket_ranking", "pre
           "bucket_merge", "k_mwm_merge(block)", "k_mwm_merge(bucket)", "k_rank", "k_lsd_pass"]
 # kernels that move every record once per launch (a permuting pass: 2 w bytes per key)
 PERMUTING = ("tile_sort", "k_lsd_pass", "k_mwm_merge(block)", "k_mwm_merge(bucket)")
-ALL = ("c0", "learned", "int64_kv", "segmented", "operating")
+ALL = ("c0", "variants", "learned", "int64_kv", "segmented", "operating")
 
 
 def log(msg):
@@ -171,13 +176,14 @@ def summary(ts, n):
     return {"ms": med, "ms_min": ts[0], "ms_max": ts[-1], "steps": len(ts), "keys_per_s": n / (med / 1e3)}
 
 
-def bench_sort(bsps, torch, base, K, Wm, p, s, variant=0, bucketing=0, route=0, leaves=0, vbase=None):
+def bench_sort(bsps, torch, base, K, Wm, p, s, variant=0, bucketing=0, route=0, leaves=0, vbase=None, untagged=False,
+               rounds=1):
     """K timed sorts of the staged input (median); then one stage-timed run."""
     n = base.numel()
     work = torch.empty_like(base)
     vwork = None if vbase is None else torch.empty_like(vbase)
     dt = {torch.int32: bsps.I32, torch.int64: bsps.I64, torch.float32: bsps.F32}[base.dtype]
-    prm = bsps.make_params(p, s, variant, 1, bucketing, route, leaves)
+    prm = bsps.make_params(p, s, variant, 1, bucketing, route, leaves, untagged=untagged, rounds=rounds)
     ws = torch.empty(bsps.workspace_bytes(n, dt, vbase is not None, prm), dtype=torch.uint8, device=base.device)
 
     def restage():
@@ -186,7 +192,8 @@ def bench_sort(bsps, torch, base, K, Wm, p, s, variant=0, bucketing=0, route=0, 
             vwork.copy_(vbase)
 
     def run():
-        bsps.sort_(work, p, s, variant, values=vwork, bucketing=bucketing, route=route, leaves=leaves, workspace=ws)
+        bsps.sort_(work, p, s, variant, values=vwork, bucketing=bucketing, route=route, leaves=leaves, workspace=ws,
+                   untagged=untagged, rounds=rounds)
 
     ts = time_steps(torch, run, restage, K, Wm)
     res = summary(ts, n)
@@ -243,6 +250,40 @@ def bench_c0(bsps, torch, W, args, keys):
     return n, p, s, res
 
 
+def bench_variants(bsps, torch, W, args, keys):
+    """On the headline input (2^28 int32 uniform, p = 256, s = 64): the
+    Sort_Ran_BSP ordering (Figure SortR), the iterative Sort_Det_BSP with m =
+    2, 4 and 8 rounds (k = 16, 4, 2 buckets per round, Section 5.1), and the
+    duplicate handling switched off (Section 6.4's ablation) next to it on
+    the headline input and on 2^28 keys over 2^10 distinct values."""
+    n, p, s = keys.size, 256, 64
+    base = to_dev(torch, keys)
+    K, Wm = max(5, min(args.steps, 10)), max(1, min(args.warmup, 2))
+    out = {"workload": f"2^{int(math.log2(n))} int32 uniform, p={p}, s={s}"}
+    runs = [("sr", dict(variant=bsps.RAN_SR)), ("iter_m2", dict(rounds=2)), ("iter_m4", dict(rounds=4)),
+            ("iter_m8", dict(rounds=8)), ("untagged", dict(untagged=True))]
+    for name, kw in runs:
+        r, o, _ = bench_sort(bsps, torch, base, K, Wm, p, s, **kw)
+        r["sorted"] = is_sorted(torch, o)
+        out[name] = r
+        del o
+        log(f"variants/{name}: median {r['ms']:.3f} ms [{r['ms_min']:.3f}, {r['ms_max']:.3f}], "
+            f"{n / r['ms'] / 1e6:.2f} Gkeys/s, sorted={r['sorted']}")
+    del base
+    dk = to_dev(torch, W.int32_keys(n, p, "dict1024"))
+    for name, kw in (("dict1024_tagged", {}), ("dict1024_untagged", dict(untagged=True))):
+        r, o, _ = bench_sort(bsps, torch, dk, K, Wm, p, s, **kw)
+        r["sorted"] = is_sorted(torch, o)
+        t = dk.clone()
+        r["max_bucket_ratio"] = bsps.sort_(t, p, s, stats=True, untagged=kw.get("untagged", False))["max_bucket_ratio"]
+        out[name] = r
+        del o, t
+        log(f"variants/{name}: median {r['ms']:.3f} ms, largest bucket {r['max_bucket_ratio']:.3f} n/p")
+    del dk
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_learned(bsps, torch, W, args):
     n, p, s, L = 1 << args.log2n, 1024, 64, 4096
     log(f"learned: generating 2^{args.log2n} float32 lognormal-mixture keys")
@@ -250,12 +291,16 @@ def bench_learned(bsps, torch, W, args):
     K, Wm = max(20, args.steps), max(2, args.warmup)
     out = {"workload": f"2^{args.log2n} float32, mixture of 3 lognormals with 1024 -0.0 and 1024 +0.0, "
                        f"p={p}, s={s}, leaves={L}"}
-    for variant, vname in ((bsps.DET, "det"), (bsps.RAN, "ran")):
+    for variant, vname in ((bsps.DET, "det"), (bsps.RAN, "ran"), (bsps.RAN_SR, "sr")):
         ref = None
         e_all = {}
         for name, bucketing, route in (("fused", bsps.SPLITTER, bsps.ROUTE_FUSED),
                                        ("scatter_splitter", bsps.SPLITTER, bsps.ROUTE_SCATTER),
-                                       ("scatter_learned", bsps.LEARNED, bsps.ROUTE_SCATTER)):
+                                       ("scatter_learned", bsps.LEARNED, bsps.ROUTE_SCATTER),
+                                       ("sr_splitter", bsps.SPLITTER, bsps.ROUTE_FUSED),
+                                       ("sr_learned", bsps.LEARNED, bsps.ROUTE_FUSED)):
+            if (variant == bsps.RAN_SR) != name.startswith("sr_"):
+                continue
             if variant == bsps.RAN and name == "scatter_splitter":
                 continue
             r, o, _ = bench_sort(bsps, torch, base, K, Wm, p, s, variant, bucketing, route, L)
@@ -272,13 +317,16 @@ def bench_learned(bsps, torch, W, args):
                 f"rank {r.get('rank_kernel_keys_per_s', 0) / 1e9:.1f} Gkeys/s, identical={same}")
         # misprediction statistics of one diagnostic run (outside the timed region)
         t = base.clone()
-        st = bsps.sort_(t, p, s, variant, bucketing=bsps.LEARNED, route=bsps.ROUTE_SCATTER, leaves=L, stats=True)
+        st = bsps.sort_(t, p, s, variant, bucketing=bsps.LEARNED,
+                        route=bsps.ROUTE_FUSED if variant == bsps.RAN_SR else bsps.ROUTE_SCATTER, leaves=L, stats=True)
         e_all["mispredict_rate"] = st["mispredict_rate"]
         e_all["mean_fix_dist"] = st["mean_fix_dist"]
         e_all["max_bucket_ratio"] = st["max_bucket_ratio"]
         del t, ref
-        if "scatter_splitter" in e_all:
-            sl, ss = e_all["scatter_learned"], e_all["scatter_splitter"]
+        pair = (("scatter_learned", "scatter_splitter") if "scatter_splitter" in e_all else
+                ("sr_learned", "sr_splitter") if "sr_splitter" in e_all else None)
+        if pair:
+            sl, ss = e_all[pair[0]], e_all[pair[1]]
             e_all["learned_speedup_rank_kernel"] = (sl.get("rank_kernel_keys_per_s", 0) /
                                                     max(ss.get("rank_kernel_keys_per_s", 1), 1))
             e_all["learned_speedup_end_to_end"] = ss["ms"] / sl["ms"]
@@ -424,6 +472,8 @@ def main():
     n, p, s, c0 = bench_c0(bsps, torch, W, args, keys)
     det = c0["det"]
     detail = {"det": det, "ran": c0["ran"], "stream_copy": c0["stream_copy"]}
+    if "variants" in only:
+        detail["variants"] = bench_variants(bsps, torch, W, args, keys)
     if "learned" in only:
         detail["learned_vs_splitter"] = bench_learned(bsps, torch, W, args)
     if "int64_kv" in only:

@@ -7,13 +7,22 @@
  * (Section 5.2, Figure SortRI), both with the duplicate-key handling of
  * Section 5.1.1. The paper's p BSP processors are p virtual processors on one
  * GPU: processor k owns the contiguous block [floor(k n / p), floor((k+1) n / p))
- * of the input and bucket k of the output.
+ * of the input and bucket k of the output. Also selectable: the iterative
+ * version of Sort_Det_BSP (Section 5.1, m rounds of k-way partitioning,
+ * bsps_params.rounds), the Sort_Ran_BSP ordering (Section 5.2, Figure SortR:
+ * sample, route, then sort; BSPS_RAN_SR), and the duplicate handling switched
+ * off (the ablation of Section 6.4, bsps_params.untagged).
  *
  * Conventions for every entry point:
  *  - Pointers are DEVICE pointers unless a comment says HOST. The caller owns
  *    all memory; the library allocates no device memory on any sort path and
  *    frees nothing it did not allocate. (bsps_sort_noalloc instead uses a
- *    fixed scratch array that the library's code holds on every GPU.)
+ *    fixed scratch array that the library's code holds on every GPU.) State
+ *    the library does own: the cached graph executables of the segmented sort,
+ *    their capture stream and a pinned host buffer for its segment tables
+ *    (all released by bsps_release_cache), the events of the diagnostic stage
+ *    timer, and, during a diagnostic call only, a pinned staging buffer
+ *    (allocated and freed inside that call).
  *  - `stream` is a hipStream_t passed as void* (NULL = default stream). Work is
  *    enqueued asynchronously and the call returns after enqueueing, except in
  *    diagnostic mode (a non-NULL bsps_stats*), where the call synchronizes the
@@ -48,7 +57,12 @@ typedef enum {
     BSPS_EUNSUPPORTED = 4  /* valid but outside the library limits (n, p) */
 } bsps_status;
 
-typedef enum { BSPS_DET = 0, BSPS_RAN = 1 } bsps_variant;
+/* The method: Sort_Det_BSP (Figure SortD) and Sort_IRan_BSP (Figure SortRI)
+ * sort every block first and merge the routed runs; Sort_Ran_BSP (Figure
+ * SortR, Section 5.2) samples the unsorted input, ranks and routes every key,
+ * then sorts every bucket (route and local sort are its own, so `route` must be
+ * BSPS_ROUTE_FUSED; `bucketing` picks the per-key ranking). */
+typedef enum { BSPS_DET = 0, BSPS_RAN = 1, BSPS_RAN_SR = 2 } bsps_variant;
 typedef enum { BSPS_I32 = 0, BSPS_I64 = 1, BSPS_F32 = 2 } bsps_dtype;
 
 /* How keys are assigned to buckets when every key is ranked on its own. */
@@ -94,7 +108,19 @@ typedef struct bsps_params {
                            value routes more chunks through the global-memory path
                            (used to test that path). */
     int32_t local_sort; /* bsps_local_sort: how each block is sorted (step 3) */
-    int32_t reserved[6];/* must be zero */
+    int32_t untagged;   /* 0: the duplicate handling of Section 5.1.1 (splitters carry their
+                           tags and ties are broken by position). 1: switched off (the
+                           ablation of Section 6.4): splitters compare by key alone, so all
+                           keys equal to a splitter go to the bucket it closes. The output
+                           is the same stable sort either way; buckets may be uneven with
+                           duplicates. */
+    int32_t rounds;     /* 0 or 1: Sort_Det_BSP as in Figure SortD. m >= 2: its iterative
+                           version (Section 5.1): after the local sort, m rounds each
+                           split every current bucket into k = p^(1/m) further buckets
+                           and merge every processor's share of them. Needs p = k^m
+                           (k >= 2), variant DET, route FUSED, bucketing SPLITTER,
+                           untagged 0; m <= 10. Same output (the stable sort). */
+    int32_t reserved[4];/* must be zero */
 } bsps_params;
 
 /*
@@ -106,14 +132,14 @@ typedef struct bsps_params {
 typedef struct bsps_stats {
     void* splitter_keys;       /* p-1 keys of the call's dtype */
     int64_t* splitter_pos;     /* p-1 tags: positions in the block-sorted array */
-    void* sample_keys;         /* sorted sample: DET p*s, RAN p*s-1 keys */
-    int64_t* sample_pos;       /* their positions in the block-sorted array */
+    void* sample_keys;         /* sorted sample: DET p*s, RAN and RAN_SR p*s-1 keys */
+    int64_t* sample_pos;       /* their positions in the block-sorted array (RAN_SR: in the input) */
     int64_t* bucket_sizes;     /* p */
     int64_t* count_matrix;     /* p*p, row k = source block, column i = bucket */
     void* block_sorted;        /* n keys: every block sorted (Figure SortD step 3) */
     uint32_t* block_sorted_values; /* n payloads, kv calls only */
-    void* routed;              /* n keys after routing (route = SCATTER only) */
-    uint32_t* buckets;         /* n bucket ids of block_sorted (route = SCATTER only) */
+    void* routed;              /* n keys after routing (route = SCATTER, or variant RAN_SR) */
+    uint32_t* buckets;         /* n bucket ids of block_sorted (route = SCATTER), of the input (RAN_SR) */
     double max_bucket_ratio;   /* largest bucket / (n/p) */
     double mispredict_rate;    /* learned bucketing: fraction of keys corrected */
     double mean_fix_dist;      /* learned bucketing: mean |predicted - true| */

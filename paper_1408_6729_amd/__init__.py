@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("BSPS_LIB") or os.path.join(_HERE, "libbsps.so")
 
 OK, EINVAL, EWORKSPACE, EDEVICE, EUNSUPPORTED = 0, 1, 2, 3, 4
-DET, RAN = 0, 1
+DET, RAN, RAN_SR = 0, 1, 2
 I32, I64, F32 = 0, 1, 2
 SPLITTER, LEARNED = 0, 1
 ROUTE_FUSED, ROUTE_SCATTER = 0, 1
@@ -37,7 +37,8 @@ class BspsError(RuntimeError):
 class Params(ct.Structure):
     _fields_ = [("p", ct.c_int32), ("s", ct.c_int32), ("variant", ct.c_int32), ("bucketing", ct.c_int32),
                 ("route", ct.c_int32), ("leaves", ct.c_int32), ("seed", ct.c_uint64),
-                ("chunk_cap", ct.c_int32), ("local_sort", ct.c_int32), ("reserved", ct.c_int32 * 6)]
+                ("chunk_cap", ct.c_int32), ("local_sort", ct.c_int32), ("untagged", ct.c_int32),
+                ("rounds", ct.c_int32), ("reserved", ct.c_int32 * 4)]
 
 
 class Stats(ct.Structure):
@@ -113,11 +114,14 @@ def status_string(code: int) -> str:
 
 
 def make_params(p: int, s: int, variant: int = DET, seed: int = 1, bucketing: int = SPLITTER,
-                route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0, local_sort: int = LOCAL_AUTO) -> Params:
+                route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0, local_sort: int = LOCAL_AUTO,
+                untagged: bool = False, rounds: int = 1) -> Params:
     prm = Params()
     prm.p, prm.s, prm.variant, prm.bucketing = p, s, variant, bucketing
     prm.route, prm.leaves, prm.seed, prm.chunk_cap = route, leaves, seed & 0xFFFFFFFFFFFFFFFF, chunk_cap
     prm.local_sort = local_sort
+    prm.untagged = int(bool(untagged))
+    prm.rounds = rounds
     return prm
 
 
@@ -143,18 +147,21 @@ def _stream(t) -> int:
 
 def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, bucketing: int = SPLITTER,
           route: int = ROUTE_FUSED, leaves: int = 0, chunk_cap: int = 0, stats: bool = False, workspace=None,
-          stats_arrays: bool = False, local_sort: int = LOCAL_AUTO):
+          stats_arrays: bool = False, local_sort: int = LOCAL_AUTO, untagged: bool = False, rounds: int = 1):
     """Sorts `keys` (a contiguous int32/int64/float32 CUDA tensor) in place; with
     `values` (uint32 payload as an int32 tensor of the same length) a key-value
     sort. With stats=True the call synchronizes and returns the diagnostic
     statistics (splitters, sample, counts, bucket sizes ...); stats_arrays=True
     adds the n-element arrays (block-sorted keys and payloads, and for the
-    scatter route the routed keys and bucket ids)."""
+    scatter route the routed keys and bucket ids; Sort_Ran_BSP the routed keys).
+    rounds=m >= 2 runs the iterative Sort_Det_BSP (p = k^m); its count matrix
+    comes back as m x p x k (round, processor, bucket) and its p-1 splitters
+    are round 1's, then round 2's group by group, ..."""
     import torch
     assert keys.is_cuda and keys.is_contiguous() and keys.dim() == 1
     n = keys.numel()
     dt = _dtype_code(keys)
-    prm = make_params(p, s, variant, seed, bucketing, route, leaves, chunk_cap, local_sort)
+    prm = make_params(p, s, variant, seed, bucketing, route, leaves, chunk_cap, local_sort, untagged, rounds)
     hasv = values is not None
     if hasv:
         assert values.is_cuda and values.is_contiguous() and values.numel() == n and values.element_size() == 4
@@ -178,7 +185,7 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
             host["block_sorted"] = np.zeros(max(n, 1), kd)
         if hasv and stats_arrays:
             host["block_sorted_values"] = np.zeros(max(n, 1), np.uint32)
-        if route == ROUTE_SCATTER and stats_arrays:
+        if (route == ROUTE_SCATTER or variant == RAN_SR) and stats_arrays:
             host["routed"] = np.zeros(max(n, 1), kd)
             host["buckets"] = np.zeros(max(n, 1), np.uint32)
         for k, arr in host.items():
@@ -199,7 +206,11 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
     ns = p * s if variant == DET else p * s - 1
     out["sample_keys"] = out["sample_keys"][:ns]
     out["sample_pos"] = out["sample_pos"][:ns]
-    out["count_matrix"] = out["count_matrix"].reshape(p, p)
+    if rounds >= 2 and p > 1:
+        k = round(p ** (1.0 / rounds))
+        out["count_matrix"] = out["count_matrix"][:rounds * p * k].reshape(rounds, p, k)
+    else:
+        out["count_matrix"] = out["count_matrix"].reshape(p, p)
     if stats_arrays:
         out["block_sorted"] = out["block_sorted"][:n]
     out["max_bucket_ratio"] = st.max_bucket_ratio

@@ -5,9 +5,13 @@ processors (each block at most one tile) and oversampling s; segments are
 grouped by size class (n <= 2^max_log2) and every class has its own (block, s).
 This tool measures, on the GPU, each candidate (block, s) of a class on a
 synthetic batch made only of segments of that class (sizes log-uniform inside
-the class, uniform and 2^8-distinct segments alternating), timing the whole
-captured graph launch with HIP events on the launching stream, and writes
-the fastest table as JSON in the library's tuning format:
+the class, uniform and 2^8-distinct segments alternating), timing the cached
+graph's replays with HIP events on the launching stream (the input is
+restaged outside the timed region), then the threshold above which segments
+use learned bucketing (2^16, 2^18 or never) on a batch spanning every class,
+and writes the fastest table as JSON in the library's tuning format. The tile
+shape itself (512 threads x 32 keys, 16 Ki keys) is fixed by the LDS budget,
+so a block is at most one tile:
 
     python -m paper_1408_6729_amd.autotune [--out tuning.json] [--keys-per-class 2^25]
 
@@ -23,8 +27,9 @@ import sys
 import time
 
 CLASSES = (14, 16, 18, 20, 30)
-BLOCKS = (2048, 4096, 8192, 16384)
-OVERSAMPLING = (1, 2, 4, 8, 16, 32, 64)
+BLOCKS = (4096, 8192, 16384)
+OVERSAMPLING = (1, 4, 8, 16, 32, 64)
+LEARNED = (16, 18, 40)  # learned bucketing above 2^16, above 2^18, never
 
 
 def _log(msg):
@@ -42,35 +47,42 @@ def _batch(lo_log2: float, hi_log2: float, total: int, seed: int):
     return W.segmented_int32(np.array(sizes, dtype=np.int64), seed=seed)
 
 
-def _table(classes):
-    return json.dumps({"classes": [{"max_log2": c, "block": b, "s": s} for c, (b, s) in classes]})
+def _table(classes, learned_above_log2=40):
+    return json.dumps({"learned_above_log2": learned_above_log2,
+                       "classes": [{"max_log2": c, "block": b, "s": s} for c, (b, s) in classes]})
 
 
 def _time(bsps, torch, base, offs, tuning: str, reps: int) -> float:
-    """Median milliseconds of one graph launch over `reps` staged copies."""
+    """Median milliseconds of one graph launch: one fixed work buffer, the
+    input restaged into it before every launch outside the timed region; the
+    first call captures the graph, every timed call replays it from the cache."""
     n = base.numel()
     ws = torch.empty(max(1, bsps.segmented_workspace_bytes(offs, bsps.I32, False, tuning)), dtype=torch.uint8,
                      device=base.device)
-    copies = torch.empty((reps + 1, n), dtype=torch.int32, device=base.device)
-    for i in range(reps + 1):
-        copies[i].copy_(base)
-    bsps.sort_segmented_(copies[0], offs, tuning=tuning, workspace=ws)  # capture + warm-up
+    work = torch.empty_like(base)
+    work.copy_(base)
+    bsps.sort_segmented_(work, offs, tuning=tuning, workspace=ws)  # capture + warm-up
     torch.cuda.synchronize()
     times = []
-    for i in range(1, reps + 1):
+    for _ in range(reps):
+        work.copy_(base)
+        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        bsps.sort_segmented_(copies[i], offs, tuning=tuning, workspace=ws)
+        bsps.sort_segmented_(work, offs, tuning=tuning, workspace=ws)
         e1.record()
         e1.synchronize()
         times.append(e0.elapsed_time(e1))
-    out = copies[reps]
-    desc = out[1:] < out[:-1]
+    desc = work[1:] < work[:-1]
     inner = torch.as_tensor(offs[1:-1], dtype=torch.int64, device=base.device)
     inner = inner[(inner > 0) & (inner < n)]
     desc[inner - 1] = False  # a descent across a segment boundary is allowed
     if bool(desc.any()):
         raise RuntimeError(f"segmented sort produced an unsorted segment with tuning {tuning}")
+    work.copy_(base)
+    st = bsps.sort_segmented_(work, offs, tuning=tuning, workspace=ws, stats=True)
+    if not st["graph_cached"]:
+        raise RuntimeError("the timed launches did not replay the cached graph")
     bsps.release_cache()
     return sorted(times)[len(times) // 2]
 
@@ -127,7 +139,25 @@ def tune(classes=CLASSES, blocks=BLOCKS, oversampling=OVERSAMPLING, keys_per_cla
         lo = hi
         del base
         torch.cuda.empty_cache()
-    return json.loads(_table(best)), report
+    # the learned-bucketing threshold, on a batch spanning every class (the
+    # candidates' order breaks near-ties towards no learned bucketing)
+    keys, offs = _batch(8.0, 20.0, keys_per_class * 2, seed=99)
+    pin = torch.empty(keys.shape, dtype=torch.int32, pin_memory=True)
+    pin.copy_(torch.from_numpy(keys))
+    base = pin.to(dev)
+    del pin
+    lres = []
+    for lg in LEARNED:
+        ms = _time(bsps, torch, base, offs, _table(best, lg), reps)
+        lres.append((ms, lg))
+        _log(f"learned bucketing above 2^{lg}: {ms:8.3f} ms")
+    fastest = min(m for m, _ in lres)
+    lg_best = max(lg for m, lg in lres if m <= fastest * 1.01)
+    report.append({"learned_above_log2": lg_best, "candidates": [{"learned_above_log2": lg, "ms": m}
+                                                                 for m, lg in lres]})
+    del base
+    torch.cuda.empty_cache()
+    return json.loads(_table(best, lg_best)), report
 
 
 def main():

@@ -22,6 +22,8 @@
 #include "bsps_kernels.h"
 #include "bsps_learned.h"
 #include "bsps_lsd.h"
+#include "bsps_sr.h"
+#include "bsps_iter.h"
 #include "bsps_segmented.h"
 
 #include <map>
@@ -39,6 +41,7 @@ namespace {
 
 constexpr u32 kSampleStride = 32;  // tile and block samples for the merges: every 32nd key
 constexpr int kMaxP = MAXR;  // p <= 1024
+constexpr int kMaxRounds = 10;  // iterative rounds: p = k^m with k >= 2 and p <= 1024
 
 // A failed HIP call maps to BSPS_EDEVICE; with BSPS_DEBUG set in the
 // environment the call, the source line and HIP's message go to stderr.
@@ -97,6 +100,7 @@ struct DryRun {
 thread_local DryRun* t_dry = nullptr;
 
 inline u64 cdiv(u64 a, u64 b) { return (a + b - 1) / b; }
+inline int bitw(u64 v) { int b = 0; while (v) { b++; v >>= 1; } return b; }
 // The learned-rank counters (two u64, updated by 64-bit atomics) follow the
 // p*p count matrix at the next 8-byte boundary.
 inline size_t lstats_off(int p) { return ((size_t)p * p + 1) & ~(size_t)1; }
@@ -195,8 +199,14 @@ void dry_check(const LsdArgs<K>& a) {
     dry_span("LsdArgs.dbase", a.dbase, p * DP * LSD_RADIX);
     dry_span("LsdArgs.plist", a.plist, p * (DP + 1));
     dry_span("LsdArgs.smp", a.smp, p * a.spb);
+    dry_span("LsdArgs.blk", a.blk, p);
     if (!a.inv != !a.outv || !a.av != !a.outv || !a.bv != !a.outv)
         t_dry->fail("LsdArgs: payload buffers given for some passes only", a.outv, 0);
+}
+void dry_check(const LsdSweep& w) {
+    dry_span("LsdSweep.status", w.status, (u64)w.ntile * LSD_RADIX);
+    dry_span("LsdSweep.ctr", w.ctr, 2);
+    if (!w.status || !w.ctr || !w.tstart) t_dry->fail("LsdSweep: missing buffer", w.status, 0);
 }
 template <typename... A>
 void dry_launch(const char* name, dim3 grid, dim3 block, const A&... args) {
@@ -335,12 +345,12 @@ int device_cus() {
 // Per-key rank launch: every tile once, with at most as many workgroups as
 // are resident at the same time (the kernel walks tiles with a stride).
 template <typename K, bool LEARNED>
-bsps_status launch_rank(const K* B, i64 n, int p, const K* spk, const u32* spp, int dt, const void* model,
+bsps_status launch_rank(const K* B, i64 n, int p, const K* spk, const u32* spp, int dt, int sdt, const void* model,
                         u32* bucket, u32* counts, unsigned long long* lstats, hipStream_t st) {
     typedef RankShape<LEARNED> RS;
     const int tpb = (int)cdiv(cdiv((u64)n, (u64)p), (u64)rank_tile<LEARNED>());
     const u32 grid = (u32)std::max<i64>(1, std::min<i64>((i64)p * tpb, (i64)device_cus() * RS::WG_PER_CU));
-    LAUNCH((k_rank<K, LEARNED>), dim3(grid), dim3(RS::NT), 0, st, B, n, p, tpb, spk, spp, dt, model,
+    LAUNCH((k_rank<K, LEARNED>), dim3(grid), dim3(RS::NT), 0, st, B, n, p, tpb, spk, spp, dt, sdt, model,
                        bucket, counts, lstats);
     LAUNCH_OK();
     return BSPS_OK;
@@ -472,8 +482,24 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
 // are the scratch of the passes in between (in is consumed). osmp: block
 // samples every yb-th key (slot stride spb).
 template <typename K, bool HASV>
+bsps_status lsd_launch(const LsdArgs<K>& a, const LsdSweep& w, hipStream_t st);
+
+// Buffers of the tile-parallel passes: per tile and digit one status word,
+// the ticket and overrun counters, the first tile of every block.
+template <typename K>
+LsdSweep carve_sweep(Carver& c, i64 n, int p) {
+    LsdSweep w{};
+    w.ntile = (u32)(cdiv((u64)n, tileT<K>()) + (u64)p);
+    w.status = c.take<u32>((u64)w.ntile * LSD_RADIX);
+    w.ctr = c.take<u32>(8);
+    w.tstart = c.take<u32>((u64)p + 1);
+    w.spin_limit = 1u << 16;  // a wait lasts about one tile sort; this is some 1000 times that
+    return w;
+}
+
+template <typename K, bool HASV>
 bsps_status lsd_block_sort(K* in, u32* inv, int in_dt, K* A, u32* Av, K* out, u32* outv, u32* dbase, u32* plist,
-                           i64 n, int p, int tpb, K* osmp, u32 yb, u32 spb, hipStream_t st) {
+                           const LsdSweep& w, i64 n, int p, int tpb, K* osmp, u32 yb, u32 spb, hipStream_t st) {
     constexpr int NT = Shape<K>::NT;
     LsdArgs<K> a{};
     a.in = in; a.inv = inv; a.in_dt = in_dt;
@@ -482,20 +508,38 @@ bsps_status lsd_block_sort(K* in, u32* inv, int in_dt, K* A, u32* Av, K* out, u3
     a.n = n; a.p = p; a.tpb = tpb;
     a.dbase = dbase; a.plist = plist;
     a.smp = osmp; a.ys = yb; a.spb = spb;
-    static int occ = -1;
-    if (!t_dry && occ < 0 && hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_lsd_pass<K, HASV>, NT, 0) != hipSuccess)
-        occ = 0;
-    const u32 grid = (u32)std::max<i64>(1, std::min<i64>(p, (i64)device_cus() * std::max(occ, 1)));
+    a.blk = nullptr;
+    a.out_dt = BSPS_DT_NONE;
+    return lsd_launch<K, HASV>(a, w, st);
+}
+
+// The digit counts of every block, then one tile-parallel launch per digit
+// position (blocks that need fewer passes skip the later launches).
+template <typename K, bool HASV>
+bsps_status lsd_launch(const LsdArgs<K>& a, const LsdSweep& w, hipStream_t st) {
+    constexpr int NT = Shape<K>::NT;
+    const int p = a.p;
     StageScope sc(ST_TILE, st);
     LAUNCH((k_lsd_hist<K>), dim3((u32)p), dim3(LSD_HIST_NT), 0, st, a);
     LAUNCH_OK();
+    LAUNCH((k_lsd_tiles<K>), dim3(1), dim3(1024), 0, st, a, w);
+    LAUNCH_OK();
+    LAUNCH(k_zero_u32, dim3(1), dim3(64), 0, st, w.ctr, 8);
+    LAUNCH_OK();
     StageScope sk(ST_LSD_K, st);
+    const u64 nstat = (u64)w.ntile * LSD_RADIX;
     for (int pass = 0; pass < (int)sizeof(K); pass++) {
-        LAUNCH((k_lsd_pass<K, HASV>), dim3(grid), dim3(NT), 0, st, a, pass);
+        LAUNCH(k_zero_u32, dim3((u32)cdiv(nstat, 256)), dim3(256), 0, st, w.status, (int)nstat);
+        LAUNCH_OK();
+        LAUNCH(k_zero_u32, dim3(1), dim3(64), 0, st, w.ctr, 1);  // the ticket
+        LAUNCH_OK();
+        (void)p;
+        LAUNCH((k_lsd_sweep<K, HASV>), dim3(w.ntile), dim3(NT), 0, st, a, w, pass);
         LAUNCH_OK();
     }
     return BSPS_OK;
 }
+
 
 // ------------------------------------------------------------------ learned model
 
@@ -529,38 +573,15 @@ bsps_status fit_model(const K* smp, i64 N, int dt, int p, int s, int L, int iter
                       hipStream_t st) {
     Carver c(ws);
     FitWs f = carve_fit(c, N, L);
-    const u32 gN = (u32)std::max<u64>(1, cdiv((u64)N, 256));
-    LAUNCH((k_model_init<K>), dim3(1), dim3(64), 0, st, smp, N, dt, p, s, L, model);
+    // root, leaf ranges, leaves: three launches
+    LAUNCH((k_fit_root<K>), dim3(1), dim3(FIT_NT), 0, st, smp, N, dt, p, s, L, iters, model, f.x);
     LAUNCH_OK();
-    for (int stage = 0; stage < 2; stage++) {
-        const int nmod = stage == 0 ? 1 : L;
-        const u32 gM = (u32)cdiv((u64)nmod + 1, 256);
-        LAUNCH((k_model_x<K>), dim3(gN), dim3(256), 0, st, smp, N, dt, (const void*)model, stage, f.x,
-                           f.leafid);
-        LAUNCH_OK();
-        LAUNCH(k_model_ranges, dim3(gM), dim3(256), 0, st, f.leafid, N, nmod, f.lo);
-        LAUNCH_OK();
-        if (stage == 0)
-            LAUNCH(k_model_centres<1024>, dim3(1), dim3(1024), 0, st, f.x, f.lo, nmod, model, stage);
-        else
-            LAUNCH(k_model_centres<64>, dim3(nmod), dim3(64), 0, st, f.x, f.lo, nmod, model, stage);
-        LAUNCH_OK();
-        for (int it = 0; it < iters; it++) {
-            LAUNCH(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, f.leafid, N, p, s,
-                               (const void*)model, stage, f.r);
-            LAUNCH_OK();
-            if (stage == 0)
-                LAUNCH(k_model_backward<1024>, dim3(1), dim3(1024), 0, st, f.x, f.r, f.lo, nmod, N,
-                                   (const void*)model, stage, f.g, f.hs, f.lossp);
-            else
-                LAUNCH(k_model_backward<64>, dim3(nmod), dim3(64), 0, st, f.x, f.r, f.lo, nmod, N,
-                                   (const void*)model, stage, f.g, f.hs, f.lossp);
-            LAUNCH_OK();
-            LAUNCH(k_model_update, dim3(gM), dim3(256), 0, st, f.g, f.hs, f.lo, nmod, p, s, model,
-                               stage);
-            LAUNCH_OK();
-        }
-    }
+    LAUNCH(k_fit_ranges, dim3((u32)cdiv((u64)N + 1, 256)), dim3(256), 0, st, (const float*)f.x, N,
+           (const void*)model, L, f.lo);
+    LAUNCH_OK();
+    LAUNCH(k_fit_leaves, dim3((u32)cdiv((u64)L, FIT_LEAF_NT / 64)), dim3(FIT_LEAF_NT), 0, st, (const float*)f.x,
+           (const int32_t*)f.lo, N, L, p, s, iters, model);
+    LAUNCH_OK();
     return BSPS_OK;
 }
 
@@ -584,6 +605,7 @@ struct Plan {
     bool lsd;                // A1 by LSD radix through HBM (else tiles + multiway merge)
     u32* dbase;              // LSD: digit starts [p][sizeof(K)][256]
     u32* plist;              // LSD: passes of every block [p][sizeof(K) + 1]
+    LsdSweep lsw;            // LSD: look-back status, tickets, tiles of every block
     BlockSortBufs<K> bs;     // main block sort
     K* B;
     u32* Bv;
@@ -605,6 +627,7 @@ struct Plan {
     // splitters and counts
     K* pk;
     u32* pp;
+    u32* pcmp;               // splitter tags the bucket searches compare with (all +inf when untagged)
     u32* cntT;
     MwmBufs<K> bm;           // bucket merge
     // scatter route
@@ -615,7 +638,46 @@ struct Plan {
     void* model;
     void* fitws;
     size_t fitws_bytes;
+    // iterative rounds (m >= 2): group tables, share samples, sample sorts
+    int m, k;
+    u32* grp0;
+    u32* grp1;
+    K* itsmp0;
+    K* itsmp1;
+    u32 itspb;
+    BlockSortBufs<K> its[kMaxRounds];
 };
+
+// k with k^m = p (k >= 2), or 0 when p is not an m-th power (m >= 2).
+int iter_k(int p, int m) {
+    if (m <= 1) return p;
+    for (int k = 2; k <= p; k++) {
+        u64 v = 1;
+        for (int r = 0; r < m && v <= (u64)p; r++) v *= (u64)k;
+        if (v == (u64)p) return k;
+        if (v > (u64)p) return 0;
+    }
+    return 0;
+}
+
+// Sample slots per share for the shares the non-final rounds produce: every
+// kSampleStride-th key of the largest possible share. A sub-bucket of a group
+// of z records on q processors holds at most (t + q - 1) x records (Lemma
+// balance inside the group: t = q s / k sample ranks per sub-bucket, segments
+// of x = ceil(ceil(z/q)/s) keys); a share of the next round is at most
+// ceil(that / (q/k)). The merge writes no sample past the slots, so a share
+// above the bound would only get a coarser merge plan.
+u32 iter_spb(i64 n, int p, int s, int m, int k) {
+    u64 z = (u64)n, q = (u64)p, best = 0;
+    for (int r = 0; r + 1 < m; r++) {
+        const u64 x = cdiv(cdiv(z, q), (u64)s);
+        const u64 t = q * (u64)s / (u64)k;
+        z = std::min<u64>((u64)n, (t + q - 1) * x);
+        q /= (u64)k;
+        best = std::max<u64>(best, cdiv(z, q));
+    }
+    return (u32)std::max<u64>(1, best / kSampleStride);
+}
 
 // Which local sort A1 uses (bsps_local_sort). Auto: the tile sort and merge,
 // measured faster than the LSD passes on every workload.
@@ -627,8 +689,58 @@ bool use_lsd(i64 n, const bsps_params* prm) {
     return false;
 }
 
+// Sort_Ran_BSP: the routed array Z (= B), the LSD scratch A and tables, the
+// bucket of every key, the sample and its sorts, splitters and counts.
+template <typename K>
+size_t carve_plan_sr(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* prm) {
+    const int p = prm->p, s = prm->s;
+    const Opts o = opts_for<K>(prm);
+    P.lsd = true;
+    std::memset(&P.bs, 0, sizeof(P.bs));
+    P.bs.A = c.take<K>(n);
+    P.bs.Av = hasv ? c.take<u32>(n) : nullptr;
+    P.dbase = c.take<u32>((u64)p * sizeof(K) * LSD_RADIX);
+    P.plist = c.take<u32>((u64)p * (sizeof(K) + 1));
+    P.lsw = carve_sweep<K>(c, n, p);
+    P.B = c.take<K>(n);
+    P.Bv = hasv ? c.take<u32>(n) : nullptr;
+    P.spb = 0;
+    P.bsmp = nullptr;
+    P.ns = (i64)p * s - 1;
+    const i64 ns1 = std::max<i64>(1, P.ns);
+    P.skey = c.take<K>(ns1);
+    P.spos = c.take<u32>(ns1);
+    P.ssk = c.take<K>(ns1);
+    P.ssp = c.take<u32>(ns1);
+    P.sscr = c.take<K>(ns1);
+    P.sscrv = c.take<u32>(ns1);
+    carve_block_sort<K>(c, P.ss, (u64)ns1, 1, true, o.tavg, false);
+    P.rpos = c.take<u32>(ns1);
+    P.rpos_s = c.take<u32>(ns1);
+    P.rpos_scr = c.take<u32>(ns1);
+    carve_block_sort<u32>(c, P.rs, (u64)ns1, 1, false, std::max<u32>(1, opts_for<u32>(prm).tavg), false);
+    P.pk = c.take<K>(p);
+    P.pp = c.take<u32>(p);
+    P.pcmp = prm->untagged ? c.take<u32>(p) : P.pp;
+    P.cntT = c.take<u32>((u64)(p + 1) * p);
+    std::memset(&P.bm, 0, sizeof(P.bm));
+    P.bucket = c.take<u32>(n);
+    P.C = c.take<u32>(lstats_off(p) + 4);
+    P.off = c.take<u32>((u64)p * p);
+    P.model = P.fitws = nullptr;
+    P.fitws_bytes = 0;
+    if (prm->bucketing == BSPS_LEARNED) {
+        const int L = prm->leaves > 0 ? prm->leaves : 4096;
+        P.model = c.take<char>(bsps_model_bytes(L));
+        P.fitws_bytes = bsps_fit_workspace_bytes(P.ns, L);
+        P.fitws = c.take<char>(P.fitws_bytes);
+    }
+    return c.off + 256;
+}
+
 template <typename K>
 size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* prm) {
+    if (prm->variant == BSPS_RAN_SR) return carve_plan_sr<K>(c, P, n, hasv, prm);
     const int p = prm->p;
     const Opts o = opts_for<K>(prm);
     const bool scatter = prm->route == BSPS_ROUTE_SCATTER;
@@ -642,7 +754,9 @@ size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* pr
         P.bs.Av = hasv ? c.take<u32>(n) : nullptr;
         P.dbase = c.take<u32>((u64)p * sizeof(K) * LSD_RADIX);
         P.plist = c.take<u32>((u64)p * (sizeof(K) + 1));
+        P.lsw = carve_sweep<K>(c, n, p);
     } else {
+        std::memset(&P.lsw, 0, sizeof(P.lsw));
         carve_block_sort<K>(c, P.bs, (u64)n, p, hasv, o.tavg, true);  // A doubles as merge scratch / routed array
     }
     P.B = c.take<K>(n);
@@ -669,6 +783,7 @@ size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* pr
     }
     P.pk = c.take<K>(p);
     P.pp = c.take<u32>(p);
+    P.pcmp = prm->untagged ? c.take<u32>(p) : P.pp;
     P.cntT = c.take<u32>((u64)(p + 1) * p);
     carve_mwm<K>(c, P.bm, p, p, (u64)n, o.tavg);
     P.bucket = P.C = P.off = nullptr;
@@ -685,6 +800,25 @@ size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* pr
             P.fitws = c.take<char>(P.fitws_bytes);
         }
     }
+    P.m = prm->rounds >= 2 && p > 1 ? prm->rounds : 1;
+    P.k = iter_k(p, P.m);
+    P.grp0 = P.grp1 = nullptr;
+    P.itsmp0 = P.itsmp1 = nullptr;
+    P.itspb = 0;
+    if (P.m >= 2) {
+        P.grp0 = c.take<u32>((u64)p + 1);
+        P.grp1 = c.take<u32>((u64)p + 1);
+        P.itspb = iter_spb(n, p, prm->s, P.m, P.k);
+        P.itsmp0 = c.take<K>((u64)p * P.itspb);
+        P.itsmp1 = c.take<K>((u64)p * P.itspb);
+        // round r sorts the p*s sample records as k^r blocks (one per group)
+        P.its[0] = P.ss;
+        u64 G = 1;
+        for (int r = 1; r < P.m; r++) {
+            G *= (u64)P.k;
+            carve_block_sort<K>(c, P.its[r], (u64)ns1, (int)G, true, o.tavg, false);
+        }
+    }
     return c.off + 256;
 }
 
@@ -693,14 +827,23 @@ bsps_status validate(i64 n, int dtype, const bsps_params* prm) {
     if (n < 0 || prm->p < 1 || prm->s < 1) return BSPS_EINVAL;
     if ((i64)prm->p > std::max<i64>(n, 1)) return BSPS_EINVAL;
     if (dtype < 0 || dtype > 2) return BSPS_EINVAL;
-    if (prm->variant != BSPS_DET && prm->variant != BSPS_RAN) return BSPS_EINVAL;
+    if (prm->variant != BSPS_DET && prm->variant != BSPS_RAN && prm->variant != BSPS_RAN_SR) return BSPS_EINVAL;
     if (prm->route != BSPS_ROUTE_FUSED && prm->route != BSPS_ROUTE_SCATTER) return BSPS_EINVAL;
     if (prm->bucketing != BSPS_SPLITTER && prm->bucketing != BSPS_LEARNED) return BSPS_EINVAL;
     if (prm->leaves < 0 || prm->leaves > MAX_LEAVES || prm->chunk_cap < 0) return BSPS_EINVAL;
     if (prm->local_sort < BSPS_LOCAL_AUTO || prm->local_sort > BSPS_LOCAL_LSD) return BSPS_EINVAL;
-    for (int i = 0; i < 6; i++)
+    if (prm->untagged != 0 && prm->untagged != 1) return BSPS_EINVAL;
+    for (int i = 0; i < 4; i++)
         if (prm->reserved[i]) return BSPS_EINVAL;
-    if (prm->variant == BSPS_RAN && (i64)prm->s * prm->p - 1 > n) return BSPS_EINVAL;
+    if (prm->rounds < 0 || prm->rounds > kMaxRounds) return BSPS_EINVAL;
+    if (prm->rounds >= 2 && prm->p > 1) {
+        // the iterative version of Sort_Det_BSP: regular sample, splitter search, fused route
+        if (prm->variant != BSPS_DET || prm->route != BSPS_ROUTE_FUSED || prm->bucketing != BSPS_SPLITTER ||
+            prm->untagged)
+            return BSPS_EINVAL;
+        if (iter_k(prm->p, prm->rounds) < 2) return BSPS_EINVAL;
+    }
+    if (prm->variant != BSPS_DET && (i64)prm->s * prm->p - 1 > n) return BSPS_EINVAL;
     if (n >= (i64)0xFFFFFFFFll || prm->p > kMaxP) return BSPS_EUNSUPPORTED;
     // every block must split into at most MAXR tiles
     const int kb = key_bytes(dtype);
@@ -708,6 +851,7 @@ bsps_status validate(i64 n, int dtype, const bsps_params* prm) {
     if (n > 1 && cdiv(cdiv((u64)n, (u64)prm->p), T) > (u64)MAXR) return BSPS_EUNSUPPORTED;
     const i64 ns = prm->variant == BSPS_DET ? (i64)prm->p * prm->s : (i64)prm->p * prm->s - 1;
     if (ns > (i64)MAXR * (i64)T || ns >= (i64)0xFFFFFFFFll) return BSPS_EUNSUPPORTED;
+    if (prm->variant == BSPS_RAN_SR && prm->route != BSPS_ROUTE_FUSED) return BSPS_EINVAL;  // it has one route
     return BSPS_OK;
 }
 
@@ -768,6 +912,16 @@ bsps_status d2h(void* host, const void* dev, size_t bytes, hipStream_t st) {
     return rc;
 }
 
+// Waits of the tile-parallel passes that hit their spin limit (diagnostic
+// calls only: nonzero means the output cannot be trusted).
+bsps_status sweep_overruns(const LsdSweep& w, hipStream_t st) {
+    if (t_dry || !w.ctr) return BSPS_OK;
+    u32 c[2];
+    const bsps_status rc = d2h(c, w.ctr, 8, st);
+    if (rc) return rc;
+    return c[1] ? BSPS_EDEVICE : BSPS_OK;
+}
+
 template <typename K>
 bsps_status copy_keys_out(void* host, const K* dev, i64 count, int dt, hipStream_t st) {
     if (!host || count <= 0) return BSPS_OK;
@@ -790,9 +944,272 @@ bsps_status copy_u32_to_i64(int64_t* host, const u32* dev, i64 count, hipStream_
 
 // ------------------------------------------------------------------ the sort
 
+// Sort_Ran_BSP (Section 5.2, Figure SortR): sample the unsorted input, sort
+// the sample, pick the splitters, rank every input record (key, position)
+// against them (splitter search or the learned model with the exact check),
+// route the records to their buckets in input order, then sort every bucket
+// (a stable LSD sort through HBM, buckets of any size).
+template <typename K, bool HASV>
+bsps_status run_sort_sr(void* keys, u32* vals, i64 n, int dt, const bsps_params* prm, void* ws, size_t ws_bytes,
+                        hipStream_t st, bsps_stats* stats) {
+    const int p = prm->p, s = prm->s;
+    Carver c(ws);
+    Plan<K> P{};
+    const size_t need = carve_plan<K>(c, P, n, HASV, prm);
+    if (!ws_ok(ws) || ws_bytes < need) return BSPS_EWORKSPACE;
+    const Opts o = opts_for<K>(prm);
+    K* io = (K*)keys;
+    const i64 ns = P.ns;
+    const bool learned = prm->bucketing == BSPS_LEARNED;
+    bsps_status rc;
+    if (ns > 0) {  // (p = s = 1 draws no sample: one bucket, no splitters)
+        StageScope sc(ST_SAMPLE, st);
+        // step 2: s*p - 1 input positions without replacement, in position order
+        LAUNCH(k_ran_positions, dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, (u64)prm->seed, n, ns, P.rpos);
+        LAUNCH_OK();
+        const Opts ou = opts_for<u32>(prm);
+        rc = block_sort<u32, false>(P.rs, P.rpos, nullptr, BSPS_DT_NONE, P.spos, nullptr, BSPS_DT_NONE, P.rpos_scr,
+                                    nullptr, ns, 1, ou.cap, ou.tavg, nullptr, 1, 1, st);
+        if (rc) return rc;
+        LAUNCH((k_gather_sample_in<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, io, dt, P.spos, ns, P.skey);
+        LAUNCH_OK();
+        // steps 5-6: sample sorted by (key, position), splitters at ranks s, 2s, ...
+        rc = block_sort<K, true>(P.ss, P.skey, P.spos, BSPS_DT_NONE, P.ssk, P.ssp, BSPS_DT_NONE, P.sscr, P.sscrv, ns, 1,
+                                 o.cap, o.tavg, nullptr, 1, 1, st);
+        if (rc) return rc;
+        LAUNCH((k_splitters<K>), dim3((u32)cdiv(p, 256)), dim3(256), 0, st, P.ssk, P.ssp, p, s, P.pk, P.pp);
+        LAUNCH_OK();
+        if (prm->untagged) {
+            LAUNCH(k_fill_u32, dim3((u32)cdiv(p, 256)), dim3(256), 0, st, P.pcmp, p, 0xFFFFFFFFu);
+            LAUNCH_OK();
+        }
+    }
+    {
+        // step 9: the bucket of every input record, and the counts C[k][i]
+        StageScope sc(ST_COUNT, st);
+        if (learned && ns > 0) {
+            const int L = prm->leaves > 0 ? prm->leaves : 4096;
+            rc = fit_model<K>(P.ssk, ns, BSPS_DT_NONE, p, s, L, 1, P.model, P.fitws, st);
+            if (rc) return rc;
+        }
+        LAUNCH(k_zero_u32, dim3((u32)cdiv(lstats_off(p) + 4, 256)), dim3(256), 0, st, P.C, (int)(lstats_off(p) + 4));
+        LAUNCH_OK();
+        StageScope sk(ST_RANK_K, st);
+        unsigned long long* lst = (unsigned long long*)(P.C + lstats_off(p));
+        if (learned && ns > 0)
+            rc = launch_rank<K, true>(io, n, p, P.pk, P.pcmp, dt, BSPS_DT_NONE, P.model, P.bucket, P.C, lst, st);
+        else
+            rc = launch_rank<K, false>(io, n, p, P.pk, P.pcmp, dt, BSPS_DT_NONE, nullptr, P.bucket, P.C, nullptr, st);
+        if (rc) return rc;
+    }
+    {
+        // steps 10-11: the p prefix computations, then the order-preserving route
+        StageScope sc(ST_TABLES, st);
+        LAUNCH(k_counts_to_cntT, dim3(p), dim3(256), 0, st, P.C, p, P.cntT);
+        LAUNCH_OK();
+        LAUNCH(k_route_offsets, dim3(p), dim3(256), 0, st, P.C, P.cntT, p, P.off);
+        LAUNCH_OK();
+        static int occ = -1;
+        if (!t_dry && occ < 0 &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_route_sr<K, HASV>, SR_NT, 0) != hipSuccess)
+            occ = 0;
+        const u32 grid = (u32)std::max<i64>(1, std::min<i64>(p, (i64)device_cus() * std::max(occ, 1)));
+        const int dbits = std::max(1, (int)bitw((u64)(p - 1)));
+        LAUNCH((k_route_sr<K, HASV>), dim3(grid), dim3(SR_NT), 0, st, (const K*)io, (const u32*)vals, dt,
+               (const u32*)P.bucket, n, p, dbits, (const u32*)P.off, P.B, P.Bv);
+        LAUNCH_OK();
+    }
+    if (stats && stats->routed) {
+        rc = copy_keys_out<K>(stats->routed, P.B, n, dt, st);
+        if (rc) return rc;
+    }
+    if (stats && stats->buckets) {
+        rc = d2h(stats->buckets, P.bucket, 4 * (size_t)n, st);
+        if (rc) return rc;
+    }
+    {
+        // step 12: every bucket sorted stably: Z -> the caller's buffer, raw keys.
+        // Bucket i of Z starts at off[0][i] (block 0's run of it).
+        StageScope sc(ST_BUCKET_MERGE, st);
+        LsdArgs<K> a{};
+        a.in = P.B; a.inv = P.Bv; a.in_dt = BSPS_DT_NONE;
+        a.a = P.bs.A; a.av = P.bs.Av; a.b = P.B; a.bv = P.Bv;
+        a.out = io; a.outv = vals;
+        a.n = n; a.p = p; a.tpb = 0;
+        a.dbase = P.dbase; a.plist = P.plist;
+        a.smp = nullptr; a.ys = 1; a.spb = 0;
+        a.blk = P.off;
+        a.out_dt = dt;
+        rc = lsd_launch<K, HASV>(a, P.lsw, st);
+        if (rc) return rc;
+    }
+    if (stats) {
+        HIP_OK(hipStreamSynchronize(st));
+        rc = sweep_overruns(P.lsw, st);
+        if (rc) return rc;
+        rc = copy_keys_out<K>(stats->splitter_keys, P.pk, p - 1, dt, st);
+        if (rc) return rc;
+        rc = copy_u32_to_i64(stats->splitter_pos, P.pp, p - 1, st);
+        if (rc) return rc;
+        rc = copy_keys_out<K>(stats->sample_keys, P.ssk, ns, dt, st);
+        if (rc) return rc;
+        rc = copy_u32_to_i64(stats->sample_pos, P.ssp, ns, st);
+        if (rc) return rc;
+        std::vector<u32> ct((size_t)(p + 1) * p);
+        rc = d2h(ct.data(), P.cntT, 4 * ct.size(), st);
+        if (rc) return rc;
+        double mx = 0;
+        for (int i = 0; i < p; i++) {
+            i64 bsz = 0;
+            for (int k = 0; k < p; k++) {
+                const i64 cki = (i64)ct[(size_t)(i + 1) * p + k] - (i64)ct[(size_t)i * p + k];
+                if (stats->count_matrix) stats->count_matrix[(size_t)k * p + i] = cki;
+                bsz += cki;
+            }
+            if (stats->bucket_sizes) stats->bucket_sizes[i] = bsz;
+            mx = std::max(mx, (double)bsz);
+        }
+        stats->max_bucket_ratio = mx / ((double)n / p);
+        stats->oversize_chunks = 0;
+        if (learned) {
+            unsigned long long ls[2];
+            rc = d2h(ls, P.C + lstats_off(p), 16, st);
+            if (rc) return rc;
+            stats->mispredict_rate = (double)ls[0] / (double)n;
+            stats->mean_fix_dist = (double)ls[1] / (double)n;
+        }
+    }
+    return BSPS_OK;
+}
+
+// The iterative version of Sort_Det_BSP (Section 5.1), after the local sort
+// (B, block samples): m rounds, each splitting every group into k sub-buckets
+// and merging every processor's share of them. Round r reads the array the
+// previous round wrote (B, then A and B in turn) and the last round writes
+// raw keys into the caller's buffer; between rounds that buffer is the
+// oversize-chunk scratch of the merge.
+template <typename K, bool HASV>
+bsps_status run_iter(Plan<K>& P, K* io, u32* vals, i64 n, int dt, const bsps_params* prm, const Opts& o,
+                     hipStream_t st, bsps_stats* stats) {
+    const int p = prm->p, s = prm->s, m = P.m, k = P.k;
+    const i64 ns = (i64)p * s;
+    bsps_status rc;
+    LAUNCH(k_it_groups_init, dim3(1), dim3(64), 0, st, P.grp0, n);
+    LAUNCH_OK();
+    const K* src = P.B;
+    const u32* srcv = P.Bv;
+    const K* smp_in = P.bsmp;
+    u32 spb_in = std::max<u32>(1, P.spb);
+    u32* grp = P.grp0;
+    u32* ngrp = P.grp1;
+    int G = 1;
+    u32 ctr[4] = {0, 0, 0, 0};
+    for (int r = 0; r < m; r++) {
+        const int q = p / G;
+        const bool last = r == m - 1, even = r % 2 == 0;
+        K* dst = last ? io : (even ? P.bs.A : P.B);
+        u32* dstv = last ? vals : (even ? P.bs.Av : P.Bv);
+        K* scr = last ? (even ? P.bs.A : P.B) : io;
+        u32* scrv = last ? (even ? P.bs.Av : P.Bv) : vals;
+        K* smp_out = last ? nullptr : (even ? P.itsmp0 : P.itsmp1);
+        K* pk = P.pk + (G - 1);  // round r's splitters follow the k^r - 1 of earlier rounds
+        u32* pp = P.pp + (G - 1);
+        {
+            StageScope sc(ST_SAMPLE, st);
+            // regular sample of every share, sorted group by group, k - 1 splitters per group
+            LAUNCH((k_it_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, src, n, (const u32*)grp, q, s, ns,
+                   P.skey, P.spos);
+            LAUNCH_OK();
+            rc = block_sort<K, true>(P.its[r], P.skey, P.spos, BSPS_DT_NONE, P.ssk, P.ssp, BSPS_DT_NONE, P.sscr,
+                                     P.sscrv, ns, G, o.cap, o.tavg, nullptr, 1, 1, st);
+            if (rc) return rc;
+            LAUNCH((k_it_splitters<K>), dim3((u32)cdiv((u64)G * (k - 1), 256)), dim3(256), 0, st,
+                   (const K*)P.ssk, (const u32*)P.ssp, G, q, s, k, pk, pp);
+            LAUNCH_OK();
+        }
+        if (stats && r == 0) {
+            rc = copy_keys_out<K>(stats->sample_keys, P.ssk, ns, dt, st);
+            if (rc) return rc;
+            rc = copy_u32_to_i64(stats->sample_pos, P.ssp, ns, st);
+            if (rc) return rc;
+        }
+        {
+            StageScope sc(ST_COUNT, st);
+            LAUNCH((k_it_count<K>), dim3((u32)cdiv((u64)(k + 1) * p, 256)), dim3(256), 0, st, src,
+                   (const u32*)grp, p, q, k, (const K*)pk, (const u32*)pp, P.cntT);
+            LAUNCH_OK();
+        }
+        if (stats && stats->count_matrix) {
+            std::vector<u32> ct((size_t)(k + 1) * p);
+            rc = d2h(ct.data(), P.cntT, 4 * ct.size(), st);
+            if (rc) return rc;
+            for (int P_ = 0; P_ < p; P_++)
+                for (int b = 0; b < k; b++)
+                    stats->count_matrix[((size_t)r * p + P_) * k + b] =
+                        (i64)ct[(size_t)(b + 1) * p + P_] - (i64)ct[(size_t)b * p + P_];
+        }
+        {
+            StageScope sc(ST_TABLES, st);
+            LAUNCH(k_it_tables, dim3((u32)(G * k)), dim3(IT_NT), 0, st, (const u32*)grp, G, p, q, k,
+                   (const u32*)P.cntT, kSampleStride, spb_in, ngrp, P.bm.run_start, P.bm.run_len, P.bm.out_base,
+                   P.bm.sdesc);
+            LAUNCH_OK();
+        }
+        {
+            StageScope sc(ST_BUCKET_MERGE, st);
+            MwmArgs<K> a = mwm_args<K>(P.bm, src, srcv, dst, dstv, scr, scrv, smp_in, o.cap, o.tavg,
+                                       last ? dt : BSPS_DT_NONE, smp_out, kSampleStride, P.itspb);
+            a.R = q;  // run slot j of every share: the piece of source share j of its group
+            rc = mwm_run<K, HASV>(a, st, ST_BUCKET_MERGE_K);
+            if (rc) return rc;
+        }
+        if (stats) {
+            u32 c4[4];
+            rc = d2h(c4, P.bm.counters, 16, st);
+            if (rc) return rc;
+            ctr[1] += c4[1];
+            ctr[3] = std::max(ctr[3], c4[3]);
+        }
+        src = dst;
+        srcv = dstv;
+        smp_in = smp_out;
+        spb_in = P.itspb;
+        std::swap(grp, ngrp);
+        G *= k;
+    }
+    if (stats) {
+        HIP_OK(hipStreamSynchronize(st));
+        rc = copy_keys_out<K>(stats->splitter_keys, P.pk, p - 1, dt, st);
+        if (rc) return rc;
+        rc = copy_u32_to_i64(stats->splitter_pos, P.pp, p - 1, st);
+        if (rc) return rc;
+        std::vector<u32> g((size_t)p + 1);
+        rc = d2h(g.data(), grp, 4 * g.size(), st);
+        if (rc) return rc;
+        double mx = 0;
+        for (int i = 0; i < p; i++) {
+            const i64 bsz = (i64)g[i + 1] - (i64)g[i];
+            if (stats->bucket_sizes) stats->bucket_sizes[i] = bsz;
+            mx = std::max(mx, (double)bsz);
+        }
+        stats->max_bucket_ratio = mx / ((double)n / p);
+        u32 ctr2[4] = {0, 0, 0, 0};
+        if (!P.lsd && P.bs.tpb > 1) {
+            rc = d2h(ctr2, P.bs.mwm.counters, 16, st);
+            if (rc) return rc;
+        }
+        stats->oversize_chunks = (i64)ctr[1] + (i64)ctr2[1];
+        stats->reserved_i[0] = ctr2[1];                         // block merge
+        stats->reserved_i[1] = ctr[1];                          // the rounds' merges
+        stats->reserved_i[2] = (i64)std::max(ctr[3], ctr2[3]);  // largest oversize chunk
+    }
+    return BSPS_OK;
+}
+
 template <typename K, bool HASV>
 bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* prm, void* ws, size_t ws_bytes,
                      hipStream_t st, bsps_stats* stats) {
+    if (prm->variant == BSPS_RAN_SR) return run_sort_sr<K, HASV>(keys, vals, n, dt, prm, ws, ws_bytes, st, stats);
     const int p = prm->p, s = prm->s;
     Carver c(ws);
     Plan<K> P{};
@@ -803,13 +1220,17 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
     bsps_status rc;
     // A1: every virtual processor sorts its block (stable).
     if (P.lsd)
-        rc = lsd_block_sort<K, HASV>(io, vals, dt, P.bs.A, P.bs.Av, P.B, P.Bv, P.dbase, P.plist, n, p, P.bs.tpb,
+        rc = lsd_block_sort<K, HASV>(io, vals, dt, P.bs.A, P.bs.Av, P.B, P.Bv, P.dbase, P.plist, P.lsw, n, p, P.bs.tpb,
                                      P.bsmp, kSampleStride, P.spb, st);
     else
         rc = block_sort<K, HASV>(P.bs, io, vals, dt, P.B, P.Bv, BSPS_DT_NONE, io, vals, n, p, o.cap, o.tavg, P.bsmp,
                                  kSampleStride, std::max<u32>(1, P.spb), st, ST_TILE, ST_BLOCK_MERGE,
                                  ST_BLOCK_MERGE_K);
     if (rc) return rc;
+    if (stats && P.lsd) {
+        rc = sweep_overruns(P.lsw, st);
+        if (rc) return rc;
+    }
     if (stats && stats->block_sorted) {
         rc = copy_keys_out<K>(stats->block_sorted, P.B, n, dt, st);
         if (rc) return rc;
@@ -830,6 +1251,7 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         }
         return BSPS_OK;
     }
+    if (P.m >= 2) return run_iter<K, HASV>(P, io, vals, n, dt, prm, o, st, stats);
     const i64 ns = P.ns;
     {
         StageScope sc(ST_SAMPLE, st);
@@ -856,16 +1278,21 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         if (rc) return rc;
         LAUNCH((k_splitters<K>), dim3((u32)cdiv(p, 256)), dim3(256), 0, st, P.ssk, P.ssp, p, s, P.pk, P.pp);
         LAUNCH_OK();
+        if (prm->untagged) {
+            // duplicate handling switched off: every splitter compares as (key, +inf)
+            LAUNCH(k_fill_u32, dim3((u32)cdiv(p, 256)), dim3(256), 0, st, P.pcmp, p, 0xFFFFFFFFu);
+            LAUNCH_OK();
+        }
     }
     // A4: bucket boundaries inside every sorted block (splitters searched into it).
     {
         StageScope sc(ST_COUNT, st);
         const u64 ncnt = (u64)(p + 1) * p;
         if (P.spb > 0 && P.spb <= (u32)COUNT_SMAX)
-            LAUNCH((k_count_staged<K>), dim3(p), dim3(COUNT_NT), 0, st, P.B, n, p, P.pk, P.pp, P.bsmp, P.spb,
+            LAUNCH((k_count_staged<K>), dim3(p), dim3(COUNT_NT), 0, st, P.B, n, p, P.pk, P.pcmp, P.bsmp, P.spb,
                    kSampleStride, P.cntT);
         else
-            LAUNCH((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pp, P.cntT);
+            LAUNCH((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pcmp, P.cntT);
         LAUNCH_OK();
     }
     if (prm->route == BSPS_ROUTE_FUSED) {
@@ -909,12 +1336,12 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
                 typedef RankShape<true> RS;
                 const int wpb = (int)std::max<i64>(1, cdiv((u64)device_cus() * RS::WG_PER_CU * 2, (u64)p));
                 LAUNCH((k_scatter_rank<K, true, HASV>), dim3((u32)(p * wpb)), dim3(RS::NT), 0, st, P.B, P.Bv, n, p,
-                       wpb, P.pk, P.pp, (const void*)P.model, P.cntT, P.off, P.bs.A, P.bs.Av, bids, lst);
+                       wpb, P.pk, P.pcmp, (const void*)P.model, P.cntT, P.off, P.bs.A, P.bs.Av, bids, lst);
             } else {
                 typedef RankShape<false> RS;
                 const int wpb = (int)std::max<i64>(1, cdiv((u64)device_cus() * RS::WG_PER_CU * 2, (u64)p));
                 LAUNCH((k_scatter_rank<K, false, HASV>), dim3((u32)(p * wpb)), dim3(RS::NT), 0, st, P.B, P.Bv, n,
-                       p, wpb, P.pk, P.pp, (const void*)nullptr, P.cntT, P.off, P.bs.A, P.bs.Av, bids, lst);
+                       p, wpb, P.pk, P.pcmp, (const void*)nullptr, P.cntT, P.off, P.bs.A, P.bs.Av, bids, lst);
             }
             LAUNCH_OK();
         }
@@ -1668,17 +2095,17 @@ bsps_status bsps_rank(const void* keys, int64_t n, int32_t dtype, int32_t p, con
         bsps_status rc;
         if (dtype == BSPS_I64) {
             if (bucketing == BSPS_LEARNED)
-                rc = launch_rank<u64, true>((const u64*)keys, n, p, (const u64*)spl_keys, spl_pos, dtype, model,
+                rc = launch_rank<u64, true>((const u64*)keys, n, p, (const u64*)spl_keys, spl_pos, dtype, dtype, model,
                                             out_bucket, out_counts, lst, s);
             else
-                rc = launch_rank<u64, false>((const u64*)keys, n, p, (const u64*)spl_keys, spl_pos, dtype, model,
+                rc = launch_rank<u64, false>((const u64*)keys, n, p, (const u64*)spl_keys, spl_pos, dtype, dtype, model,
                                              out_bucket, out_counts, lst, s);
         } else {
             if (bucketing == BSPS_LEARNED)
-                rc = launch_rank<u32, true>((const u32*)keys, n, p, (const u32*)spl_keys, spl_pos, dtype, model,
+                rc = launch_rank<u32, true>((const u32*)keys, n, p, (const u32*)spl_keys, spl_pos, dtype, dtype, model,
                                             out_bucket, out_counts, lst, s);
             else
-                rc = launch_rank<u32, false>((const u32*)keys, n, p, (const u32*)spl_keys, spl_pos, dtype, model,
+                rc = launch_rank<u32, false>((const u32*)keys, n, p, (const u32*)spl_keys, spl_pos, dtype, dtype, model,
                                              out_bucket, out_counts, lst, s);
         }
         if (rc) return rc;
@@ -1715,7 +2142,6 @@ bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int3
     Carver c(ws);
     FitWs f = carve_fit(c, N, leaves);
     const u32 gN = (u32)std::max<u64>(1, cdiv((u64)N, 256));
-    const u32 gM = (u32)cdiv((u64)leaves + 1, 256);
     if (dtype == BSPS_I64)
         LAUNCH((k_model_x<u64>), dim3(gN), dim3(256), 0, st, (const u64*)smp_keys, N, dtype, model, 1,
                            f.x, out_leaf);
@@ -1723,12 +2149,12 @@ bsps_status bsps_model_grad(const void* smp_keys, int64_t N, int32_t dtype, int3
         LAUNCH((k_model_x<u32>), dim3(gN), dim3(256), 0, st, (const u32*)smp_keys, N, dtype, model, 1,
                            f.x, out_leaf);
     LAUNCH_OK();
-    LAUNCH(k_model_ranges, dim3(gM), dim3(256), 0, st, out_leaf, N, leaves, f.lo);
+    // leaf ranges and the forward / backward pass of the fit, at the given parameters
+    LAUNCH(k_fit_ranges, dim3((u32)cdiv((u64)N + 1, 256)), dim3(256), 0, st, (const float*)f.x, N, model, leaves,
+           f.lo);
     LAUNCH_OK();
-    LAUNCH(k_model_forward, dim3(gN), dim3(256), 0, st, f.x, out_leaf, N, p, s, model, 1, f.r);
-    LAUNCH_OK();
-    LAUNCH(k_model_backward<64>, dim3(leaves), dim3(64), 0, st, f.x, f.r, f.lo, leaves, N, model, 1,
-                       out_grad, out_gram, f.lossp);
+    LAUNCH(k_grad_leaves, dim3((u32)cdiv((u64)leaves, FIT_LEAF_NT / 64)), dim3(FIT_LEAF_NT), 0, st,
+           (const float*)f.x, (const int32_t*)f.lo, N, leaves, p, s, model, out_grad, out_gram, f.lossp);
     LAUNCH_OK();
     LAUNCH(k_sum_loss, dim3(1), dim3(256), 0, st, f.lossp, leaves, N, out_loss);
     LAUNCH_OK();

@@ -103,7 +103,8 @@ struct MwmArgs {
     uint4* gpar;           // [2G] per listed group: {f, Sg, q, dsh}, {N, 0, 0, 0} (see k_mwm_size)
     u32 S;                 // slot capacity
     int out_dt;            // BSPS_DT_NONE: keep order keys; else write raw keys of this dtype
-    K* osmp;               // output samples every oys-th key of each group (or NULL)
+    K* osmp;               // output samples every oys-th key of each group (or NULL), at most
+                           // ospb per group (later ones are not written)
     u32 oys, ospb;
 };
 
@@ -160,6 +161,11 @@ __global__ void k_block_tables(i64 n, int p, int tpb, u32 T, u32 ys, u32 spt, u3
 __global__ void k_zero_u32(u32* p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
+}
+
+__global__ void k_fill_u32(u32* p, int n, u32 v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ======================================================================= tile sort
@@ -737,7 +743,7 @@ template <typename K, bool HASV>
 __device__ void mwm_emit(const MwmArgs<K>& a, u32 g, u32 o, K u, u32 gstart) {
     if (a.osmp) {
         const u32 rel = o - gstart + 1;
-        if ((rel & (a.oys - 1)) == 0) a.osmp[(i64)g * a.ospb + rel / a.oys - 1] = u;
+        if ((rel & (a.oys - 1)) == 0 && rel / a.oys <= a.ospb) a.osmp[(i64)g * a.ospb + rel / a.oys - 1] = u;
     }
 }
 
@@ -1098,8 +1104,10 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
     auto emit_samples = [&](auto* e) {
         if (a.osmp) {
             const u32 step = om + 1, first = (gstart - out - 1) & om;
-            for (u32 i = first + (u32)t * step; i < N; i += (u32)NT * step)
-                a.osmp[(i64)g * a.ospb + ((out + i - gstart + 1) >> osh) - 1] = (K)e[padi((int)i)] + mn;
+            for (u32 i = first + (u32)t * step; i < N; i += (u32)NT * step) {
+                const u32 si = (out + i - gstart + 1) >> osh;  // 1-based sample number in the group
+                if (si <= a.ospb) a.osmp[(i64)g * a.ospb + si - 1] = (K)e[padi((int)i)] + mn;
+            }
         }
     };
     if (sizeof(K) == 8 && nbits > 32) {

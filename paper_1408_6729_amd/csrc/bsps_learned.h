@@ -72,23 +72,6 @@ template <bool LEARNED> constexpr int rank_tile() { return RankShape<LEARNED>::N
 
 // ---------------------------------------------------------------- training
 
-// Header: range of the sorted sample (order keys) and the model's shape.
-template <typename K>
-__global__ void k_model_init(const K* smp, i64 N, int dt, int p, int s, int L, void* model) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    ModelHdr* h = (ModelHdr*)model;
-    const K lo = N > 0 ? okey<K>(smp[0], dt) : (K)0;
-    const K hi = N > 0 ? okey<K>(smp[N - 1], dt) : (K)0;
-    h->lo = (double)lo;
-    h->hi = (double)hi;
-    h->inv = hi > lo ? (float)(1.0 / ((double)hi - (double)lo)) : 0.0f;
-    h->a = h->b = h->mur = 0.0f;
-    h->L = L;
-    h->p = p;
-    h->s = s;
-    h->pad = 0;
-}
-
 // x_t of every sample and the leaf each sample uses at this stage (stage 0:
 // the root, one model; stage 1: leaf chosen by the root).
 template <typename K>
@@ -114,13 +97,6 @@ __global__ void k_model_ranges(const int32_t* leafid, i64 N, int L, int32_t* lo)
     lo[l] = (int32_t)a;
 }
 
-// Parameter views: stage 0 uses the root (a, b, mu_r) as one "leaf"; stage 1
-// the L leaf triples (c, d, mu).
-__device__ __forceinline__ float* stage_params(void* model, int stage) {
-    ModelHdr* h = (ModelHdr*)model;
-    return stage == 0 ? &h->a : (float*)(h + 1);
-}
-
 // Sum over the workgroup (NTR threads, a multiple of 64); every thread gets
 // the total. red: NTR/64 floats of LDS.
 template <int NTR>
@@ -138,110 +114,6 @@ __device__ __forceinline__ float wg_sum(float v, float* red) {
     return acc;
 }
 
-// Leaf centres mu = mean x over each leaf's samples (0 for an empty leaf);
-// parameters start at zero. One workgroup of NTR threads per model.
-template <int NTR>
-__global__ __launch_bounds__(NTR) void k_model_centres(const float* x, const int32_t* lo, int nmod, void* model,
-                                                         int stage) {
-    __shared__ float red[NTR / 64];
-    const int l = blockIdx.x;
-    if (l >= nmod) return;
-    float* q = stage_params(model, stage);
-    const int32_t a = lo[l], b = lo[l + 1];
-    float sx = 0.0f;
-    for (int32_t t = a + (int32_t)threadIdx.x; t < b; t += NTR) sx += x[t];
-    sx = wg_sum<NTR>(sx, red);
-    if (threadIdx.x != 0) return;
-    const float mu = b > a ? sx / (float)(b - a) : 0.0f;
-    if (stage == 0) {
-        q[0] = 0.0f; q[1] = 0.0f; q[2] = mu;   // a, b, mu_r
-    } else {
-        q[3 * l] = 0.0f; q[3 * l + 1] = 0.0f; q[3 * l + 2] = mu;
-    }
-}
-
-__device__ __forceinline__ void stage_get(const float* q, int stage, int l, float& c, float& d, float& mu) {
-    if (stage == 0) { c = q[0]; d = q[1]; mu = q[2]; }
-    else { c = q[3 * l]; d = q[3 * l + 1]; mu = q[3 * l + 2]; }
-}
-
-// Forward: residual r_t = f(x_t) - y_t of every sample under its model.
-__global__ void k_model_forward(const float* x, const int32_t* leafid, i64 N, int p, int s, const void* model,
-                                int stage, float* r) {
-    const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N) return;
-    const float* q = stage_params(const_cast<void*>(model), stage);
-    float c, d, mu;
-    stage_get(q, stage, leafid[t], c, d, mu);
-    const float y = ((float)t + 0.5f) / ((float)p * (float)s);
-    r[t] = c * (x[t] - mu) + d - y;
-}
-
-// Backward: per model, gradient of the loss and the Gram sums (all times 2/N):
-// g = (sum r dx, sum r), h = (sum dx^2, sum dx, count), dx = x - mu; also the
-// model's share of the loss sum r^2. One workgroup of NTR threads per model,
-// partial sums per thread then a tree over the workgroup.
-template <int NTR>
-__global__ __launch_bounds__(NTR) void k_model_backward(const float* x, const float* r, const int32_t* lo, int nmod,
-                                                          i64 N, const void* model, int stage, float* g, float* hs,
-                                                          float* lossp) {
-    __shared__ float red[NTR / 64];
-    const int l = blockIdx.x;
-    if (l >= nmod) return;
-    const float* q = stage_params(const_cast<void*>(model), stage);
-    float c, d, mu;
-    stage_get(q, stage, l, c, d, mu);
-    float s_rx = 0, s_r = 0, s_xx = 0, s_x = 0, s_rr = 0;
-    const int32_t a = lo[l], b = lo[l + 1];
-    for (int32_t t = a + (int32_t)threadIdx.x; t < b; t += NTR) {
-        const float dx = x[t] - mu, rv = r[t];
-        s_rx += rv * dx;
-        s_r += rv;
-        s_xx += dx * dx;
-        s_x += dx;
-        s_rr += rv * rv;
-    }
-    s_rx = wg_sum<NTR>(s_rx, red);
-    s_r = wg_sum<NTR>(s_r, red);
-    s_xx = wg_sum<NTR>(s_xx, red);
-    s_x = wg_sum<NTR>(s_x, red);
-    s_rr = wg_sum<NTR>(s_rr, red);
-    if (threadIdx.x != 0) return;
-    const float sc = N > 0 ? 2.0f / (float)N : 0.0f;
-    g[2 * l] = s_rx * sc;
-    g[2 * l + 1] = s_r * sc;
-    hs[3 * l] = s_xx * sc;
-    hs[3 * l + 1] = s_x * sc;
-    hs[3 * l + 2] = (float)(b - a) * sc;
-    lossp[l] = s_rr;
-}
-
-// Update: one Newton step per model (exact for a quadratic loss); a singular
-// Gram matrix moves only the intercept; a model without samples keeps c = 0
-// and predicts the fraction of samples below it.
-__global__ void k_model_update(const float* g, const float* hs, const int32_t* lo, int nmod, int p, int s,
-                               void* model, int stage) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= nmod) return;
-    float* q = stage_params(model, stage);
-    float* c = stage == 0 ? &q[0] : &q[3 * l];
-    float* d = stage == 0 ? &q[1] : &q[3 * l + 1];
-    const float sxx = hs[3 * l], sx = hs[3 * l + 1], sn = hs[3 * l + 2];
-    if (sn <= 0.0f) {
-        *c = 0.0f;
-        *d = (float)lo[l] / ((float)p * (float)s);
-        return;
-    }
-    const float det = sxx * sn - sx * sx;
-    if (sxx > 0.0f && det > 1e-6f * sxx * sn) {
-        *c -= (sn * g[2 * l] - sx * g[2 * l + 1]) / det;
-        *d -= (-sx * g[2 * l] + sxx * g[2 * l + 1]) / det;
-    } else {
-        *d -= g[2 * l + 1] / sn;
-    }
-}
-
-// Root fitted: copy (a, b, mu_r) stays in the header; nothing else to do.
 // Loss = (sum of the models' r^2 shares) / N; one workgroup of 256 threads.
 __global__ __launch_bounds__(256) void k_sum_loss(const float* lossp, int nmod, i64 N, float* out) {
     __shared__ float red[4];
@@ -285,10 +157,11 @@ struct SplitLds<u64> {
 // the two neighbouring splitters, walking to the true bucket when the
 // prediction is off. Counts: lanes holding a run of equal buckets add its
 // length once.
+// dt: dtype of the keys, sdt: of the splitter keys (BSPS_DT_NONE: order keys).
 template <typename K, bool LEARNED>
 __global__ __launch_bounds__(RankShape<LEARNED>::NT) void k_rank(const K* B, i64 n, int p, int tpb, const K* spk,
-                                                                     const u32* spp, int dt, const void* model,
-                                                                     u32* bucket, u32* counts,
+                                                                     const u32* spp, int dt, int sdt,
+                                                                     const void* model, u32* bucket, u32* counts,
                                                                      unsigned long long* lstats) {
     constexpr int NT = RankShape<LEARNED>::NT, TILE = NT * RANK_IT;
     __shared__ SplitLds<K> S;
@@ -299,7 +172,7 @@ __global__ __launch_bounds__(RankShape<LEARNED>::NT) void k_rank(const K* B, i64
     int P2 = 1;
     while (P2 < p) P2 <<= 1;
     for (int i = t; i < P2; i += NT) {
-        if (i < p - 1) S.set(i, okey<K>(spk[i], dt), spp[i]);
+        if (i < p - 1) S.set(i, okey<K>(spk[i], sdt), spp[i]);
         else S.set_inf(i);
         if (i < p) hist[i] = 0;
     }
@@ -501,5 +374,187 @@ __global__ __launch_bounds__(256) void k_route_offsets_T(const u32* cntT, int p,
     for (int k = t * per; k < (t + 1) * per && k < p; k++) {
         off[(i64)k * p + i] = base + ex;
         ex += cntT[(i64)(i + 1) * p + k] - cntT[(i64)i * p + k];
+    }
+}
+
+// The fit in three launches (the same forward residuals, backward gradient
+// and Gram sums times 2/N, and Newton update as the kernels above, `iters`
+// steps per stage): the root on one workgroup of FIT_NT threads, which also
+// writes x of every record; the first record of every leaf; then every leaf
+// on one wave (its lanes split the leaf's records and reduce by shuffles).
+// An empty leaf takes c = 0 and d = (records below it) / (p s).
+constexpr int FIT_NT = 1024;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One Newton step of a linear model from its gradient (gc, gd) and Gram sums
+// (sxx, sx, sn), all times 2/N (exact for the quadratic loss): a singular Gram
+// matrix moves only the intercept d.
+__device__ __forceinline__ void newton_step(float& c, float& d, float gc, float gd, float sxx, float sx, float sn) {
+    const float det = sxx * sn - sx * sx;
+    if (sxx > 0.0f && det > 1e-6f * sxx * sn) {
+        c -= (sn * gc - sx * gd) / det;
+        d -= (-sx * gc + sxx * gd) / det;
+    } else {
+        d -= gd / sn;
+    }
+}
+
+// Forward and backward of one linear model f(x) = c (x - mu) + d over the
+// records [a, b) of the sorted sample this thread takes (first, first +
+// stride, ...): the residual r = f(x_t) - y_t with y_t = (t + 0.5) / (p s),
+// then the partial sums of the gradient (r dx, r), of the Gram matrix (dx^2,
+// dx) and of the loss (r^2), dx = x - mu. The fit and the gradient check
+// (bsps_model_grad) both use it.
+struct FitSums {
+    float rx, r, xx, x, rr;
+};
+
+__device__ __forceinline__ FitSums fit_partials(const float* x, i64 first, i64 b, int stride, float c, float d,
+                                                float mu, float ps) {
+    FitSums f{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (i64 i = first; i < b; i += stride) {
+        const float dx = x[i] - mu;
+        const float r = c * dx + d - ((float)i + 0.5f) / ps;  // forward
+        f.rx += r * dx;                                        // backward
+        f.r += r;
+        f.xx += dx * dx;
+        f.x += dx;
+        f.rr += r * r;
+    }
+    return f;
+}
+
+template <typename K>
+__global__ __launch_bounds__(FIT_NT) void k_fit_root(const K* smp, i64 N, int dt, int p, int s, int L, int iters,
+                                                     void* model, float* x) {
+    __shared__ float red[FIT_NT / 64];
+    __shared__ ModelHdr sh;
+    const int t = threadIdx.x;
+    ModelHdr* h = (ModelHdr*)model;
+    if (t == 0) {
+        const K klo = N > 0 ? okey<K>(smp[0], dt) : (K)0;
+        const K khi = N > 0 ? okey<K>(smp[N - 1], dt) : (K)0;
+        sh.lo = (double)klo;
+        sh.hi = (double)khi;
+        sh.inv = khi > klo ? (float)(1.0 / ((double)khi - (double)klo)) : 0.0f;
+        sh.a = sh.b = sh.mur = 0.0f;
+        sh.L = L;
+        sh.p = p;
+        sh.s = s;
+        sh.pad = 0;
+    }
+    __syncthreads();
+    const float ps = (float)p * (float)s;
+    const float sc = N > 0 ? 2.0f / (float)N : 0.0f;
+    float sx = 0.0f;
+    for (i64 i = t; i < N; i += FIT_NT) {
+        const float xv = model_x<K>(okey<K>(smp[i], dt), sh);
+        x[i] = xv;
+        sx += xv;
+    }
+    sx = wg_sum<FIT_NT>(sx, red);
+    const float mur = N > 0 ? sx / (float)N : 0.0f;
+    float ra = 0.0f, rb = 0.0f;
+    for (int it = 0; it < iters; it++) {
+        const FitSums f = fit_partials(x, t, N, FIT_NT, ra, rb, mur, ps);
+        const float s_rx = wg_sum<FIT_NT>(f.rx, red), s_r = wg_sum<FIT_NT>(f.r, red);
+        const float s_xx = wg_sum<FIT_NT>(f.xx, red), s_x = wg_sum<FIT_NT>(f.x, red);
+        if (N > 0) newton_step(ra, rb, s_rx * sc, s_r * sc, s_xx * sc, s_x * sc, (float)N * sc);
+    }
+    if (t == 0) {
+        h->lo = sh.lo;
+        h->hi = sh.hi;
+        h->inv = sh.inv;
+        h->a = ra;
+        h->b = rb;
+        h->mur = mur;
+        h->L = L;
+        h->p = p;
+        h->s = s;
+        h->pad = 0;
+    }
+}
+
+// lo[l] = first record of leaf l (l = 0..L; lo[L] = N). The root's leaf never
+// decreases along the sorted sample, so record i starts every leaf in
+// (leaf(i-1), leaf(i)]; one thread per record boundary i = 0..N. Leaf ids are
+// capped at L, so only lo[0..L] is written whatever the model holds.
+__global__ void k_fit_ranges(const float* x, i64 N, const void* model, int L, int32_t* lo) {
+    const i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > N) return;
+    const ModelHdr h = *(const ModelHdr*)model;
+    const int a = i > 0 ? min(model_leaf(x[i - 1], h), L) : -1;
+    const int b = i < N ? min(model_leaf(x[i], h), L) : L;
+    for (int l = a + 1; l <= b; l++) lo[l] = (int32_t)i;
+}
+
+constexpr int FIT_LEAF_NT = 256;
+
+__global__ __launch_bounds__(FIT_LEAF_NT) void k_fit_leaves(const float* x, const int32_t* lo, i64 N, int L, int p,
+                                                           int s, int iters, void* model) {
+    const ModelHdr* h = (const ModelHdr*)model;
+    const int lane = threadIdx.x & 63;
+    const int l = blockIdx.x * (FIT_LEAF_NT / 64) + (threadIdx.x >> 6);
+    if (l >= L) return;
+    const float ps = (float)p * (float)s;
+    const float sc = N > 0 ? 2.0f / (float)N : 0.0f;
+    float* q = (float*)(h + 1);
+    // (clamped: with a model whose leaves do not follow the sample order, lo is
+    // not a partition, and the reads must still stay inside the sample)
+    const int32_t a = (int32_t)max((i64)0, min((i64)lo[l], N)), b = (int32_t)max((i64)a, min((i64)lo[l + 1], N));
+    if (b <= a) {
+        if (lane == 0) {
+            q[3 * l] = 0.0f;
+            q[3 * l + 1] = (float)a / ps;
+            q[3 * l + 2] = 0.0f;
+        }
+        return;
+    }
+    float cx = 0.0f;
+    for (int32_t i = a + lane; i < b; i += 64) cx += x[i];
+    const float mu = wave_sum(cx) / (float)(b - a);
+    float c = 0.0f, d = 0.0f;
+    for (int it = 0; it < iters; it++) {
+        const FitSums f = fit_partials(x, a + lane, b, 64, c, d, mu, ps);
+        newton_step(c, d, wave_sum(f.rx) * sc, wave_sum(f.r) * sc, wave_sum(f.xx) * sc, wave_sum(f.x) * sc,
+                    (float)(b - a) * sc);
+    }
+    if (lane == 0) {
+        q[3 * l] = c;
+        q[3 * l + 1] = d;
+        q[3 * l + 2] = mu;
+    }
+}
+
+// Gradient check of the leaf stage (bsps_model_grad): for every leaf, at the
+// model's current parameters, the same forward and backward as the fit, the
+// gradient and Gram sums times 2/N (g[2l], g[2l+1]; hs[3l], hs[3l+1],
+// hs[3l+2] = count times 2/N) and the leaf's share of the loss sum r^2. One
+// wave per leaf.
+__global__ __launch_bounds__(FIT_LEAF_NT) void k_grad_leaves(const float* x, const int32_t* lo, i64 N, int L,
+                                                            int p, int s, const void* model, float* g, float* hs,
+                                                            float* lossp) {
+    const ModelHdr* h = (const ModelHdr*)model;
+    const int lane = threadIdx.x & 63;
+    const int l = blockIdx.x * (FIT_LEAF_NT / 64) + (threadIdx.x >> 6);
+    if (l >= L) return;
+    const float ps = (float)p * (float)s;
+    const float sc = N > 0 ? 2.0f / (float)N : 0.0f;
+    const float* q = (const float*)(h + 1);
+    const int32_t a = (int32_t)max((i64)0, min((i64)lo[l], N)), b = (int32_t)max((i64)a, min((i64)lo[l + 1], N));
+    const FitSums f = fit_partials(x, a + lane, b, 64, q[3 * l], q[3 * l + 1], q[3 * l + 2], ps);
+    const float rx = wave_sum(f.rx), r = wave_sum(f.r), xx = wave_sum(f.xx), xs = wave_sum(f.x), rr = wave_sum(f.rr);
+    if (lane == 0) {
+        g[2 * l] = rx * sc;
+        g[2 * l + 1] = r * sc;
+        hs[3 * l] = xx * sc;
+        hs[3 * l + 1] = xs * sc;
+        hs[3 * l + 2] = (float)(b - a) * sc;
+        lossp[l] = rr;
     }
 }

@@ -41,7 +41,21 @@ struct LsdArgs {
     u32* plist;        // [p][sizeof(K) + 1]: passes c >= 1, then the c digit positions
     K* smp;            // block samples: key at block position (j+1)*ys - 1 -> smp[k*spb + j]
     u32 ys, spb;
+    const u32* blk;    // NULL: block k = [floor(k n/p), floor((k+1) n/p)); else [blk[k], blk[k+1]) (blk[p] = n
+                       // implied), blocks of any sizes, empty ones included
+    int out_dt;        // the last pass writes raw keys of this dtype (BSPS_DT_NONE: order keys)
 };
+
+template <typename K>
+__device__ __forceinline__ void lsd_block(const LsdArgs<K>& a, int k, i64& st, i64& en) {
+    if (a.blk) {
+        st = a.blk[k];
+        en = k + 1 < a.p ? (i64)a.blk[k + 1] : a.n;
+    } else {
+        st = blk_start(a.n, a.p, k);
+        en = blk_start(a.n, a.p, k + 1);
+    }
+}
 
 // Digit counts of every block at every position, their exclusive prefixes and
 // the list of positions the block needs a pass for. One workgroup per block.
@@ -58,7 +72,8 @@ __global__ __launch_bounds__(LSD_HIST_NT) void k_lsd_hist(LsdArgs<K> a) {
         for (int i = t; i < NV; i += NT) h[i] = 0u;
         if (t < DP) trivial[t] = 0u;
         __syncthreads();
-        const i64 st = blk_start(a.n, a.p, k), en = blk_start(a.n, a.p, k + 1);
+        i64 st, en;
+        lsd_block(a, k, st, en);
         auto count = [&](K raw) {
             const K u = okey<K>(raw, a.in_dt);
 #pragma unroll
@@ -135,7 +150,10 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_lsd_pass(LsdAr
         K* dst = last ? a.out : ((pass & 1) ? a.b : a.a);
         u32* dstv = last ? a.outv : ((pass & 1) ? a.bv : a.av);
         const int sdt = first ? a.in_dt : BSPS_DT_NONE;
-        const i64 st = blk_start(a.n, a.p, k), en = blk_start(a.n, a.p, k + 1);
+        const int odt = last ? a.out_dt : BSPS_DT_NONE;
+        i64 st, en;
+        lsd_block(a, k, st, en);
+        if (en <= st) continue;  // an empty block has nothing to move
         if (t < LSD_RADIX) {
             off[t] = (u32)st + a.dbase[((i64)k * DP + pos) * LSD_RADIX + t];
             ts[t] = 0u;
@@ -186,7 +204,7 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_lsd_pass(LsdAr
                     const K u = exch[padj<NT>(j, t)];
                     const u32 d = digit(u);
                     const u32 g = off[d] + ((u32)i - ts[d]);
-                    dst[g] = u;
+                    dst[g] = rawkey<K>(u, odt);
                     if (HASV) dstv[g] = vbuf[padj<NT>(j, t)];
                     if (last && a.smp) {
                         const u32 rel = g - (u32)st + 1u;
@@ -203,5 +221,182 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_lsd_pass(LsdAr
             if (cnt <= 0) break;
         }
         __syncthreads();  // off of this block is no longer read
+    }
+}
+
+// ---------------------------------------------------------------- one sweep per pass, every tile in parallel
+//
+// The same pass with one workgroup per tile instead of one per block: a tile
+// learns where each of its digits goes from the tiles before it in its block
+// by a decoupled look-back. Every tile publishes, per digit, its count (flag
+// A) and, once it knows the sum over all earlier tiles of the block, that
+// inclusive prefix (flag P); a tile sums its predecessors' entries backwards
+// until it meets a P. Tiles take tickets from a counter in the order they
+// start, and a tile only ever waits on tiles with smaller tickets, which have
+// all started before it: the smallest unfinished ticket never waits, so every
+// wait ends. A spin limit bounds each wait all the same (an overrun is
+// counted, and the host reports it as an error).
+constexpr u32 LSD_FA = 1u << 30, LSD_FP = 2u << 30, LSD_CM = (1u << 30) - 1u;
+constexpr int LSD_LB = 8;  // predecessors read per look-back step
+
+struct LsdSweep {
+    u32* status;     // [ntile][256]: 0 (not yet), LSD_FA | count, or LSD_FP | inclusive prefix
+    u32* ctr;        // [0] ticket, [1] waits that hit the spin limit
+    u32* tstart;     // [p + 1] first tile of every block (global tile numbers)
+    u32 ntile;       // grid: at least the number of tiles
+    u32 spin_limit;  // loads per wait before giving up
+};
+
+// tstart[k] = tiles of the blocks before k (a block of m keys has ceil(m/T)
+// tiles, an empty one none). One workgroup; p <= 1024.
+template <typename K>
+__global__ __launch_bounds__(1024) void k_lsd_tiles(LsdArgs<K> a, LsdSweep w) {
+    constexpr int T = Shape<K>::NT * Shape<K>::IT;
+    __shared__ u32 wsum[1024 / 64 + 2];
+    const int k = threadIdx.x;
+    u32 nt = 0;
+    if (k < a.p) {
+        i64 st, en;
+        lsd_block(a, k, st, en);
+        nt = (u32)((en - st + T - 1) / T);
+    }
+    u32 total;
+    const u32 ex = block_excl_scan<1024>(nt, total, wsum);
+    if (k < a.p) w.tstart[k] = ex;
+    if (k == 0) w.tstart[a.p] = total;
+}
+
+template <typename K, bool HASV>
+__global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_lsd_sweep(LsdArgs<K> a, LsdSweep w, int pass) {
+    constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT, T = NT * IT, DP = (int)sizeof(K);
+    __shared__ SortSmem<NT, (int)sizeof(K), IT, true> sm;
+    __shared__ u32 off[LSD_RADIX], ts[LSD_RADIX], te[LSD_RADIX];
+    __shared__ u32 sh_tile;
+    static_assert(SortSmem<NT, (int)sizeof(K), IT, true>::CNTW >= NT * IT + NT * IT / 32, "payload exchange fits");
+    K* exch = sm.template ex<K>();
+    u32* vbuf = sm.cnt();
+    const int t = threadIdx.x, i0 = t * IT;
+    if (t == 0) sh_tile = atomicAdd(&w.ctr[0], 1u);
+    if (t < LSD_RADIX) {
+        ts[t] = 0u;
+        te[t] = 0u;
+    }
+    __syncthreads();
+    const u32 tile = uniform(sh_tile);
+    if (tile >= w.tstart[a.p]) return;  // past the last tile
+    // the block of this tile: the last k with tstart[k] <= tile
+    int lo = 0, hi = a.p - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (w.tstart[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    const int k = uniform(lo);
+    const u32 tt = tile - w.tstart[k];
+    const u32* pl = a.plist + (i64)k * (DP + 1);
+    const int c = (int)uniform(pl[0]);
+    if (pass >= c) return;  // the block needs no pass here (none of its tiles waits)
+    const int pos = (int)uniform(pl[1 + pass]);
+    const int sh = 8 * pos;
+    const bool first = pass == 0, last = pass == c - 1;
+    const K* src = first ? a.in : ((pass & 1) ? a.a : a.b);
+    const u32* srcv = first ? a.inv : ((pass & 1) ? a.av : a.bv);
+    K* dst = last ? a.out : ((pass & 1) ? a.b : a.a);
+    u32* dstv = last ? a.outv : ((pass & 1) ? a.bv : a.av);
+    const int sdt = first ? a.in_dt : BSPS_DT_NONE;
+    const int odt = last ? a.out_dt : BSPS_DT_NONE;
+    i64 st, en;
+    lsd_block(a, k, st, en);
+    const i64 base = st + (i64)tt * T;
+    const int cnt = (int)min((i64)T, en - base);
+    auto digit = [&](K u) { return (u32)(u >> sh) & 255u; };
+    K nk[IT], kr[IT];
+    u32 v[IT], rank[IT];
+    load_blocked<K, IT>(src + base + i0, cnt - i0, nk);
+    const int valid = cnt - i0;
+#pragma unroll
+    for (int j = 0; j < IT; j++) kr[j] = j < valid ? okey<K>(nk[j], sdt) : KeyMax<K>::v;  // padding sorts last
+    if (HASV) load_blocked<u32, IT>(srcv + base + i0, valid, v);
+    wg_sort_regs<NT, IT, K, HASV, true, true>(kr, v, rank, 8, exch, sm.cnt(), sm.wsum, sh);
+    // runs of equal digits in the sorted tile: where each starts and ends
+#pragma unroll 4
+    for (int j = 0; j < IT; j++) {
+        const int i = j * NT + t;
+        if (i < cnt) {
+            const u32 d = digit(exch[padj<NT>(j, t)]);
+            const u32 dp = i > 0 ? digit(exch[padi(i - 1)]) : 256u;
+            if (d != dp) {
+                ts[d] = (u32)i;
+                if (i > 0) te[dp] = (u32)i;
+            }
+            if (i == cnt - 1) te[d] = (u32)cnt;
+        }
+    }
+    if (HASV) {
+        // the counters are free: the payloads go to their final slots there
+#pragma unroll
+        for (int j = 0; j < IT; j++) vbuf[padi((int)rank[j])] = v[j];
+    }
+    __syncthreads();
+    if (t < LSD_RADIX) {
+        // publish this tile's count of digit t, then look back for the sum
+        // over the earlier tiles of the block
+        const u32 mine = te[t] - ts[t];
+        u32* sp = w.status + (u64)tile * LSD_RADIX + t;
+        u32 before = 0;
+        if (tt == 0) {
+            __hip_atomic_store(sp, LSD_FP | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(sp, LSD_FA | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // look back LSD_LB tiles at a time (their loads in flight together):
+            // add ready counts from the nearest tile on, up to a prefix; a tile
+            // that is not ready yet is read again
+            const u32 first_tile = w.tstart[k];
+            u32 j = tile;  // tiles j, j+1, ..., tile-1 are summed into `before`
+            u32 spins = 0;
+            bool done = false;
+            while (!done) {
+                const u32 nw = min((u32)LSD_LB, j - first_tile);
+                u32 sv[LSD_LB];
+#pragma unroll
+                for (int q = 0; q < LSD_LB; q++)
+                    sv[q] = (u32)q < nw ? __hip_atomic_load(w.status + (u64)(j - 1 - q) * LSD_RADIX + t,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                        : 0u;
+                u32 q = 0;
+                for (; q < nw; q++) {
+                    const u32 f = sv[q] & ~LSD_CM;
+                    if (f == 0u) break;  // not ready yet
+                    before += sv[q] & LSD_CM;
+                    if (f == LSD_FP) {
+                        done = true;
+                        break;
+                    }
+                }
+                if (done) break;
+                j -= q;
+                if (q == 0 && ++spins > w.spin_limit) {
+                    atomicAdd(&w.ctr[1], 1u);
+                    break;
+                }
+            }
+            __hip_atomic_store(sp, LSD_FP | (before + mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        off[t] = (u32)st + a.dbase[((i64)k * DP + pos) * LSD_RADIX + t] + before;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int j = 0; j < IT; j++) {
+        const int i = j * NT + t;
+        if (i < cnt) {
+            const K u = exch[padj<NT>(j, t)];
+            const u32 d = digit(u);
+            const u32 g = off[d] + ((u32)i - ts[d]);
+            dst[g] = rawkey<K>(u, odt);
+            if (HASV) dstv[g] = vbuf[padj<NT>(j, t)];
+            if (last && a.smp) {
+                const u32 rel = g - (u32)st + 1u;
+                if ((rel & (a.ys - 1)) == 0 && rel / a.ys <= a.spb) a.smp[(i64)k * a.spb + rel / a.ys - 1] = u;
+            }
+        }
     }
 }

@@ -45,6 +45,13 @@ def _call(bsps, n, dtype, prm, ws=None, ws_bytes=0, keys=1):
     dict(n=-1, p=1, s=1), dict(n=10, p=0, s=1), dict(n=10, p=11, s=1), dict(n=10, p=2, s=0),
     dict(n=10, p=2, s=6, variant=1), dict(n=10, p=2, s=1, variant=7), dict(n=10, p=2, s=1, route=5),
     dict(n=10, p=2, s=1, bucketing=3), dict(n=10, p=2, s=1, leaves=-1), dict(n=10, p=2, s=1, dtype=9),
+    dict(n=10, p=2, s=6, variant=2), dict(n=10, p=2, s=1, variant=2, route=1), dict(n=10, p=2, s=1, variant=3),
+    dict(n=10, p=2, s=1, local_sort=3),
+    # iterative rounds: p must be k^m (k >= 2), DET, fused route, splitter search, tagged, m <= 10
+    dict(n=100, p=12, s=1, rounds=2), dict(n=100, p=8, s=1, rounds=2), dict(n=100, p=16, s=1, rounds=2, variant=1),
+    dict(n=100, p=16, s=1, rounds=2, route=1), dict(n=100, p=16, s=1, rounds=2, bucketing=1),
+    dict(n=100, p=16, s=1, rounds=2, untagged=True), dict(n=5000, p=1024, s=1, rounds=11),
+    dict(n=100, p=16, s=1, rounds=-1),
 ])
 def test_invalid_arguments_rejected_on_host(bsps, case):
     case = dict(case)
@@ -53,6 +60,26 @@ def test_invalid_arguments_rejected_on_host(bsps, case):
     prm = bsps.make_params(case.pop("p"), case.pop("s"), **case)
     assert bsps.workspace_bytes(n, dtype, False, prm) == 0
     assert _call(bsps, n, dtype, prm) == bsps.EINVAL
+
+
+def test_untagged_flag_is_boolean(bsps):
+    prm = bsps.make_params(2, 2)
+    prm.untagged = 2
+    assert bsps.workspace_bytes(10, 0, False, prm) == 0
+    assert _call(bsps, 10, 0, prm) == bsps.EINVAL
+
+
+def test_iterative_dry_run(bsps):
+    """Every launch of the iterative rounds checked on the host for several
+    shapes (k = 2 .. 32, m = 2 .. 10), dtypes and payloads."""
+    for n, p, s, m, dt, kv in [(1 << 20, 16, 8, 2, 0, False), (1 << 20, 64, 4, 3, 1, True), (1000, 16, 2, 4, 2, False),
+                               (100_000, 1024, 4, 2, 0, True), (1 << 26, 1024, 16, 2, 0, False),
+                               (1 << 28, 256, 64, 2, 1, True), (70, 64, 1, 3, 0, False), (5000, 1024, 1, 10, 0, True)]:
+        k, rep = bsps.check_sort(n, dt, kv, bsps.make_params(p, s, rounds=m))
+        assert k == 0, rep
+    # rounds = 1 and p = 1 take the one-round path
+    assert bsps.workspace_bytes(1000, 0, False, bsps.make_params(12, 2, rounds=1)) > 0
+    assert bsps.workspace_bytes(1000, 0, False, bsps.make_params(1, 2, rounds=3)) > 0
 
 
 def test_reserved_fields_must_be_zero(bsps):

@@ -26,13 +26,13 @@ def _torch_keys(keys, dev):
     return torch.from_numpy(np.ascontiguousarray(keys)).to(dev)
 
 
-def _run(dev, keys, p, s, variant, seed=1, values=None, chunk_cap=0, local_sort=0):
+def _run(dev, keys, p, s, variant, seed=1, values=None, chunk_cap=0, local_sort=0, untagged=False, route=0):
     import torch
     import paper_1408_6729_amd as bsps
     t = _torch_keys(keys, dev)
     v = None if values is None else torch.from_numpy(values.view(np.int32)).to(dev)
     st = bsps.sort_(t, p, s, variant, seed, values=v, chunk_cap=chunk_cap, stats=True, stats_arrays=True,
-                    local_sort=local_sort)
+                    local_sort=local_sort, untagged=untagged, route=route)
     torch.cuda.synchronize()
     out = t.cpu().numpy()
     outv = None if v is None else v.cpu().numpy().view(np.uint32)
@@ -43,10 +43,11 @@ def _bits(a):
     return a.view(np.uint32) if a.dtype == np.float32 else a
 
 
-def _check(ora, dev, keys, p, s, variant, seed=1, kv=False, chunk_cap=0, check_B=True, local_sort=0):
+def _check(ora, dev, keys, p, s, variant, seed=1, kv=False, chunk_cap=0, check_B=True, local_sort=0, untagged=False,
+           route=0):
     vals = np.arange(keys.size, dtype=np.uint32) if kv else None
-    ref = ora.sort(keys, p, s, variant, seed, vals)
-    out, outv, st = _run(dev, keys, p, s, variant, seed, vals, chunk_cap, local_sort)
+    ref = ora.sort(keys, p, s, variant, seed, vals, untagged=untagged)
+    out, outv, st = _run(dev, keys, p, s, variant, seed, vals, chunk_cap, local_sort, untagged, route)
     assert np.array_equal(_bits(out), _bits(ref["keys"])), "sorted keys differ"
     if kv:
         assert np.array_equal(outv, ref["values"]), "payload order differs"
@@ -243,3 +244,97 @@ def test_lsd_many_blocks(ora, dev):
     n = 1100 * 16390
     keys = W.random_keys(n, "int32", seed=77, distinct=n // 2)
     _check(ora, dev, keys, 1024, 8, ora.DET, local_sort=2)
+
+
+# ----------------------------------------------------------------- duplicate handling switched off
+
+@pytest.mark.parametrize("route", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("case", ["distinct", "dict", "zero", "int64kv"])
+def test_untagged_against_oracle(ora, dev, route, variant, case):
+    """The ablation of Section 6.4: splitters compared by key alone. Output,
+    payloads, splitters and count matrix equal the untagged oracle's; with
+    distinct keys the count matrix also equals the tagged one, and with all-equal
+    keys every key lands in bucket 0."""
+    n = 3 * 16384 + 777
+    if case == "distinct":
+        keys = np.random.default_rng(3).permutation(n).astype(np.int32)
+    elif case == "dict":
+        keys = W.random_keys(n, "int32", seed=8, distinct=300)
+    elif case == "zero":
+        keys = np.zeros(n, dtype=np.int32)
+    else:
+        keys = W.random_keys(n, "int64", seed=9, distinct=500)
+    st = _check(ora, dev, keys, 16, 8, variant, seed=2, kv=case != "distinct", untagged=True, route=route)
+    if case == "distinct":
+        tagged = ora.sort(keys, 16, 8, variant, 2)
+        assert np.array_equal(st["count_matrix"], tagged["C"])
+    if case == "zero":
+        assert np.array_equal(st["count_matrix"][:, 1:], np.zeros((16, 15), dtype=np.int64))
+
+
+# ----------------------------------------------------------------- Sort_Ran_BSP (Figure SortR)
+
+def _check_sr(ora, dev, keys, p, s, seed=1, kv=False, bucketing=0, untagged=False):
+    import torch
+    import paper_1408_6729_amd as bsps
+    vals = np.arange(keys.size, dtype=np.uint32) if kv else None
+    ref = ora.sort_sr(keys, p, s, seed, vals)
+    t = _torch_keys(keys, dev)
+    v = None if vals is None else torch.from_numpy(vals.view(np.int32)).to(dev)
+    st = bsps.sort_(t, p, s, bsps.RAN_SR, seed, values=v, bucketing=bucketing, leaves=256, stats=True,
+                    stats_arrays=True, untagged=untagged)
+    torch.cuda.synchronize()
+    assert np.array_equal(_bits(t.cpu().numpy()), _bits(ref["keys"])), "sorted keys differ"
+    if kv:
+        assert np.array_equal(v.cpu().numpy().view(np.uint32), ref["values"]), "payload order differs"
+    if p > 1:
+        assert np.array_equal(st["sample_pos"], ref["sample_pos"]), "sample tags (input positions) differ"
+        assert np.array_equal(st["splitter_pos"], ref["spl_pos"]), "splitter tags differ"
+        assert np.array_equal(_bits(st["splitter_keys"]), _bits(keys[ref["spl_pos"]]))
+    assert np.array_equal(st["count_matrix"], ref["C"]), "count matrix differs"
+    assert np.array_equal(_bits(st["routed"][:keys.size]), _bits(ref["Z_keys"])), "routed array differs"
+    # the bucket of every input record: the bucket its routed position falls in
+    want = np.empty(keys.size, np.uint32)
+    want[ref["Z_perm"]] = np.repeat(np.arange(p, dtype=np.uint32), ref["bucket_sizes"])
+    assert np.array_equal(st["buckets"][:keys.size], want), "per-record bucket ids differ"
+    return st
+
+
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+@pytest.mark.parametrize("kv", [False, True])
+@pytest.mark.parametrize("bucketing", [0, 1])
+def test_sr_against_oracle(ora, dev, dtype, kv, bucketing):
+    """Sort_Ran_BSP: sample of the unsorted input, splitters, every input record
+    ranked (splitter search or learned model with the exact check), routed in
+    input order, buckets sorted. Output, payloads, sample and splitter tags,
+    count matrix and routed array equal the oracle's; ragged sizes, buckets
+    of several tiles, duplicates."""
+    rng = np.random.default_rng(21 + bucketing)
+    for trial in range(3):
+        n = int(rng.integers(50000, 400000))
+        p = int(rng.integers(2, 300))
+        s = max(1, min(int(rng.integers(1, 40)), (n + 1) // p))
+        keys = W.random_keys(n, dtype, seed=trial + 60, distinct=None if trial % 2 else 500)
+        _check_sr(ora, dev, keys, p, s, seed=trial + 2, kv=kv, bucketing=bucketing)
+
+
+@pytest.mark.parametrize("case", ["zero", "p1", "p1024", "untagged"])
+def test_sr_edges(ora, dev, case):
+    if case == "zero":
+        st = _check_sr(ora, dev, np.zeros(100003, dtype=np.int32), 64, 8, kv=True)
+        assert st["bucket_sizes"].max() < 4 * 100003 / 64  # ties split by position
+    elif case == "p1":
+        _check_sr(ora, dev, W.random_keys(70001, "int32", seed=3), 1, 1, kv=True)
+    elif case == "p1024":
+        _check_sr(ora, dev, W.random_keys(1 << 21, "float32", seed=4), 1024, 16, bucketing=1)
+    else:
+        keys = W.random_keys(200000, "int32", seed=5, distinct=100)
+        vals = np.arange(keys.size, dtype=np.uint32)
+        import torch
+        import paper_1408_6729_amd as bsps
+        t = _torch_keys(keys, dev)
+        v = torch.from_numpy(vals.view(np.int32)).to(dev)
+        bsps.sort_(t, 32, 8, bsps.RAN_SR, 3, values=v, untagged=True)
+        assert np.array_equal(t.cpu().numpy(), keys[np.argsort(keys, kind="stable")])
+        assert np.array_equal(v.cpu().numpy().view(np.uint32), np.argsort(keys, kind="stable").astype(np.uint32))
