@@ -13,6 +13,9 @@ The reported time is the median over the timed steps (min and max beside it).
 The randomized variant (Figure SortRI) is timed on the same input.
 
 Beside it (in "detail"), each timed the same way:
+  configs      2^20 int32 uniform keys at p = 16, s = 8, and the seven
+               synthetic distributions at 2^26 int32 keys, p = 128, s = 32,
+               both variants
   variants     the same input sorted by Sort_Ran_BSP (Figure SortR), by the
                iterative Sort_Det_BSP (m = 2, 4, 8 rounds, Section 5.1), and
                with the duplicate handling switched off (Section 6.4), the
@@ -37,7 +40,7 @@ kernel (algorithmic bytes of one launch over its HIP-event-timed duration,
 against the 8 TB/s HBM peak and against the rate the library's reference copy
 kernel attains on the same array), and the CPU oracle timed on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c0,variants,learned,int64_kv,segmented,operating]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only c0,configs,variants,learned,int64_kv,segmented,operating]
 """
 from __future__ import annotations
 
@@ -60,7 +63,7 @@ STAGES = ["tile_sort", "block_merge", "sample_splitters", "bucket_ranking", "pre
           "bucket_merge", "k_mwm_merge(block)", "k_mwm_merge(bucket)", "k_rank", "k_lsd_pass"]
 # kernels that move every record once per launch (a permuting pass: 2 w bytes per key)
 PERMUTING = ("tile_sort", "k_lsd_pass", "k_mwm_merge(block)", "k_mwm_merge(bucket)")
-ALL = ("c0", "variants", "learned", "int64_kv", "segmented", "operating")
+ALL = ("c0", "configs", "variants", "learned", "int64_kv", "segmented", "operating")
 
 
 def log(msg):
@@ -177,13 +180,14 @@ def summary(ts, n):
 
 
 def bench_sort(bsps, torch, base, K, Wm, p, s, variant=0, bucketing=0, route=0, leaves=0, vbase=None, untagged=False,
-               rounds=1):
+               rounds=1, local_sort=0):
     """K timed sorts of the staged input (median); then one stage-timed run."""
     n = base.numel()
     work = torch.empty_like(base)
     vwork = None if vbase is None else torch.empty_like(vbase)
     dt = {torch.int32: bsps.I32, torch.int64: bsps.I64, torch.float32: bsps.F32}[base.dtype]
-    prm = bsps.make_params(p, s, variant, 1, bucketing, route, leaves, untagged=untagged, rounds=rounds)
+    prm = bsps.make_params(p, s, variant, 1, bucketing, route, leaves, local_sort=local_sort, untagged=untagged,
+                           rounds=rounds)
     ws = torch.empty(bsps.workspace_bytes(n, dt, vbase is not None, prm), dtype=torch.uint8, device=base.device)
 
     def restage():
@@ -193,7 +197,7 @@ def bench_sort(bsps, torch, base, K, Wm, p, s, variant=0, bucketing=0, route=0, 
 
     def run():
         bsps.sort_(work, p, s, variant, values=vwork, bucketing=bucketing, route=route, leaves=leaves, workspace=ws,
-                   untagged=untagged, rounds=rounds)
+                   untagged=untagged, rounds=rounds, local_sort=local_sort)
 
     ts = time_steps(torch, run, restage, K, Wm)
     res = summary(ts, n)
@@ -250,18 +254,48 @@ def bench_c0(bsps, torch, W, args, keys):
     return n, p, s, res
 
 
+def bench_configs(bsps, torch, W, args):
+    """The small and mid-size parity configurations, timed the same way: 2^20
+    int32 uniform keys at p = 16, s = 8 (DET), and the seven distributions at
+    2^26 int32 keys, p = 128, s = 32, DET and RAN."""
+    out = {}
+    K, Wm = max(5, min(args.steps, 10)), max(1, min(args.warmup, 2))
+    base = to_dev(torch, W.int32_keys(1 << 20, 16, "uniform"))
+    r, o, _ = bench_sort(bsps, torch, base, K, Wm, 16, 8, bsps.DET)
+    r["sorted"] = is_sorted(torch, o)
+    del r["stages"]
+    out["C1_det"] = r
+    log(f"configs/C1 det: median {r['ms']:.3f} ms, {r['keys_per_s'] / 1e9:.2f} Gkeys/s, sorted={r['sorted']}")
+    del base, o
+    for dist in W.DISTRIBUTIONS:
+        base = to_dev(torch, W.int32_keys(1 << 26, 128, dist))
+        for variant, vname in ((bsps.DET, "det"), (bsps.RAN, "ran")):
+            r, o, _ = bench_sort(bsps, torch, base, K, Wm, 128, 32, variant)
+            r["sorted"] = is_sorted(torch, o)
+            del r["stages"]
+            out[f"C2_{dist}_{vname}"] = r
+            log(f"configs/C2 {dist} {vname}: median {r['ms']:.3f} ms, {r['keys_per_s'] / 1e9:.2f} Gkeys/s, "
+                f"sorted={r['sorted']}")
+            del o
+        del base
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_variants(bsps, torch, W, args, keys):
     """On the headline input (2^28 int32 uniform, p = 256, s = 64): the
     Sort_Ran_BSP ordering (Figure SortR), the iterative Sort_Det_BSP with m =
-    2, 4 and 8 rounds (k = 16, 4, 2 buckets per round, Section 5.1), and the
+    2, 4 and 8 rounds (k = 16, 4, 2 buckets per round, Section 5.1), the
     duplicate handling switched off (Section 6.4's ablation) next to it on
-    the headline input and on 2^28 keys over 2^10 distinct values."""
+    the headline input and on 2^28 keys over 2^10 distinct values, and the
+    LSD local sort in place of tiles + merge."""
     n, p, s = keys.size, 256, 64
     base = to_dev(torch, keys)
     K, Wm = max(5, min(args.steps, 10)), max(1, min(args.warmup, 2))
     out = {"workload": f"2^{int(math.log2(n))} int32 uniform, p={p}, s={s}"}
     runs = [("sr", dict(variant=bsps.RAN_SR)), ("iter_m2", dict(rounds=2)), ("iter_m4", dict(rounds=4)),
-            ("iter_m8", dict(rounds=8)), ("untagged", dict(untagged=True))]
+            ("iter_m8", dict(rounds=8)), ("untagged", dict(untagged=True)),
+            ("lsd_local_sort", dict(local_sort=bsps.LOCAL_LSD))]
     for name, kw in runs:
         r, o, _ = bench_sort(bsps, torch, base, K, Wm, p, s, **kw)
         r["sorted"] = is_sorted(torch, o)
@@ -472,6 +506,8 @@ def main():
     n, p, s, c0 = bench_c0(bsps, torch, W, args, keys)
     det = c0["det"]
     detail = {"det": det, "ran": c0["ran"], "stream_copy": c0["stream_copy"]}
+    if "configs" in only:
+        detail["configs"] = bench_configs(bsps, torch, W, args)
     if "variants" in only:
         detail["variants"] = bench_variants(bsps, torch, W, args, keys)
     if "learned" in only:
