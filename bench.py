@@ -60,9 +60,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 STAGES = ["tile_sort", "block_merge", "sample_splitters", "bucket_ranking", "prefix_routing",
-          "bucket_merge", "k_mwm_merge(block)", "k_mwm_merge(bucket)", "k_rank", "k_lsd_pass"]
+          "bucket_merge", "k_mwm_merge(block)", "k_mwm_merge(bucket)", "k_rank", "k_lsd_sweep"]
 # kernels that move every record once per launch (a permuting pass: 2 w bytes per key)
-PERMUTING = ("tile_sort", "k_lsd_pass", "k_mwm_merge(block)", "k_mwm_merge(bucket)")
+PERMUTING = ("tile_sort", "k_lsd_sweep", "k_mwm_merge(block)", "k_mwm_merge(bucket)")
 ALL = ("c0", "configs", "variants", "learned", "int64_kv", "segmented", "operating")
 
 
@@ -125,6 +125,29 @@ def cpu_baseline(keys, p: int, s: int, log2_one: int):
             "one_core": {"value": n1 / dt_one, "unit": "keys/s", "cores": 1,
                          "sample": f"2^{log2_one} int32 uniform keys, p={p}, s={s}, DET, one thread: {dt_one:.1f} s"},
             "host_cpu": cpu_model(), "host_cpu_count": os.cpu_count()}
+
+
+def cpu_configs(W, threads):
+    """The oracle (threaded per-processor steps, as in cpu_baseline) on the
+    parity configurations, for the comparison table: 2^20 int32 (p = 16, s =
+    8), 2^26 int32 uniform (p = 128, s = 32), 2^28 int64 Zipf key-value (p =
+    256, s = 64) and 2^28 float32 lognormal mixture (p = 1024, s = 64), DET.
+    Seconds of the sort call only (inputs generated before)."""
+    import oracle
+    out = {}
+    cases = [("C1", lambda: (W.int32_keys(1 << 20, 16, "uniform"), None), 16, 8),
+             ("C2_uniform", lambda: (W.int32_keys(1 << 26, 128, "uniform"), None), 128, 32),
+             ("C3", lambda: W.zipf_int64_kv(1 << 28), 256, 64),
+             ("C4", lambda: (W.lognormal_f32(1 << 28), None), 1024, 64)]
+    for name, gen, p, s in cases:
+        keys, vals = gen()
+        t0 = time.perf_counter()
+        oracle.sort(keys, p, s, oracle.DET, values=vals, intermediates=False, threads=threads)
+        dt = time.perf_counter() - t0
+        out[name] = {"keys_per_s": keys.size / dt, "seconds": dt, "threads": threads, "n": int(keys.size)}
+        log(f"cpu oracle {name}: {dt:.2f} s, {keys.size / dt / 1e6:.1f} Mkeys/s on {threads} threads")
+        del keys, vals
+    return out
 
 
 def to_dev(torch, a):
@@ -473,7 +496,7 @@ def bench_operating(bsps, torch, W, args):
 def dominant(stages):
     """The permuting kernel with the largest total time per step."""
     cand = {k: v for k, v in stages.items() if k in PERMUTING and not (
-        k == "tile_sort" and "k_lsd_pass" in stages)}
+        k == "tile_sort" and "k_lsd_sweep" in stages)}
     return max(cand, key=lambda k: cand[k]["ms_per_launch"] * cand[k]["launches_per_step"])
 
 
@@ -485,6 +508,8 @@ def main():
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--cpu-log2n", type=int, default=25)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="also time the oracle on the parity configurations (about two minutes)")
     ap.add_argument("--only", default=",".join(ALL))
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -526,7 +551,7 @@ def main():
     achieved = alg_bytes / (det["stages"][dom]["ms_per_launch"] / 1e3) / 1e9
     workload = "C0"
     passes = sum(det["stages"][k]["launches_per_step"] for k in det["stages"] if k in PERMUTING and not (
-        k == "tile_sort" and "k_lsd_pass" in det["stages"]))
+        k == "tile_sort" and "k_lsd_sweep" in det["stages"]))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic(dom, workload), "kernel": dom,
                 "alg_bytes_per_launch": alg_bytes, "attainable_copy_gbs": c0["stream_copy"]["gbs"],
@@ -538,6 +563,9 @@ def main():
     if not args.no_cpu:
         log(f"timing the CPU oracle on the headline input and on 2^{args.cpu_log2n} keys")
         cpu = cpu_baseline(keys, p, s, args.cpu_log2n)
+        if args.cpu_configs:
+            import oracle
+            cpu["configs"] = cpu_configs(W, oracle.default_threads())
     line = {
         "metric": "keys/s and % HBM roofline, 2^28 int32; learned vs splitter bucketing",
         "value": det["keys_per_s"], "unit": "keys/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

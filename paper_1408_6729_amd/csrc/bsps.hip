@@ -206,6 +206,7 @@ void dry_check(const LsdArgs<K>& a) {
 void dry_check(const LsdSweep& w) {
     dry_span("LsdSweep.status", w.status, (u64)w.ntile * LSD_RADIX);
     dry_span("LsdSweep.ctr", w.ctr, 2);
+    if (!w.hist) t_dry->fail("LsdSweep: missing digit counts", w.hist, 0);
     if (!w.status || !w.ctr || !w.tstart) t_dry->fail("LsdSweep: missing buffer", w.status, 0);
 }
 template <typename... A>
@@ -493,6 +494,7 @@ LsdSweep carve_sweep(Carver& c, i64 n, int p) {
     w.status = c.take<u32>((u64)w.ntile * LSD_RADIX);
     w.ctr = c.take<u32>(8);
     w.tstart = c.take<u32>((u64)p + 1);
+    w.hist = c.take<u32>((u64)p * sizeof(K) * LSD_RADIX);
     w.spin_limit = 1u << 16;  // a wait lasts about one tile sort; this is some 1000 times that
     return w;
 }
@@ -520,9 +522,15 @@ bsps_status lsd_launch(const LsdArgs<K>& a, const LsdSweep& w, hipStream_t st) {
     constexpr int NT = Shape<K>::NT;
     const int p = a.p;
     StageScope sc(ST_TILE, st);
-    LAUNCH((k_lsd_hist<K>), dim3((u32)p), dim3(LSD_HIST_NT), 0, st, a);
-    LAUNCH_OK();
+    // digit counts: every tile adds its own into its block's, then every block's are scanned
     LAUNCH((k_lsd_tiles<K>), dim3(1), dim3(1024), 0, st, a, w);
+    LAUNCH_OK();
+    const u64 nh = (u64)p * sizeof(K) * LSD_RADIX;
+    LAUNCH(k_zero_u32, dim3((u32)cdiv(nh, 256)), dim3(256), 0, st, w.hist, (int)nh);
+    LAUNCH_OK();
+    LAUNCH((k_lsd_count<K>), dim3(w.ntile), dim3(LSD_COUNT_NT), 0, st, a, w, w.hist);
+    LAUNCH_OK();
+    LAUNCH((k_lsd_scan<K>), dim3((u32)p), dim3(LSD_HIST_NT), 0, st, a, (const u32*)w.hist);
     LAUNCH_OK();
     LAUNCH(k_zero_u32, dim3(1), dim3(64), 0, st, w.ctr, 8);
     LAUNCH_OK();
