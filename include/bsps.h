@@ -35,9 +35,10 @@
  *  - The result is the STABLE ascending order: equal keys keep their input
  *    order, which is exactly the order the paper's tie rule (processor
  *    identifier, then local index, Section 5.1.1) produces.
- *  - Limits: n < 2^32 - 1 (positions are 32-bit), 1 <= p <= 1024, and each block
- *    of about n/p keys splits into at most 1024 tiles (16K keys for 4-byte keys,
- *    8K for int64), i.e. n/p <= 2^24 (2^23 for int64).
+ *  - Limits: n < 2^32 - 1 (positions are 32-bit) and 1 <= p <= 1024. The
+ *    local sort by tiles + merge takes blocks of at most 1024 tiles (16K keys
+ *    for 4-byte keys, 8K for int64), i.e. n/p <= 2^24 (2^23 for int64):
+ *    local_sort = MERGE rejects larger blocks, AUTO sorts them by LSD passes.
  */
 #ifndef BSPS_H
 #define BSPS_H
@@ -317,10 +318,14 @@ void bsps_release_cache(void);
 /*
  * Diagnostics: per-stage timing with HIP events recorded on the caller's
  * stream around every stage of the following calls. Stages (index):
- *   0 tile sorts, 1 block merge, 2 sample + sample sort + splitters,
- *   3 bucket ranking, 4 prefix sums / routing, 5 bucket merge,
+ *   0 local sort (tile sorts; any LSD sort, local or Sort_Ran_BSP's bucket
+ *     sort, with its digit counts and passes), 1 block merge,
+ *   2 sample + sample sort + splitters,
+ *   3 bucket ranking (bucket boundaries, the learned model's fit, per-key
+ *     ranking), 4 prefix sums / routing, 5 bucket merge (every round of the
+ *     iterative version; Sort_Ran_BSP: the sort of its buckets),
  *   6 merge kernel of the block merge, 7 merge kernel of the bucket merge,
- *   8 per-key ranking kernel.
+ *   8 per-key ranking kernel, 9 the LSD passes (tile-parallel sweeps).
  * bsps_timing_read waits for the recorded events and returns, for the first
  * nstage stages, the summed milliseconds (ms, HOST) and launch counts
  * (launches, HOST); reset != 0 clears the record. Not thread safe.

@@ -693,8 +693,8 @@ template <typename K>
 bool use_lsd(i64 n, const bsps_params* prm) {
     if (prm->local_sort == BSPS_LOCAL_LSD) return true;
     if (prm->local_sort == BSPS_LOCAL_MERGE) return false;
-    (void)n;
-    return false;
+    // AUTO: tiles + merge, unless a block has more tiles than a merge group takes runs
+    return cdiv(cdiv((u64)n, (u64)prm->p), tileT<K>()) > (u64)MAXR;
 }
 
 // Sort_Ran_BSP: the routed array Z (= B), the LSD scratch A and tables, the
@@ -853,10 +853,13 @@ bsps_status validate(i64 n, int dtype, const bsps_params* prm) {
     }
     if (prm->variant != BSPS_DET && (i64)prm->s * prm->p - 1 > n) return BSPS_EINVAL;
     if (n >= (i64)0xFFFFFFFFll || prm->p > kMaxP) return BSPS_EUNSUPPORTED;
-    // every block must split into at most MAXR tiles
+    // the merge of a block's tiles takes at most MAXR tiles (AUTO sorts larger
+    // blocks by LSD passes, and Sort_Ran_BSP merges no tiles)
     const int kb = key_bytes(dtype);
     const u64 T = kb == 8 ? tileT<u64>() : tileT<u32>();
-    if (n > 1 && cdiv(cdiv((u64)n, (u64)prm->p), T) > (u64)MAXR) return BSPS_EUNSUPPORTED;
+    if (n > 1 && prm->local_sort == BSPS_LOCAL_MERGE && prm->variant != BSPS_RAN_SR &&
+        cdiv(cdiv((u64)n, (u64)prm->p), T) > (u64)MAXR)
+        return BSPS_EUNSUPPORTED;
     const i64 ns = prm->variant == BSPS_DET ? (i64)prm->p * prm->s : (i64)prm->p * prm->s - 1;
     if (ns > (i64)MAXR * (i64)T || ns >= (i64)0xFFFFFFFFll) return BSPS_EUNSUPPORTED;
     if (prm->variant == BSPS_RAN_SR && prm->route != BSPS_ROUTE_FUSED) return BSPS_EINVAL;  // it has one route

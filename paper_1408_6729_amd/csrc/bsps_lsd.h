@@ -239,11 +239,11 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_lsd_sweep(LsdA
 
 // ---------------------------------------------------------------- digit counts, every tile in parallel
 //
-// The counts of k_lsd_hist without its one-workgroup-per-block walk (which
-// leaves a large block, a large bucket of Sort_Ran_BSP, to one CU): every
-// tile counts its digits in LDS and adds them to its block's counts in
-// global memory (hist, zeroed before); k_lsd_scan then turns every block's
-// counts into its digit starts and pass list, as k_lsd_hist does.
+// Every tile counts its digits in LDS and adds them to its block's counts in
+// global memory (hist, zeroed before), so a large block (a large bucket of
+// Sort_Ran_BSP) is spread over as many workgroups as it has tiles;
+// k_lsd_scan then turns every block's counts into its digit starts and its
+// pass list.
 constexpr int LSD_COUNT_NT = 512;
 
 template <typename K>

@@ -91,8 +91,16 @@ def test_reserved_fields_must_be_zero(bsps):
 def test_limits(bsps):
     assert _call(bsps, 5000, 0, bsps.make_params(1025, 1)) == bsps.EUNSUPPORTED
     assert _call(bsps, 1 << 32, 0, bsps.make_params(4, 1)) == bsps.EUNSUPPORTED
-    # a block of more than 1024 tiles of 16K keys
-    assert _call(bsps, (1 << 24) * 2 + 10, 0, bsps.make_params(1, 1)) == bsps.EUNSUPPORTED
+    # a block of more than 1024 tiles of 16K keys: too many runs for the merge of
+    # its tiles; AUTO (and Sort_Ran_BSP, which merges no tiles) take it, by LSD passes
+    big = (1 << 24) * 2 + 10
+    assert _call(bsps, big, 0, bsps.make_params(1, 1, local_sort=bsps.LOCAL_MERGE)) == bsps.EUNSUPPORTED
+    assert bsps.workspace_bytes(big, 0, False, bsps.make_params(1, 1)) > 0
+    assert bsps.workspace_bytes(big, 0, False, bsps.make_params(2, 1, variant=bsps.RAN_SR)) > 0
+    for prm in (bsps.make_params(1, 1), bsps.make_params(8, 64), bsps.make_params(8, 64, variant=bsps.RAN_SR),
+                bsps.make_params(4, 16, rounds=2)):
+        k, rep = bsps.check_sort(big, 0, True, prm)
+        assert k == 0, rep
 
 
 def test_workspace_checked_before_device(bsps):

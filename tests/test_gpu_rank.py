@@ -197,7 +197,7 @@ def test_model_fit_matches_oracle(ora, dev, iters):
     hdr, leaf = bsps.model_fields(model)
     assert (hdr["lo"], hdr["hi"]) == tuple(m["lohi"])
     assert hdr["L"] == L and hdr["p"] == p and hdr["s"] == s
-    # root: sums of N = 2^16 terms by FP32 tree reductions (see the design notes)
+    # root: sums of N = 2^16 terms by FP32 tree reductions, error about lg N * 2^-24 of the sum of magnitudes
     assert np.allclose([hdr["a"], hdr["b"], hdr["mur"]], m["root"], rtol=1e-4, atol=1e-6)
     c, d, mu = (leaf[:, i].astype(np.float64) for i in range(3))
     # leaf membership by the oracle's root; the margin makes it the GPU's too

@@ -289,3 +289,26 @@ def test_iter_full(ora, dev):
     assert C.shape == (2, p, k) and (C.sum(axis=(1, 2)) == n).all()
     assert np.array_equal(C[0].sum(axis=1), [ora.block_start(n, p, j + 1) - ora.block_start(n, p, j)
                                             for j in range(p)])
+
+
+@pytest.mark.timeout(400)
+def test_large_blocks_beyond_merge_limit(ora, dev):
+    """p = 8 on 2^27 + 12345 int32 keys: blocks of 2^24 + 1543 keys have more tiles
+    than a merge group takes, so AUTO sorts them by LSD passes; Sort_Det_BSP and
+    Sort_IRan_BSP against the threaded oracle (output, splitter tags, count
+    matrix), and Sort_Ran_BSP (which merges no tiles) against the oracle's output."""
+    import paper_1408_6729_amd as bsps
+    n, p, s = (1 << 27) + 12345, 8, 64
+    keys = W.random_keys(n, "int32", seed=27)
+    for variant in (bsps.DET, bsps.RAN):
+        t = _to_dev(keys, dev)
+        st = bsps.sort_(t, p, s, variant, seed=3, stats=True)
+        out = _to_host(t)
+        del t
+        ref = ora.sort(keys, p, s, variant, seed=3, threads=_threads())
+        assert np.array_equal(out, ref["keys"]), variant
+        assert np.array_equal(st["splitter_pos"], ref["spl_pos"]), variant
+        assert np.array_equal(st["count_matrix"], ref["C"]), variant
+    t = _to_dev(keys, dev)
+    bsps.sort_(t, p, s, bsps.RAN_SR, seed=3)
+    assert np.array_equal(_to_host(t), np.sort(keys))
