@@ -146,7 +146,9 @@ typedef struct bsps_stats {
     double mean_fix_dist;      /* learned bucketing: mean |predicted - true| */
     int64_t oversize_chunks;   /* merge chunks sorted by the global-memory path */
     int64_t reserved_i[4];     /* bsps_sort: [0] oversize chunks of the block merge, [1] of the
-                                  bucket merge, [2] keys in the largest one. bsps_sort_segmented:
+                                  bucket merge, [2] keys in the largest one, [3] the most low key bits
+                                  the tile sort left to the block merge in any block (0: every
+                                  block's tiles fully sorted). bsps_sort_segmented:
                                   [0] blocks, [1] merged segments, [2] 1 if the graph was captured
                                   and launched by this call, 2 if a cached graph was launched,
                                   [3] segments with learned bucketing (NL) */

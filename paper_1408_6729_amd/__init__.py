@@ -218,6 +218,7 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
     out["mean_fix_dist"] = st.mean_fix_dist
     out["oversize_chunks"] = st.oversize_chunks
     out["oversize_block"], out["oversize_bucket"], out["oversize_max"] = (int(x) for x in st.reserved_i[:3])
+    out["trunc_shift"] = int(st.reserved_i[3])  # low key bits the tile sort left to the block merge
     return out
 
 

@@ -141,6 +141,7 @@ void dry_span(const char* what, const T* p, u64 count) {
 template <typename K>
 void dry_check(const TileArgs<K>& a) {
     const u64 n = (u64)std::max<i64>(a.n, 0);
+    dry_span("TileArgs.gsh", a.gsh, a.btab ? 1 : (u64)a.p);
     dry_span("TileArgs.in", a.in, n);
     dry_span("TileArgs.inv", a.inv, n);
     dry_span("TileArgs.out", a.out, n);
@@ -176,6 +177,7 @@ void dry_check(const MwmArgs<K>& a) {
     dry_span("MwmArgs.grp_base", a.grp_base, G);
     dry_span("MwmArgs.grp_nb", a.grp_nb, G);
     dry_span("MwmArgs.bkey", a.bkey, S);
+    dry_span("MwmArgs.gsh", a.gsh, G);
     dry_span("MwmArgs.bpos", a.bpos, S);
     dry_span("MwmArgs.cuts", a.cuts, S * R);
     dry_span("MwmArgs.below", a.below, S);
@@ -448,7 +450,8 @@ u32 tile_grid(TileArgs<K>& ta, u32 ntile) {
 template <typename K, bool HASV>
 bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, int in_dt, K* out, u32* outv,
                        int out_dt, K* scr, u32* scrv, i64 n, int p, u32 cap, u32 tavg, K* osmp, u32 yb, u32 spb,
-                       hipStream_t st, int tstage = ST_N, int mstage = ST_N, int mkstage = ST_N) {
+                       hipStream_t st, int tstage = ST_N, int mstage = ST_N, int mkstage = ST_N,
+                       u32* gsh = nullptr, int keep = 0) {
     constexpr int NT = Shape<K>::NT;
     const u32 T = tileT<K>();
     TileArgs<K> ta{};
@@ -461,9 +464,14 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
         return BSPS_OK;
     }
     ta.out = b.A; ta.outv = b.Av; ta.out_dt = BSPS_DT_NONE; ta.smp = b.tsmp; ta.ys = kSampleStride; ta.spt = b.spt;
+    ta.gsh = gsh;  // tiles that are merged afterwards may be sorted on their high part only
     const u32 tgrid = tile_grid<K, HASV>(ta, (u32)(p * b.tpb));
     {
         StageScope sc(tstage, st);
+        if (gsh) {
+            LAUNCH((k_trunc_probe<K>), dim3((u32)p), dim3(TRUNC_NT), 0, st, in, in_dt, n, p, keep, gsh);
+            LAUNCH_OK();
+        }
         LAUNCH((k_tile_sort<K, HASV>), dim3(tgrid), dim3(NT), 0, st, ta);
     }
     LAUNCH_OK();
@@ -473,6 +481,7 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
                        kSampleStride, b.spt, b.mwm.run_start, b.mwm.run_len, b.mwm.out_base, b.mwm.sdesc);
     LAUNCH_OK();
     MwmArgs<K> a = mwm_args<K>(b.mwm, b.A, b.Av, out, outv, scr, scrv, b.tsmp, cap, tavg, out_dt, osmp, yb, spb);
+    a.gsh = gsh;
     return mwm_run<K, HASV>(a, st, mkstage);
 }
 
@@ -615,6 +624,7 @@ struct Plan {
     u32* plist;              // LSD: passes of every block [p][sizeof(K) + 1]
     LsdSweep lsw;            // LSD: look-back status, tickets, tiles of every block
     BlockSortBufs<K> bs;     // main block sort
+    u32* gsh;                // shift of its truncated tile sort (k_trunc_probe), or NULL
     K* B;
     u32* Bv;
     K* bsmp;                 // block samples (every kSampleStride-th key of each block)
@@ -767,6 +777,7 @@ size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* pr
         std::memset(&P.lsw, 0, sizeof(P.lsw));
         carve_block_sort<K>(c, P.bs, (u64)n, p, hasv, o.tavg, true);  // A doubles as merge scratch / routed array
     }
+    P.gsh = (!P.lsd && P.bs.tpb > 1) ? c.take<u32>((u64)p) : nullptr;
     P.B = c.take<K>(n);
     P.Bv = hasv ? c.take<u32>(n) : nullptr;
     const u64 m = cdiv((u64)n, (u64)p);
@@ -1233,11 +1244,20 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
     if (P.lsd)
         rc = lsd_block_sort<K, HASV>(io, vals, dt, P.bs.A, P.bs.Av, P.B, P.Bv, P.dbase, P.plist, P.lsw, n, p, P.bs.tpb,
                                      P.bsmp, kSampleStride, P.spb, st);
-    else
+    else {
+        // the shift of the truncated tile sort keeps lg(block) - 2 bits of the key range
+        const int keep = std::max(12, bitw(cdiv((u64)n, (u64)p) - 1) - 2);
         rc = block_sort<K, HASV>(P.bs, io, vals, dt, P.B, P.Bv, BSPS_DT_NONE, io, vals, n, p, o.cap, o.tavg, P.bsmp,
                                  kSampleStride, std::max<u32>(1, P.spb), st, ST_TILE, ST_BLOCK_MERGE,
-                                 ST_BLOCK_MERGE_K);
+                                 ST_BLOCK_MERGE_K, P.gsh, keep);
+    }
     if (rc) return rc;
+    if (stats && P.gsh) {
+        std::vector<u32> gs((size_t)p);
+        rc = d2h(gs.data(), P.gsh, 4 * gs.size(), st);
+        if (rc) return rc;
+        stats->reserved_i[3] = *std::max_element(gs.begin(), gs.end());
+    }
     if (stats && P.lsd) {
         rc = sweep_overruns(P.lsw, st);
         if (rc) return rc;

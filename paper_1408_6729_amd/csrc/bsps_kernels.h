@@ -106,6 +106,9 @@ struct MwmArgs {
     K* osmp;               // output samples every oys-th key of each group (or NULL), at most
                            // ospb per group (later ones are not written)
     u32 oys, ospb;
+    const u32* gsh;        // optional, per group: its runs sorted by key >> gsh[g] only (see TileArgs):
+                           // boundaries then cut on that part alone, never inside a group of equal
+                           // high parts
 };
 
 // Per-tile sort arguments. Tile t of block k covers
@@ -133,6 +136,11 @@ struct TileArgs {
     // btab entries) and loads each next tile while it sorts the current one.
     int persist;
     u32 ntile;
+    // Optional (the tiles of multi-tile blocks, merged afterwards): gsh[k] > 0
+    // sorts every tile of block k by the order key's bits from gsh[k] up only
+    // (key >> gsh[k]), stably, so equal high parts keep their positions; the
+    // merge then cuts the block's runs on that part and sorts each chunk in full.
+    const u32* gsh;
 };
 
 // Processor k owns [floor(k n / p), floor((k+1) n / p)): blocks differ in size by at most one.
@@ -214,7 +222,7 @@ __device__ __forceinline__ void load_blocked(const T* p, int valid, T (&r)[IT]) 
 template <typename K, bool HASV>
 __device__ __forceinline__ void tile_sort_body(const TileArgs<K>& a, SortSmem<Shape<K>::NT, (int)sizeof(K), Shape<K>::IT, !HASV>& sm,
                                                K (&kr)[Shape<K>::IT], u32 (&v)[Shape<K>::IT], int cnt, i64 base,
-                                               K* outk, u32* outv, int odt, K* smp, i64 sbase) {
+                                               K* outk, u32* outv, int odt, K* smp, i64 sbase, int gsh = 0) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
     u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x;
@@ -230,21 +238,26 @@ __device__ __forceinline__ void tile_sort_body(const TileArgs<K>& a, SortSmem<Sh
         }
     }
     block_minmax<NT, K>(mn, mx, sm.red64);
+    // truncated sort (gsh > 0): the range starts at a multiple of 2^gsh, so
+    // that (key - mn) >> gsh = (key >> gsh) - (mn >> gsh) orders like key >> gsh
+    if (gsh > 0) mn &= ~(K)((((K)1) << gsh) - 1);
     const int nbits = bitwidth64((u64)(mx - mn));
+    const int sbits = nbits > gsh ? nbits - gsh : 0;  // bits the passes sort on, from gsh up
     const u32 ysh = a.ys ? (u32)(__ffs(a.ys) - 1) : 0u;
     K* out = outk + base;
     if (sizeof(K) == 8 && nbits > 32) {
         u64 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = j < valid ? (u64)(kr[j] - mn) : (u64)(mx - mn);
-        wg_sort_regs<NT, IT, u64, HASV, (bool)BSPS_SMALLPASS, !HASV>(sk, v, rank, nbits, sm.template ex<u64>(),
-                                                                     sm.cnt(), sm.wsum);
+        wg_sort_regs<NT, IT, u64, HASV, (bool)BSPS_SMALLPASS, !HASV>(sk, v, rank, sbits, sm.template ex<u64>(),
+                                                                     sm.cnt(), sm.wsum, gsh);
         store_sorted<K, u64, NT, IT>(sm.template ex<u64>(), mn, cnt, out, odt, smp, sbase, ysh);
     } else {
         u32 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = j < valid ? (u32)(kr[j] - mn) : (u32)(mx - mn);
-        wg_sort_regs<NT, IT, u32, HASV, (bool)BSPS_SMALLPASS, !HASV>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
+        wg_sort_regs<NT, IT, u32, HASV, (bool)BSPS_SMALLPASS, !HASV>(sk, v, rank, sbits, vex, sm.cnt(), sm.wsum,
+                                                                     gsh);
         store_sorted<K, u32, NT, IT>(vex, mn, cnt, out, odt, smp, sbase, ysh);
     }
     if (HASV) {
@@ -286,6 +299,9 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
         if (tile >= ntile) return;
         tile_range(a, tile, base, cnt);
         K nk[IT];
+        // a tile's shift is read before its keys: loads complete in order, so
+        // waiting for the shift never waits for the keys in flight behind it
+        u32 ngsh = a.gsh ? a.gsh[tile / (u32)a.tpb] : 0u;
         load_blocked<K, IT>(a.in + base + i0, cnt - i0, nk);
 #pragma unroll
         for (int j = 0; j < IT; j++) v[j] = 0;
@@ -294,16 +310,17 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
             for (int j = 0; j < IT; j++) kr[j] = nk[j];
             const i64 cbase = base;
             const int ccnt = cnt;
-            const u32 ctile = tile;
+            const u32 ctile = tile, cgsh = ngsh;
             tile += gridDim.x;
             // the next tile's keys are in flight while this one is sorted
             if (tile < ntile) {
                 tile_range(a, tile, base, cnt);
+                ngsh = a.gsh ? a.gsh[tile / (u32)a.tpb] : 0u;
                 load_blocked<K, IT>(a.in + base + i0, cnt - i0, nk);
             }
             if (ccnt > 0)
                 tile_sort_body<K, HASV>(a, sm, kr, v, ccnt, cbase, a.out, a.outv, a.out_dt, a.smp,
-                                        (i64)ctile * a.spt);
+                                        (i64)ctile * a.spt, (int)uniform(cgsh));
             if (tile >= ntile) break;
             __syncthreads();
         }
@@ -386,9 +403,11 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
     }
     const int cnt = cnt64 <= 0 ? 0 : (cnt64 > NT * IT ? NT * IT : (int)cnt64);
     if (cnt == 0) return;
+    // the shift is read first, so that its latency hides behind the key loads
+    const u32 gsh = (a.gsh && !a.btab) ? a.gsh[blockIdx.x / (u32)a.tpb] : 0u;
     load_blocked<K, IT>(a.in + base + i0, cnt - i0, kr);
     if (HASV) load_blocked<u32, IT>(a.inv + base + i0, cnt - i0, v);
-    tile_sort_body<K, HASV>(a, sm, kr, v, cnt, base, outk, outv, odt, smp, sbase);
+    tile_sort_body<K, HASV>(a, sm, kr, v, cnt, base, outk, outv, odt, smp, sbase, (int)uniform(gsh));
 }
 
 // ======================================================================= MWM: pick boundaries
@@ -483,6 +502,7 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     const u32 nheavy = *a.nheavy;
     for (u32 h = blockIdx.x; h < nheavy; h += gridDim.x) {
         const u32 g = uniform(a.heavy[h]);
+        const int gsh = a.gsh ? (int)uniform(a.gsh[g]) : 0;
         const uint4 gp = a.gpar[2 * (i64)g];
         const u32 f = uniform(gp.x), Sg = uniform(gp.y), q = uniform(gp.z), dsh = uniform(gp.w);
         const u32 gb = uniform(a.grp_base[g]), nb = uniform(a.grp_nb[g]);
@@ -571,8 +591,16 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
                     int mid = (lo + hi) >> 1;
                     if (spre[mid] <= c) lo = mid; else hi = mid;
                 }
-                a.bkey[gb + b - 1] = key[j];
-                a.bpos[gb + b - 1] = sd[lo * 4 + 2] + (c - spre[lo]) * sd[lo * 4 + 3];
+                if (gsh > 0) {
+                    // runs sorted by key >> gsh: the boundary is every record whose
+                    // high part is at most this one's (largest key of that part,
+                    // any position)
+                    a.bkey[gb + b - 1] = key[j] | (K)((((K)1) << gsh) - 1);
+                    a.bpos[gb + b - 1] = 0xFFFFFFFFu;
+                } else {
+                    a.bkey[gb + b - 1] = key[j];
+                    a.bpos[gb + b - 1] = sd[lo * 4 + 2] + (c - spre[lo]) * sd[lo * 4 + 3];
+                }
             }
         }
         __syncthreads();  // LDS is reused by the next listed group
@@ -1162,6 +1190,71 @@ __global__ void k_det_sample(const K* B, i64 n, int p, int s, K* skey, u32* spos
     const i64 q = ((i64)j * x < mk ? (i64)j * x : mk) - 1;
     skey[idx] = B[st + q];
     spos[idx] = (u32)(st + q);
+}
+
+// Shift of the truncated tile sort of every block (TileArgs.gsh): the tiles
+// of a multi-tile block may be sorted on the order key's high part key >> gsh
+// alone, which saves the LSD passes over the low gsh bits; the block merge
+// then cuts the block's runs on the high part and sorts every chunk in full,
+// so the block comes out exactly sorted whatever the shift. One workgroup per
+// block samples TRUNC_S of its keys, evenly spread: the shift keeps `keep`
+// bits of their range, so that groups of equal high parts hold a few keys of
+// the block on average. A boundary of the merge moves to the end of its group,
+// so a large group makes chunks overflow LDS (such a chunk is sorted through
+// global memory): a high part seen TRUNC_DUP times or more among the samples
+// switches the truncation off for the block. Uniform keys repeat one of the
+// block's m/4 high parts that often with odds below 1e-5 at m = 2^20; a group
+// of 1/64 of the block is seen 16 times on average. The samples are counted in
+// an LDS table of 2-bit counters indexed by the high part (relative to the
+// samples' least), coarsened to TRUNC_E entries when the range has more high
+// parts than that: a coarse entry only counts more, never less. A counter
+// that reads 3 before its increment is the fourth hit (TRUNC_DUP); it carries
+// into its neighbour only at the fifth, after the flag is set.
+constexpr int TRUNC_NT = 256, TRUNC_PER = 4, TRUNC_S = TRUNC_NT * TRUNC_PER, TRUNC_DUP = 4;
+constexpr int TRUNC_LGE = 18, TRUNC_E = 1 << TRUNC_LGE;  // 2^18 counters, 64 KiB of LDS
+static_assert(TRUNC_DUP == 4, "a 2-bit counter tells the fourth hit");
+
+template <typename K>
+__global__ __launch_bounds__(TRUNC_NT) void k_trunc_probe(const K* in, int dt, i64 n, int p, int keep, u32* gsh) {
+    __shared__ u32 tab[TRUNC_E / 16];
+    __shared__ u64 red[TRUNC_NT / 64 * 2];
+    __shared__ u32 dup;
+    const int t = threadIdx.x, k = blockIdx.x;
+    const i64 st = blk_start(n, p, k), m = blk_start(n, p, k + 1) - st;
+    K u[TRUNC_PER];
+    K mn = KeyMax<K>::v, mx = 0;
+#pragma unroll
+    for (int j = 0; j < TRUNC_PER; j++) {
+        const i64 idx = st + (i64)(((u64)(t * TRUNC_PER + j) * (u64)m) / (u64)TRUNC_S);
+        u[j] = m > 0 ? okey<K>(in[idx], dt) : (K)0;
+        mn = u[j] < mn ? u[j] : mn;
+        mx = u[j] > mx ? u[j] : mx;
+    }
+    block_minmax<TRUNC_NT, K>(mn, mx, red);
+    const int bits = bitwidth64((u64)(mx - mn));
+    const int d = bits > keep ? bits - keep : 0;
+    if (d == 0) {
+        if (t == 0) gsh[k] = 0u;
+        return;
+    }
+    for (int i = t; i < TRUNC_E / 16; i += TRUNC_NT) tab[i] = 0u;
+    if (t == 0) dup = 0u;
+    __syncthreads();
+    // high parts relative to the least one span at most 2^keep + 1 values
+    const int c = keep + 1 > TRUNC_LGE ? keep + 1 - TRUNC_LGE : 0;
+    const K base = mn >> d;
+    u32 hit = 0;
+#pragma unroll
+    for (int j = 0; j < TRUNC_PER; j++) {
+        const u64 e64 = (u64)((u[j] >> d) - base) >> c;
+        const u32 e = e64 < (u64)TRUNC_E ? (u32)e64 : (u32)(TRUNC_E - 1);
+        const u32 sh = (e & 15u) * 2u;
+        const u32 old = atomicAdd(&tab[e >> 4], 1u << sh);
+        hit |= ((old >> sh) & 3u) == 3u ? 1u : 0u;
+    }
+    if (hit) dup = 1u;
+    __syncthreads();
+    if (t == 0) gsh[k] = dup ? 0u : (u32)d;
 }
 
 // Random sample (Figure SortRI step 4): s*p - 1 distinct positions of the

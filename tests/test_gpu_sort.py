@@ -338,3 +338,33 @@ def test_sr_edges(ora, dev, case):
         bsps.sort_(t, 32, 8, bsps.RAN_SR, 3, values=v, untagged=True)
         assert np.array_equal(t.cpu().numpy(), keys[np.argsort(keys, kind="stable")])
         assert np.array_equal(v.cpu().numpy().view(np.uint32), np.argsort(keys, kind="stable").astype(np.uint32))
+
+
+@pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
+def test_truncated_tile_sort(ora, dev, dtype):
+    """Tiles of multi-tile blocks sorted on the key's high part only, the block
+    merge cutting on that part and sorting every chunk in full: on spread-out
+    keys the truncation is on, on keys with a value of 1/64 of the input it is
+    off, and in every case the block-sorted array, splitters, counts and output
+    equal the oracle's. Last, a value filling a quarter of every block but
+    none of the 1024 positions the shift's probe samples (block k's sample i
+    sits at start_k + floor(i m_k / 1024)): the truncation stays on, and the
+    value's group, larger than a merge chunk, pushes chunks to the
+    global-memory sort."""
+    n, p = 1_300_001, 8  # blocks of about 10 tiles
+    keys = W.random_keys(n, dtype, seed=61)
+    st = _check(ora, dev, keys, p, 32, ora.DET, kv=True)
+    assert st["trunc_shift"] > 0
+    heavy = keys.copy()
+    heavy[np.random.default_rng(62).choice(n, n // 64, replace=False)] = heavy[0]
+    st = _check(ora, dev, heavy, p, 32, ora.RAN, kv=True, seed=5)
+    assert st["trunc_shift"] == 0
+    missed = keys.copy()
+    rng = np.random.default_rng(63)
+    for k in range(p):
+        lo, hi = k * n // p, (k + 1) * n // p
+        m = hi - lo
+        free = np.setdiff1d(np.arange(lo, hi), lo + (np.arange(1024) * m) // 1024)
+        missed[rng.choice(free, m // 4, replace=False)] = keys[n // 2]
+    st = _check(ora, dev, missed, p, 32, ora.DET, kv=True)
+    assert st["trunc_shift"] > 0 and st["oversize_block"] > 0
