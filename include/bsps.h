@@ -137,7 +137,10 @@ typedef struct bsps_stats {
     int64_t* sample_pos;       /* their positions in the block-sorted array (RAN_SR: in the input) */
     int64_t* bucket_sizes;     /* p */
     int64_t* count_matrix;     /* p*p, row k = source block, column i = bucket */
-    void* block_sorted;        /* n keys: every block sorted (Figure SortD step 3) */
+    void* block_sorted;        /* n keys: every block sorted (Figure SortD step 3); with a block
+                                  shift D > 0 (reserved_i[3] bits 8-15) sorted on the order key
+                                  >> D only, equal keys in input order: a stable sort of each
+                                  block by key gives the exactly sorted block */
     uint32_t* block_sorted_values; /* n payloads, kv calls only */
     void* routed;              /* n keys after routing (route = SCATTER, or variant RAN_SR) */
     uint32_t* buckets;         /* n bucket ids of block_sorted (route = SCATTER), of the input (RAN_SR) */
@@ -146,9 +149,11 @@ typedef struct bsps_stats {
     double mean_fix_dist;      /* learned bucketing: mean |predicted - true| */
     int64_t oversize_chunks;   /* merge chunks sorted by the global-memory path */
     int64_t reserved_i[4];     /* bsps_sort: [0] oversize chunks of the block merge, [1] of the
-                                  bucket merge, [2] keys in the largest one, [3] the most low key bits
-                                  the tile sort left to the block merge in any block (0: every
-                                  block's tiles fully sorted). bsps_sort_segmented:
+                                  bucket merge, [2] keys in the largest one, [3] bits 0-7: the most
+                                  low key bits the tile sort left to the block merge in any block
+                                  (0: every block's tiles fully sorted), bits 8-15: the block shift
+                                  D, the low key bits the block merge left to the bucket merge
+                                  (route FUSED, one round). bsps_sort_segmented:
                                   [0] blocks, [1] merged segments, [2] 1 if the graph was captured
                                   and launched by this call, 2 if a cached graph was launched,
                                   [3] segments with learned bucketing (NL) */

@@ -218,7 +218,9 @@ def sort_(keys, p: int, s: int, variant: int = DET, seed: int = 1, values=None, 
     out["mean_fix_dist"] = st.mean_fix_dist
     out["oversize_chunks"] = st.oversize_chunks
     out["oversize_block"], out["oversize_bucket"], out["oversize_max"] = (int(x) for x in st.reserved_i[:3])
-    out["trunc_shift"] = int(st.reserved_i[3])  # low key bits the tile sort left to the block merge
+    # low key bits the tile sort left to the block merge, and the block merge to the bucket merge
+    out["trunc_shift"] = int(st.reserved_i[3]) & 0xFF
+    out["block_shift"] = (int(st.reserved_i[3]) >> 8) & 0xFF
     return out
 
 

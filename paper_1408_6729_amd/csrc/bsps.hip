@@ -177,7 +177,8 @@ void dry_check(const MwmArgs<K>& a) {
     dry_span("MwmArgs.grp_base", a.grp_base, G);
     dry_span("MwmArgs.grp_nb", a.grp_nb, G);
     dry_span("MwmArgs.bkey", a.bkey, S);
-    dry_span("MwmArgs.gsh", a.gsh, G);
+    dry_span("MwmArgs.gsh", a.gsh, a.gsh_one ? 1 : G);
+    dry_span("MwmArgs.ssh", a.ssh, 1);
     dry_span("MwmArgs.bpos", a.bpos, S);
     dry_span("MwmArgs.cuts", a.cuts, S * R);
     dry_span("MwmArgs.below", a.below, S);
@@ -387,7 +388,13 @@ bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     const u32 gmerge = BSPS_MERGE_WGS_PER_CU > 0 ? (u32)std::min<u64>(a.S, (u64)cus * BSPS_MERGE_WGS_PER_CU) : a.S;
     {
         StageScope sc(kstage, st);
-        LAUNCH((k_mwm_merge<K, HASV>), dim3(gmerge), dim3(NT), 0, st, a);
+        // with a sort shift (known on the device only) both variants are
+        // launched, and the one that does not fit its value returns at once
+        if (a.ssh) {
+            LAUNCH((k_mwm_merge<K, HASV, true>), dim3(gmerge), dim3(NT), 0, st, a);
+            LAUNCH_OK();
+        }
+        LAUNCH((k_mwm_merge<K, HASV, false>), dim3(gmerge), dim3(NT), 0, st, a);
     }
     LAUNCH_OK();
     return BSPS_OK;
@@ -451,7 +458,7 @@ template <typename K, bool HASV>
 bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, int in_dt, K* out, u32* outv,
                        int out_dt, K* scr, u32* scrv, i64 n, int p, u32 cap, u32 tavg, K* osmp, u32 yb, u32 spb,
                        hipStream_t st, int tstage = ST_N, int mstage = ST_N, int mkstage = ST_N,
-                       u32* gsh = nullptr, int keep = 0) {
+                       u32* gsh = nullptr, int keep = 0, u32* bsh = nullptr) {
     constexpr int NT = Shape<K>::NT;
     const u32 T = tileT<K>();
     TileArgs<K> ta{};
@@ -471,6 +478,10 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
         if (gsh) {
             LAUNCH((k_trunc_probe<K>), dim3((u32)p), dim3(TRUNC_NT), 0, st, in, in_dt, n, p, keep, gsh);
             LAUNCH_OK();
+            if (bsh) {
+                LAUNCH(k_min_shift, dim3(1), dim3(256), 0, st, (const u32*)gsh, p, bsh);
+                LAUNCH_OK();
+            }
         }
         LAUNCH((k_tile_sort<K, HASV>), dim3(tgrid), dim3(NT), 0, st, ta);
     }
@@ -482,6 +493,7 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
     LAUNCH_OK();
     MwmArgs<K> a = mwm_args<K>(b.mwm, b.A, b.Av, out, outv, scr, scrv, b.tsmp, cap, tavg, out_dt, osmp, yb, spb);
     a.gsh = gsh;
+    a.ssh = gsh ? bsh : nullptr;  // blocks sorted on key >> *bsh only
     return mwm_run<K, HASV>(a, st, mkstage);
 }
 
@@ -625,6 +637,7 @@ struct Plan {
     LsdSweep lsw;            // LSD: look-back status, tickets, tiles of every block
     BlockSortBufs<K> bs;     // main block sort
     u32* gsh;                // shift of its truncated tile sort (k_trunc_probe), or NULL
+    u32* bsh;                // [1] the block shift D (blocks sorted on key >> D), or NULL
     K* B;
     u32* Bv;
     K* bsmp;                 // block samples (every kSampleStride-th key of each block)
@@ -756,6 +769,8 @@ size_t carve_plan_sr(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params*
     return c.off + 256;
 }
 
+constexpr int kBlockShiftMaxP = 256;
+
 template <typename K>
 size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* prm) {
     if (prm->variant == BSPS_RAN_SR) return carve_plan_sr<K>(c, P, n, hasv, prm);
@@ -777,7 +792,7 @@ size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* pr
         std::memset(&P.lsw, 0, sizeof(P.lsw));
         carve_block_sort<K>(c, P.bs, (u64)n, p, hasv, o.tavg, true);  // A doubles as merge scratch / routed array
     }
-    P.gsh = (!P.lsd && P.bs.tpb > 1) ? c.take<u32>((u64)p) : nullptr;
+    P.gsh = (!P.lsd && P.bs.tpb > 1) ? c.take<u32>((u64)p + 1) : nullptr;
     P.B = c.take<K>(n);
     P.Bv = hasv ? c.take<u32>(n) : nullptr;
     const u64 m = cdiv((u64)n, (u64)p);
@@ -821,6 +836,12 @@ size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* pr
     }
     P.m = prm->rounds >= 2 && p > 1 ? prm->rounds : 1;
     P.k = iter_k(p, P.m);
+    // Blocks left sorted on key >> D (the fused route of the one-round sort),
+    // for p <= kBlockShiftMaxP: a boundary of the bucket merge then gains about
+    // half a group of every one of the p runs, and the splitter groups are
+    // fixed by p^2 threads; at p = 1024 (2^28 float keys) that cost more than
+    // the block merge saved.
+    P.bsh = (P.gsh && !scatter && P.m < 2 && p > 1 && p <= kBlockShiftMaxP) ? P.gsh + p : nullptr;
     P.grp0 = P.grp1 = nullptr;
     P.itsmp0 = P.itsmp1 = nullptr;
     P.itspb = 0;
@@ -1249,14 +1270,15 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         const int keep = std::max(12, bitw(cdiv((u64)n, (u64)p) - 1) - 2);
         rc = block_sort<K, HASV>(P.bs, io, vals, dt, P.B, P.Bv, BSPS_DT_NONE, io, vals, n, p, o.cap, o.tavg, P.bsmp,
                                  kSampleStride, std::max<u32>(1, P.spb), st, ST_TILE, ST_BLOCK_MERGE,
-                                 ST_BLOCK_MERGE_K, P.gsh, keep);
+                                 ST_BLOCK_MERGE_K, P.gsh, keep, P.bsh);
     }
     if (rc) return rc;
     if (stats && P.gsh) {
-        std::vector<u32> gs((size_t)p);
+        std::vector<u32> gs((size_t)p + 1);
         rc = d2h(gs.data(), P.gsh, 4 * gs.size(), st);
         if (rc) return rc;
-        stats->reserved_i[3] = *std::max_element(gs.begin(), gs.end());
+        stats->reserved_i[3] = *std::max_element(gs.begin(), gs.begin() + p);
+        if (P.bsh) stats->reserved_i[3] |= (i64)gs[(size_t)p] << 8;
     }
     if (stats && P.lsd) {
         rc = sweep_overruns(P.lsw, st);
@@ -1288,8 +1310,8 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
         StageScope sc(ST_SAMPLE, st);
         // A2: sample records (key, position in B), in position order.
         if (prm->variant == BSPS_DET) {
-            LAUNCH((k_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, n, p, s, P.skey,
-                               P.spos);
+            LAUNCH((k_det_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, n, p, s,
+                   (const u32*)P.bsh, P.skey, P.spos);
             LAUNCH_OK();
         } else {
             LAUNCH(k_ran_positions, dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, (u64)prm->seed, n, ns,
@@ -1299,8 +1321,8 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
             rc = block_sort<u32, false>(P.rs, P.rpos, nullptr, BSPS_DT_NONE, P.spos, nullptr, BSPS_DT_NONE, P.rpos_scr,
                                         nullptr, ns, 1, ou.cap, ou.tavg, nullptr, 1, 1, st);
             if (rc) return rc;
-            LAUNCH((k_gather_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, P.spos, ns,
-                               P.skey);
+            LAUNCH((k_gather_sample<K>), dim3((u32)cdiv(ns, 256)), dim3(256), 0, st, P.B, n, p,
+                   (const u32*)P.bsh, P.spos, ns, P.skey);
             LAUNCH_OK();
         }
         // A3: sort the sample by (key, position): stable by key, input in position order.
@@ -1319,10 +1341,17 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
     {
         StageScope sc(ST_COUNT, st);
         const u64 ncnt = (u64)(p + 1) * p;
-        if (P.spb > 0 && P.spb <= (u32)COUNT_SMAX)
+        const bool staged = P.spb > 0 && P.spb <= (u32)COUNT_SMAX;
+        if (staged) {
+            // (does nothing under a block shift)
             LAUNCH((k_count_staged<K>), dim3(p), dim3(COUNT_NT), 0, st, P.B, n, p, P.pk, P.pcmp, P.bsmp, P.spb,
-                   kSampleStride, P.cntT);
-        else
+                   kSampleStride, (const u32*)P.bsh, P.cntT);
+            LAUNCH_OK();
+        }
+        if (P.bsh)  // blocks sorted on key >> D: the splitters' groups made exact as they are counted
+            LAUNCH((k_count_fix<K, HASV>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, HASV ? P.Bv : nullptr,
+                   n, p, (const K*)P.pk, (const u32*)P.pcmp, (const u32*)P.bsh, staged ? 1 : 0, P.cntT);
+        else if (!staged)
             LAUNCH((k_count<K>), dim3((u32)cdiv(ncnt, 256)), dim3(256), 0, st, P.B, n, p, P.pk, P.pcmp, P.cntT);
         LAUNCH_OK();
     }
@@ -1339,6 +1368,12 @@ bsps_status run_sort(void* keys, u32* vals, i64 n, int dt, const bsps_params* pr
             StageScope sc(ST_BUCKET_MERGE, st);
             MwmArgs<K> a =
                 mwm_args<K>(P.bm, P.B, P.Bv, io, vals, P.bs.A, P.bs.Av, P.bsmp, o.cap, o.tavg, dt, nullptr, 1, 1);
+            // runs sorted on key >> D: every bucket cuts them on that part; a
+            // group of a block holds about 4 keys (the shift keeps lg(block) - 2
+            // bits of its range), so a boundary gains about 2 keys per run
+            a.gsh = P.bsh;
+            a.gsh_one = 1u;
+            a.ggrow = 2u * (u32)p;
             rc = mwm_run<K, HASV>(a, st, ST_BUCKET_MERGE_K);
             if (rc) return rc;
         }

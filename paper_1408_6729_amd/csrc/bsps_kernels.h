@@ -109,7 +109,19 @@ struct MwmArgs {
     const u32* gsh;        // optional, per group: its runs sorted by key >> gsh[g] only (see TileArgs):
                            // boundaries then cut on that part alone, never inside a group of equal
                            // high parts
+    u32 gsh_one;           // nonzero: every group's runs use the one shift gsh[0]
+    u32 ggrow;             // keys a boundary gains over all runs when cut on a high part (estimate)
+    // Optional [1]: with *ssh = D > 0 a chunk is sorted on key >> D only, when
+    // no group of equal key >> D holds more than TRUNC_L of its records (else
+    // in full), so the output is sorted on key >> D and every such group of
+    // more than TRUNC_L records is exactly sorted. Needs boundaries on a part
+    // at least as coarse (gsh >= D), so that no such group spans two chunks.
+    const u32* ssh;
 };
+
+// Largest group of equal key >> D that a chunk sorted on key >> D may hold:
+// one wave sorts such a group in place.
+constexpr int TRUNC_L = 64;
 
 // Per-tile sort arguments. Tile t of block k covers
 // [start_k + t*T, min(start_k + (t+1)*T, end_k)).
@@ -460,7 +472,11 @@ __global__ __launch_bounds__(SIZE_NT) void k_mwm_size(MwmArgs<K> a) {
         // after its last subsample, which the last chunk holds: the boundary
         // count covers Sg + dsh ranks so that those keys are not left over.
         const float ys = (float)(sd[3] ? sd[3] : 1u);
-        const float off = 0.5f * (float)R * (float)f * ys / yeff;
+        float off = 0.5f * (float)R * (float)f * ys / yeff;
+        // Runs cut on a high part: every boundary moves to the end of its
+        // group, about ggrow keys further over all runs, which again only the
+        // first chunk keeps.
+        if (a.ggrow && a.gsh && a.gsh[a.gsh_one ? 0u : g] > 0u) off += (float)a.ggrow / yeff;
         dsh = off >= (float)(q - 1) ? q - 1 : (u32)off;
         nb = (Sg + dsh) / q;
     }
@@ -502,7 +518,7 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     const u32 nheavy = *a.nheavy;
     for (u32 h = blockIdx.x; h < nheavy; h += gridDim.x) {
         const u32 g = uniform(a.heavy[h]);
-        const int gsh = a.gsh ? (int)uniform(a.gsh[g]) : 0;
+        const int gsh = a.gsh ? (int)uniform(a.gsh[a.gsh_one ? 0u : g]) : 0;
         const uint4 gp = a.gpar[2 * (i64)g];
         const u32 f = uniform(gp.x), Sg = uniform(gp.y), q = uniform(gp.z), dsh = uniform(gp.w);
         const u32 gb = uniform(a.grp_base[g]), nb = uniform(a.grp_nb[g]);
@@ -889,15 +905,18 @@ struct MergeSmem {
     u32 slot;
 };
 
-template <typename K, bool HASV>
+template <typename K, bool HASV, bool TR>
 __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4 wi0, const uint4 wi1,
                                                 MergeSmem<K>& S);
 
 // Persistent merge: workgroups take work items (runs of chunks) one after
-// another; the next item is claimed while the current one is merged.
-template <typename K, bool HASV>
+// another; the next item is claimed while the current one is merged. TR: the
+// code for a sort shift (MwmArgs.ssh), left out of the other merges.
+template <typename K, bool HASV, bool TR = false>
 __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_mwm_merge(MwmArgs<K> a) {
     __shared__ MergeSmem<K> S;
+    // with a sort shift both variants are launched; the one for its value runs
+    if (a.ssh && ((*a.ssh != 0u) != TR)) return;
     const u32 nwork = min(a.S, *a.nwork);
     if (threadIdx.x == 0) S.slot = atomicAdd(a.work, 1u);
     __syncthreads();
@@ -906,14 +925,14 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_mwm_merge(MwmA
         __syncthreads();  // every thread has read S.slot
         if (w >= nwork) break;
         if (threadIdx.x == 0) S.slot = atomicAdd(a.work, 1u);
-        mwm_merge_chunk<K, HASV>(a, a.witem[2 * (i64)w], a.witem[2 * (i64)w + 1], S);
+        mwm_merge_chunk<K, HASV, TR>(a, a.witem[2 * (i64)w], a.witem[2 * (i64)w + 1], S);
         __syncthreads();
         w = S.slot;
     }
 }
 
 // Merges the chunks slot .. slot_last of one group (one LDS sort).
-template <typename K, bool HASV>
+template <typename K, bool HASV, bool TR>
 __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4 wi0, const uint4 wi1,
                                                 MergeSmem<K>& S) {
     constexpr int NT = Shape<K>::NT, IT = Shape<K>::IT;
@@ -926,6 +945,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
     PHASE_START;
     const u32 slot = uniform(wi0.x), slot_last = uniform(wi0.y), g = uniform(wi0.z), c = uniform(wi0.w);
     const u32 cl = uniform(wi1.x), nb = uniform(wi1.y), obase = uniform(wi1.z);
+    const u32 dsh0 = (TR && a.ssh) ? *a.ssh : 0u;
     const u32* lorow = a.cuts + (i64)(slot - 1) * R;
     const u32* hirow = a.cuts + (i64)slot_last * R;
     const u32* rl = a.run_len + (i64)g * R;
@@ -1122,7 +1142,44 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
 #endif
     block_minmax<NT, K>(mn, mx, sm.red64);
     PHASE(2);
-    const int nbits = uniform(bitwidth64((u64)(mx - mn)));
+    // sort on key >> dsh only when no group of equal key >> dsh holds more
+    // than TRUNC_L of the chunk's records: each item is counted in an LDS
+    // histogram of its high part (relative to the chunk's least, coarsened to
+    // 2^13 bins, which only counts more)
+    int dsh = (int)uniform(dsh0);
+    if (TR && dsh > 0) {
+        constexpr int TB = 1 << 13;
+        u32* bins = sm.cnt();
+        const K hlo = mn >> dsh;
+        const int wb = bitwidth64((u64)((mx >> dsh) - hlo));
+        const int cb = wb > 13 ? wb - 13 : 0;
+        for (int i = t; i < TB; i += NT) bins[i] = 0u;
+        if (t == 0) sm.misc[0] = 0u;
+        __syncthreads();
+        u32 big = 0;
+#pragma unroll
+        for (int j = 0; j < IT; j++)
+            if (item_ok(j)) {
+                const u32 e = (u32)((u64)((kr[j] >> dsh) - hlo) >> cb);
+                big |= atomicAdd(&bins[e], 1u) >= (u32)TRUNC_L ? 1u : 0u;
+            }
+        if (big) sm.misc[0] = 1u;
+        __syncthreads();
+        if (sm.misc[0]) dsh = 0;
+        // the range starts at a multiple of 2^dsh, so (key - mn) >> dsh orders like key >> dsh
+        if (dsh > 0) mn &= ~(K)((((K)1) << dsh) - 1);
+        // the padding needs a high part above every key's (see below): a key
+        // range that leaves none sorts in full
+        if (((u64)(mx - mn) >> dsh) + 1 > ((sizeof(K) == 4 ? 0xFFFFFFFFull : ~0ull) >> dsh)) dsh = 0;
+    }
+    // Sort keys are rebased on mn; the tail items past N are padding that must
+    // sort after every key. Sorted in full it is the largest key (ties with it
+    // are the same key); sorted on the high part it takes the next high part,
+    // since keys-only merges rank items in an order where the padding is not
+    // last and a tie by high part would push a key out of the chunk.
+    const u64 top = dsh > 0 ? ((((u64)(mx - mn)) >> dsh) + 1) << dsh : (u64)(mx - mn);
+    const int nbits = uniform(bitwidth64(top));
+    const int sbits = nbits > dsh ? nbits - dsh : 0;
     const u32 gstart = obase;
     const u32 osh = a.oys ? (u32)(__ffs(a.oys) - 1) : 0u;
     const u32 om = (1u << osh) - 1;
@@ -1141,8 +1198,8 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
     if (sizeof(K) == 8 && nbits > 32) {
         u64 sk[IT];
 #pragma unroll
-        for (int j = 0; j < IT; j++) sk[j] = item_ok(j) ? (u64)(kr[j] - mn) : (u64)(mx - mn);
-        wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
+        for (int j = 0; j < IT; j++) sk[j] = item_ok(j) ? (u64)(kr[j] - mn) : top;
+        wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, sbits, sm.template ex<u64>(), sm.cnt(), sm.wsum, dsh);
         const u64* e = sm.template ex<u64>();
 #pragma unroll
         for (int j = 0; j < IT; j++) {
@@ -1153,8 +1210,8 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
     } else {
         u32 sk[IT];
 #pragma unroll
-        for (int j = 0; j < IT; j++) sk[j] = item_ok(j) ? (u32)(kr[j] - mn) : (u32)(mx - mn);
-        wg_sort_regs<NT, IT, u32, HASV>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
+        for (int j = 0; j < IT; j++) sk[j] = item_ok(j) ? (u32)(kr[j] - mn) : (u32)top;
+        wg_sort_regs<NT, IT, u32, HASV>(sk, v, rank, sbits, vex, sm.cnt(), sm.wsum, dsh);
         PHASE(3);
 #pragma unroll
         for (int j = 0; j < IT; j++) {
@@ -1177,18 +1234,131 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
 
 // ======================================================================= sample and splitters
 
+// ======================================================================= high-part sorted blocks
+
+// A block sorted on key >> D only (D > 0; the block merge with MwmArgs.ssh):
+// every group of equal key >> D keeps its records in input order, and a group
+// of more than TRUNC_L records is exactly sorted. Sorting every group stably
+// by key gives the exactly sorted block, the same set of positions per group.
+// block_key_at: the key at rank q of the exactly sorted block [st, st + mk)
+// of B. The group around position q is found by scanning at most TRUNC_L
+// records each way: a longer group is exact and holds that key at q; in a
+// shorter one the key is the one with q - lo keys of the group below it.
+template <typename K>
+__device__ K block_key_at(const K* B, i64 st, i64 mk, i64 q, int D) {
+    const K x = B[st + q];
+    if (D <= 0) return x;
+    const K h = x >> D;
+    i64 lo = q, hi = q + 1;
+    while (lo > 0 && q - lo < TRUNC_L && (B[st + lo - 1] >> D) == h) lo--;
+    while (hi < mk && hi - lo <= TRUNC_L && (B[st + hi] >> D) == h) hi++;
+    if (hi - lo > TRUNC_L) return x;
+    const int g = (int)(hi - lo), r = (int)(q - lo);
+    for (int i = 0; i < g; i++) {
+        const K xi = B[st + lo + i];
+        int less = 0, leq = 0;
+        for (int j = 0; j < g; j++) {
+            const K xj = B[st + lo + j];
+            less += xj < xi ? 1 : 0;
+            leq += xj <= xi ? 1 : 0;
+        }
+        if (less <= r && r < leq) return xi;
+    }
+    return x;  // not reached: the ranks of the group cover 0 .. g - 1
+}
+
+// The block shift D: the least tile-sort shift over the blocks (0 when some
+// block's tiles were fully sorted). One workgroup.
+__global__ __launch_bounds__(256) void k_min_shift(const u32* gsh, int p, u32* bsh) {
+    __shared__ u32 red[4];
+    u32 m = 0xFFFFFFFFu;
+    for (int k = threadIdx.x; k < p; k += 256) m = min(m, gsh[k]);
+    for (int o = 32; o >= 1; o >>= 1) m = min(m, (u32)__shfl_xor((int)m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) *bsh = min(min(red[0], red[1]), min(red[2], red[3]));
+}
+
+// Counts under a block shift D = *bsh (cntT as k_count), on blocks sorted on
+// key >> D only. One thread per (splitter i, block k). Records at or below a
+// splitter and records above it mix only inside the group of records whose
+// key >> D equals the splitter's. The thread of the first splitter with that
+// high part sorts the group in place, stably by key with its payloads (2 ..
+// TRUNC_L records; a longer group is exactly sorted already), then counts for
+// every splitter sharing the group, by bisection from the group's start:
+// "record <= splitter" by key then position is monotone along the fixed block.
+// Other threads only compare high parts inside a group being sorted, which
+// every record of it shares. With D = 0 every thread bisects for its own
+// splitter, unless only_shift is set (then k_count_staged has counted).
+template <typename K, bool HASV>
+__global__ void k_count_fix(K* B, u32* Bv, i64 n, int p, const K* pk, const u32* pp, const u32* bsh, int only_shift,
+                            u32* cntT) {
+    const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (i64)(p + 1) * p) return;
+    const int D = (int)*bsh;
+    if (D == 0 && only_shift) return;
+    const int i = (int)(idx / p), k = (int)(idx % p);
+    const i64 st = blk_start(n, p, k), mk = blk_start(n, p, k + 1) - st;
+    if (i == 0 || i == p) {
+        cntT[idx] = i == 0 ? 0u : (u32)mk;
+        return;
+    }
+    // records <= splitter ii in [lo, hi) of the block, the predicate true before lo and false from hi
+    auto count = [&](int ii, u32 lo, u32 hi) -> u32 {
+        const K sk = pk[ii - 1];
+        const u32 sp = pp[ii - 1];
+        while (lo < hi) {
+            const u32 mid = (lo + hi) >> 1;
+            if (rec_le<K>(B[st + mid], (u32)(st + mid), sk, sp)) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    if (D == 0) {
+        cntT[idx] = count(i, 0u, (u32)mk);
+        return;
+    }
+    const K h = pk[i - 1] >> D;
+    if (i > 1 && (pk[i - 2] >> D) == h) return;  // counted with the first splitter of the group
+    u32 lo = 0, hi = (u32)mk;  // the group's first record: the first whose high part is >= h
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if ((B[st + mid] >> D) < h) lo = mid + 1; else hi = mid;
+    }
+    const u32 glo = lo;
+    u32 g = 0;
+    while (glo + g < (u32)mk && g <= (u32)TRUNC_L && (B[st + glo + g] >> D) == h) g++;
+    if (g >= 2 && g <= (u32)TRUNC_L) {
+        K* bk = B + st + glo;
+        u32* bv = HASV ? Bv + st + glo : nullptr;
+        for (u32 a = 1; a < g; a++) {
+            const K x = bk[a];
+            const u32 v = HASV ? bv[a] : 0u;
+            u32 b = a;
+            for (; b > 0 && bk[b - 1] > x; b--) {
+                bk[b] = bk[b - 1];
+                if (HASV) bv[b] = bv[b - 1];
+            }
+            bk[b] = x;
+            if (HASV) bv[b] = v;
+        }
+    }
+    // past a group of at most TRUNC_L records every high part is above h
+    const u32 gend = g <= (u32)TRUNC_L ? glo + g : (u32)mk;
+    for (int ii = i; ii < p && (pk[ii - 1] >> D) == h; ii++) cntT[(i64)ii * p + k] = count(ii, glo, gend);
+}
+
 // Regular sample (Figure SortD step 4): block k contributes the keys closing
 // its s segments of x = ceil(ceil(n/p)/s) keys; positions past a short
 // block's end are clamped to its last key. Written in position order.
 template <typename K>
-__global__ void k_det_sample(const K* B, i64 n, int p, int s, K* skey, u32* spos) {
+__global__ void k_det_sample(const K* B, i64 n, int p, int s, const u32* bsh, K* skey, u32* spos) {
     const i64 idx = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (i64)p * s) return;
     const int k = (int)(idx / s), j = (int)(idx % s) + 1;
     const i64 st = blk_start(n, p, k), mk = blk_start(n, p, k + 1) - st;
     const i64 m = (n + p - 1) / p, x = (m + s - 1) / s;
     const i64 q = ((i64)j * x < mk ? (i64)j * x : mk) - 1;
-    skey[idx] = B[st + q];
+    skey[idx] = block_key_at<K>(B, st, mk, q, bsh ? (int)*bsh : 0);
     spos[idx] = (u32)(st + q);
 }
 
@@ -1202,16 +1372,20 @@ __global__ void k_det_sample(const K* B, i64 n, int p, int s, K* skey, u32* spos
 // the block on average. A boundary of the merge moves to the end of its group,
 // so a large group makes chunks overflow LDS (such a chunk is sorted through
 // global memory): a high part seen TRUNC_DUP times or more among the samples
-// switches the truncation off for the block. Uniform keys repeat one of the
+// makes the probe try smaller shifts (a few outlying keys widen the range and
+// so every group), and switches the truncation off for the block when
+// TRUNC_TRIES shifts all see one. Uniform keys repeat one of the
 // block's m/4 high parts that often with odds below 1e-5 at m = 2^20; a group
 // of 1/64 of the block is seen 16 times on average. The samples are counted in
-// an LDS table of 2-bit counters indexed by the high part (relative to the
-// samples' least), coarsened to TRUNC_E entries when the range has more high
-// parts than that: a coarse entry only counts more, never less. A counter
-// that reads 3 before its increment is the fourth hit (TRUNC_DUP); it carries
-// into its neighbour only at the fifth, after the flag is set.
+// an LDS table of TRUNC_E 2-bit counters indexed by a multiplicative hash of
+// the high part (Fibonacci hashing), whatever the range: distinct high parts
+// share a counter only by collision, and four samples of four distinct high
+// parts land on one counter with odds about C(1024, 4) / TRUNC_E^3 = 2.5e-6.
+// A counter that reads 3 before its increment is the fourth hit (TRUNC_DUP);
+// it carries into its neighbour only at the fifth, after the flag is set.
 constexpr int TRUNC_NT = 256, TRUNC_PER = 4, TRUNC_S = TRUNC_NT * TRUNC_PER, TRUNC_DUP = 4;
 constexpr int TRUNC_LGE = 18, TRUNC_E = 1 << TRUNC_LGE;  // 2^18 counters, 64 KiB of LDS
+constexpr int TRUNC_TRIES = 4;
 static_assert(TRUNC_DUP == 4, "a 2-bit counter tells the fourth hit");
 
 template <typename K>
@@ -1232,29 +1406,29 @@ __global__ __launch_bounds__(TRUNC_NT) void k_trunc_probe(const K* in, int dt, i
     }
     block_minmax<TRUNC_NT, K>(mn, mx, red);
     const int bits = bitwidth64((u64)(mx - mn));
-    const int d = bits > keep ? bits - keep : 0;
-    if (d == 0) {
-        if (t == 0) gsh[k] = 0u;
-        return;
-    }
-    for (int i = t; i < TRUNC_E / 16; i += TRUNC_NT) tab[i] = 0u;
-    if (t == 0) dup = 0u;
-    __syncthreads();
-    // high parts relative to the least one span at most 2^keep + 1 values
-    const int c = keep + 1 > TRUNC_LGE ? keep + 1 - TRUNC_LGE : 0;
-    const K base = mn >> d;
-    u32 hit = 0;
+    const int d0 = bits > keep ? bits - keep : 0;
+    // A few outlying keys widen the range and so the groups; when a group is
+    // seen too often, smaller shifts are tried (TRUNC_TRIES in all).
+    int d = d0;
+    for (; d > 0 && d > d0 - TRUNC_TRIES; d--) {
+        for (int i = t; i < TRUNC_E / 16; i += TRUNC_NT) tab[i] = 0u;
+        if (t == 0) dup = 0u;
+        __syncthreads();
+        u32 hit = 0;
 #pragma unroll
-    for (int j = 0; j < TRUNC_PER; j++) {
-        const u64 e64 = (u64)((u[j] >> d) - base) >> c;
-        const u32 e = e64 < (u64)TRUNC_E ? (u32)e64 : (u32)(TRUNC_E - 1);
-        const u32 sh = (e & 15u) * 2u;
-        const u32 old = atomicAdd(&tab[e >> 4], 1u << sh);
-        hit |= ((old >> sh) & 3u) == 3u ? 1u : 0u;
+        for (int j = 0; j < TRUNC_PER; j++) {
+            const u32 e = (u32)(((u64)(u[j] >> d) * 0x9E3779B97F4A7C15ull) >> (64 - TRUNC_LGE));
+            const u32 sh = (e & 15u) * 2u;
+            const u32 old = atomicAdd(&tab[e >> 4], 1u << sh);
+            hit |= ((old >> sh) & 3u) == 3u ? 1u : 0u;
+        }
+        if (hit) dup = 1u;
+        __syncthreads();
+        const bool clean = dup == 0u;
+        __syncthreads();  // every thread has read dup before the next try clears it
+        if (clean) break;
     }
-    if (hit) dup = 1u;
-    __syncthreads();
-    if (t == 0) gsh[k] = dup ? 0u : (u32)d;
+    if (t == 0) gsh[k] = (d > 0 && d > d0 - TRUNC_TRIES) ? (u32)d : 0u;
 }
 
 // Random sample (Figure SortRI step 4): s*p - 1 distinct positions of the
@@ -1266,10 +1440,19 @@ __global__ void k_ran_positions(u64 seed, i64 n, i64 ns, u32* pos) {
 }
 
 template <typename K>
-__global__ void k_gather_sample(const K* B, const u32* pos, i64 ns, K* skey) {
+__global__ void k_gather_sample(const K* B, i64 n, int p, const u32* bsh, const u32* pos, i64 ns, K* skey) {
     const i64 t = (i64)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ns) return;
-    skey[t] = B[pos[t]];
+    const i64 q = pos[t];
+    const int D = bsh ? (int)*bsh : 0;
+    if (D == 0) {
+        skey[t] = B[q];
+        return;
+    }
+    // the block holding q: the largest k with floor(k n / p) <= q
+    const int k = (int)(((u64)(q + 1) * (u64)p + (u64)n - 1) / (u64)n) - 1;
+    const i64 st = blk_start(n, p, k), mk = blk_start(n, p, k + 1) - st;
+    skey[t] = block_key_at<K>(B, st, mk, q - st, D);
 }
 
 // Splitters: sorted sample records at 1-based ranks s, 2s, ..., (p-1)s.
@@ -1311,15 +1494,18 @@ __global__ void k_count(const K* B, i64 n, int p, const K* pk, const u32* pp, u3
 // ys-th key, at block positions (j+1)*ys - 1; floor(mk/ys) of them) are staged
 // in LDS and each splitter is bisected there, so only the last bisection,
 // inside one sample stride, reads the block in global memory. For blocks of
-// at most COUNT_SMAX samples.
+// at most COUNT_SMAX samples. Under a block shift (bsh != NULL and *bsh > 0)
+// it does nothing: k_count_fix counts.
 constexpr int COUNT_NT = 256, COUNT_SMAX = 8192;
 
 template <typename K>
 __global__ __launch_bounds__(COUNT_NT) void k_count_staged(const K* B, i64 n, int p, const K* pk, const u32* pp,
-                                                           const K* bsmp, u32 spb, u32 ys, u32* cntT) {
+                                                           const K* bsmp, u32 spb, u32 ys, const u32* bsh,
+                                                           u32* cntT) {
     __shared__ K ls[COUNT_SMAX];
     const int k = blockIdx.x, t = threadIdx.x;
     const i64 st = blk_start(n, p, k), mk = blk_start(n, p, k + 1) - st;
+    if (bsh && *bsh > 0u) return;
     const u32 ns = min((u32)(mk / ys), spb);
     for (u32 j = t; j < ns; j += COUNT_NT) ls[j] = bsmp[(i64)k * spb + j];
     __syncthreads();

@@ -43,6 +43,35 @@ def _bits(a):
     return a.view(np.uint32) if a.dtype == np.float32 else a
 
 
+def _order(a):
+    """Order keys (unsigned, same width) of int32 / int64 / float32 keys."""
+    if a.dtype == np.float32:
+        u = a.view(np.uint32)
+        return np.where(u >> 31 == 1, ~u, u | np.uint32(0x80000000))
+    if a.dtype == np.int32:
+        return a.view(np.uint32) ^ np.uint32(0x80000000)
+    return a.view(np.uint64) ^ np.uint64(1 << 63)
+
+
+def _exact_blocks(B, Bv, p, D):
+    """Blocks sorted on order key >> D only, equal keys in input order: checks
+    that, then returns the blocks sorted stably by key (the exactly sorted
+    blocks)."""
+    B = B.copy()
+    Bv = None if Bv is None else Bv.copy()
+    n = B.size
+    for k in range(p):
+        lo, hi = k * n // p, (k + 1) * n // p
+        o = _order(B[lo:hi])
+        h = o >> o.dtype.type(D)
+        assert np.all(h[1:] >= h[:-1]), f"block {k} not sorted on key >> {D}"
+        idx = np.argsort(o, kind="stable")
+        B[lo:hi] = B[lo:hi][idx]
+        if Bv is not None:
+            Bv[lo:hi] = Bv[lo:hi][idx]
+    return B, Bv
+
+
 def _check(ora, dev, keys, p, s, variant, seed=1, kv=False, chunk_cap=0, check_B=True, local_sort=0, untagged=False,
            route=0):
     vals = np.arange(keys.size, dtype=np.uint32) if kv else None
@@ -58,9 +87,12 @@ def _check(ora, dev, keys, p, s, variant, seed=1, kv=False, chunk_cap=0, check_B
         assert np.array_equal(st["count_matrix"], ref["C"]), "count matrix differs"
         assert np.array_equal(st["bucket_sizes"], ref["bucket_sizes"])
     if check_B:
-        assert np.array_equal(_bits(st["block_sorted"]), _bits(ref["B_keys"])), "block-sorted array differs"
+        B, Bv = st["block_sorted"], (st["block_sorted_values"][:keys.size] if kv else None)
+        if st.get("block_shift", 0):
+            B, Bv = _exact_blocks(B, Bv, p, st["block_shift"])
+        assert np.array_equal(_bits(B), _bits(ref["B_keys"])), "block-sorted array differs"
         if kv:
-            assert np.array_equal(st["block_sorted_values"][:keys.size], ref["B_values"])
+            assert np.array_equal(Bv, ref["B_values"])
     return st
 
 
@@ -343,10 +375,11 @@ def test_sr_edges(ora, dev, case):
 @pytest.mark.parametrize("dtype", ["int32", "int64", "float32"])
 def test_truncated_tile_sort(ora, dev, dtype):
     """Tiles of multi-tile blocks sorted on the key's high part only, the block
-    merge cutting on that part and sorting every chunk in full: on spread-out
-    keys the truncation is on, on keys with a value of 1/64 of the input it is
-    off, and in every case the block-sorted array, splitters, counts and output
-    equal the oracle's. Last, a value filling a quarter of every block but
+    merge cutting on that part, and the blocks themselves left sorted on a high
+    part (the block shift): on spread-out keys both are on, on keys with a
+    value of 1/64 of the input they are off, and in every case the block-sorted
+    array (after a stable sort of every block), sample, splitters, counts and
+    output equal the oracle's. Last, a value filling a quarter of every block but
     none of the 1024 positions the shift's probe samples (block k's sample i
     sits at start_k + floor(i m_k / 1024)): the truncation stays on, and the
     value's group, larger than a merge chunk, pushes chunks to the
@@ -354,7 +387,13 @@ def test_truncated_tile_sort(ora, dev, dtype):
     n, p = 1_300_001, 8  # blocks of about 10 tiles
     keys = W.random_keys(n, dtype, seed=61)
     st = _check(ora, dev, keys, p, 32, ora.DET, kv=True)
-    assert st["trunc_shift"] > 0
+    assert st["trunc_shift"] > 0 and st["block_shift"] > 0
+    # every value about three times: groups of equal high parts hold equal
+    # keys on both sides of a splitter, which the tags must order
+    few = keys[np.random.default_rng(64).integers(0, n // 3, n)]
+    for variant, untagged in ((ora.DET, False), (ora.RAN, False), (ora.DET, True)):
+        st = _check(ora, dev, few, p, 32, variant, kv=True, seed=7, untagged=untagged)
+        assert st["block_shift"] > 0
     heavy = keys.copy()
     heavy[np.random.default_rng(62).choice(n, n // 64, replace=False)] = heavy[0]
     st = _check(ora, dev, heavy, p, 32, ora.RAN, kv=True, seed=5)
@@ -367,4 +406,14 @@ def test_truncated_tile_sort(ora, dev, dtype):
         free = np.setdiff1d(np.arange(lo, hi), lo + (np.arange(1024) * m) // 1024)
         missed[rng.choice(free, m // 4, replace=False)] = keys[n // 2]
     st = _check(ora, dev, missed, p, 32, ora.DET, kv=True)
-    assert st["trunc_shift"] > 0 and st["oversize_block"] > 0
+    assert st["trunc_shift"] > 0 and st["oversize_block"] > 0 and st["block_shift"] > 0
+
+
+def test_block_shift_limit(ora, dev):
+    """The blocks stay exactly sorted above 256 virtual processors (the block
+    shift is off), and below it on all-equal keys (the tile sort is full)."""
+    keys = W.random_keys(10_240_001, "int32", seed=65)  # blocks of 2 tiles
+    st = _check(ora, dev, keys, 512, 4, ora.DET)
+    assert st["trunc_shift"] > 0 and st["block_shift"] == 0
+    st = _check(ora, dev, np.full(1 << 21, 7, dtype=np.int32), 64, 8, ora.RAN, kv=True)
+    assert st["trunc_shift"] == 0 and st["block_shift"] == 0
