@@ -479,7 +479,7 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
             LAUNCH((k_trunc_probe<K>), dim3((u32)p), dim3(TRUNC_NT), 0, st, in, in_dt, n, p, keep, gsh);
             LAUNCH_OK();
             if (bsh) {
-                LAUNCH(k_min_shift, dim3(1), dim3(256), 0, st, (const u32*)gsh, p, bsh);
+                LAUNCH(k_min_shift, dim3(1), dim3(256), 0, st, (const u32*)(gsh + p + 1), p, bsh);
                 LAUNCH_OK();
             }
         }
@@ -494,6 +494,9 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
     MwmArgs<K> a = mwm_args<K>(b.mwm, b.A, b.Av, out, outv, scr, scrv, b.tsmp, cap, tavg, out_dt, osmp, yb, spb);
     a.gsh = gsh;
     a.ssh = gsh ? bsh : nullptr;  // blocks sorted on key >> *bsh only
+    // a block's groups of equal tile-shift high parts: m / 2^TRUNC_KEEPC keys
+    // on average, each boundary gaining about half of one (k_trunc_probe)
+    if (gsh) a.ggrow = (u32)(cdiv(cdiv((u64)n, (u64)p), (u64)1 << TRUNC_KEEPC));
     return mwm_run<K, HASV>(a, st, mkstage);
 }
 
@@ -792,7 +795,8 @@ size_t carve_plan(Carver& c, Plan<K>& P, i64 n, bool hasv, const bsps_params* pr
         std::memset(&P.lsw, 0, sizeof(P.lsw));
         carve_block_sort<K>(c, P.bs, (u64)n, p, hasv, o.tavg, true);  // A doubles as merge scratch / routed array
     }
-    P.gsh = (!P.lsd && P.bs.tpb > 1) ? c.take<u32>((u64)p + 1) : nullptr;
+    // the tile shifts of the p blocks, the block shift, the p fine shifts
+    P.gsh = (!P.lsd && P.bs.tpb > 1) ? c.take<u32>(2 * (u64)p + 1) : nullptr;
     P.B = c.take<K>(n);
     P.Bv = hasv ? c.take<u32>(n) : nullptr;
     const u64 m = cdiv((u64)n, (u64)p);

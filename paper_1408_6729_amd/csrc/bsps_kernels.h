@@ -1267,12 +1267,13 @@ __device__ K block_key_at(const K* B, i64 st, i64 mk, i64 q, int D) {
     return x;  // not reached: the ranks of the group cover 0 .. g - 1
 }
 
-// The block shift D: the least tile-sort shift over the blocks (0 when some
-// block's tiles were fully sorted). One workgroup.
-__global__ __launch_bounds__(256) void k_min_shift(const u32* gsh, int p, u32* bsh) {
+// The block shift D: the least fine shift of the probe over the blocks
+// (fine[k] = gsh[p + 1 + k]; 0 when some block's tiles were fully sorted).
+// One workgroup.
+__global__ __launch_bounds__(256) void k_min_shift(const u32* fine, int p, u32* bsh) {
     __shared__ u32 red[4];
     u32 m = 0xFFFFFFFFu;
-    for (int k = threadIdx.x; k < p; k += 256) m = min(m, gsh[k]);
+    for (int k = threadIdx.x; k < p; k += 256) m = min(m, fine[k]);
     for (int o = 32; o >= 1; o >>= 1) m = min(m, (u32)__shfl_xor((int)m, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
@@ -1383,10 +1384,22 @@ __global__ void k_det_sample(const K* B, i64 n, int p, int s, const u32* bsh, K*
 // parts land on one counter with odds about C(1024, 4) / TRUNC_E^3 = 2.5e-6.
 // A counter that reads 3 before its increment is the fourth hit (TRUNC_DUP);
 // it carries into its neighbour only at the fifth, after the flag is set.
+//
+// That fine shift d (groups of about 4 keys of the block) is what the block
+// shift needs (gsh[p + 1 + k]; k_min_shift takes their least into gsh[p]).
+// The tiles themselves may be sorted on a coarser part: the block merge's
+// chunk sort ranks every bit below it anyway, and its boundaries only need
+// groups well inside a chunk. The tile shift gsh[k] keeps TRUNC_KEEPC bits of
+// the range when that is fewer than `keep` (groups of m / 2^12 keys, 256 at
+// m = 2^20: two 6-bit passes instead of three), unless a coarse group is seen
+// TRUNC_DUPC times among the samples (a group of 6/1024 of the block on
+// average; 4-bit counters, 2^TRUNC_LGC of them, hashed alike), and else is d.
 constexpr int TRUNC_NT = 256, TRUNC_PER = 4, TRUNC_S = TRUNC_NT * TRUNC_PER, TRUNC_DUP = 4;
 constexpr int TRUNC_LGE = 18, TRUNC_E = 1 << TRUNC_LGE;  // 2^18 counters, 64 KiB of LDS
 constexpr int TRUNC_TRIES = 4;
+constexpr int TRUNC_KEEPC = 12, TRUNC_DUPC = 6, TRUNC_LGC = 16;
 static_assert(TRUNC_DUP == 4, "a 2-bit counter tells the fourth hit");
+static_assert((1 << TRUNC_LGC) / 8 <= TRUNC_E / 16, "the coarse counters reuse the fine table");
 
 template <typename K>
 __global__ __launch_bounds__(TRUNC_NT) void k_trunc_probe(const K* in, int dt, i64 n, int p, int keep, u32* gsh) {
@@ -1428,7 +1441,29 @@ __global__ __launch_bounds__(TRUNC_NT) void k_trunc_probe(const K* in, int dt, i
         __syncthreads();  // every thread has read dup before the next try clears it
         if (clean) break;
     }
-    if (t == 0) gsh[k] = (d > 0 && d > d0 - TRUNC_TRIES) ? (u32)d : 0u;
+    const int dk = (d > 0 && d > d0 - TRUNC_TRIES) ? d : 0;
+    int dc = dk;
+    const int c = bits - TRUNC_KEEPC;
+    if (dk > 0 && c > dk) {
+        for (int i = t; i < (1 << TRUNC_LGC) / 8; i += TRUNC_NT) tab[i] = 0u;
+        if (t == 0) dup = 0u;
+        __syncthreads();
+        u32 hit = 0;
+#pragma unroll
+        for (int j = 0; j < TRUNC_PER; j++) {
+            const u32 e = (u32)(((u64)(u[j] >> c) * 0x9E3779B97F4A7C15ull) >> (64 - TRUNC_LGC));
+            const u32 sh = (e & 7u) * 4u;
+            const u32 old = atomicAdd(&tab[e >> 3], 1u << sh);
+            hit |= ((old >> sh) & 15u) + 1u >= (u32)TRUNC_DUPC ? 1u : 0u;
+        }
+        if (hit) dup = 1u;
+        __syncthreads();
+        if (dup == 0u) dc = c;
+    }
+    if (t == 0) {
+        gsh[k] = (u32)dc;
+        gsh[p + 1 + k] = (u32)dk;
+    }
 }
 
 // Random sample (Figure SortRI step 4): s*p - 1 distinct positions of the
