@@ -437,6 +437,23 @@ __global__ __launch_bounds__(Shape<K>::NT, BSPS_WG_PER_CU) void k_tile_sort(Tile
 // sized for).
 constexpr int SIZE_NT = 256;
 
+// Subsample of the merge's boundary pick: run r takes its samples r mod f,
+// r mod f + f, ... (of s_r samples). Its count, and their total over the R
+// runs of a group (one workgroup).
+__device__ __forceinline__ u32 mwm_sub_count(u32 s_r, int r, u32 f) {
+    const u32 ph = (u32)r % f;
+    return s_r > ph ? (s_r - 1u - ph) / f + 1u : 0u;
+}
+template <int NT>
+__device__ u32 mwm_sub_total(const u32* sd, int R, u32 f, u32* wsum) {
+    u32 my = 0;
+    for (int r = threadIdx.x; r < R; r += NT) my += mwm_sub_count(sd[r * 4 + 1], r, f);
+    u32 tot;
+    __syncthreads();  // wsum is free
+    (void)block_excl_scan<NT>(my, tot, wsum);
+    return tot;
+}
+
 template <typename K>
 __global__ __launch_bounds__(SIZE_NT) void k_mwm_size(MwmArgs<K> a) {
     constexpr int T = Shape<K>::NT * Shape<K>::IT;
@@ -455,8 +472,22 @@ __global__ __launch_bounds__(SIZE_NT) void k_mwm_size(MwmArgs<K> a) {
     (void)block_excl_scan<SIZE_NT>(myn, N, wsum);
     u32 nb = 0, f = 1, Sg = 0, q = 1, dsh = 0;
     if (N > a.cap && Sraw > 0) {
+        // Subsample: every f-th sample of each run, run r from its sample
+        // r mod f on (mwm_sub_count). Every run's j-th sample sits near the
+        // same quantile when the runs are alike (tiles of one block), so with
+        // one phase for all runs the subsamples line up across runs near both
+        // ends of the key range, and a boundary there takes the keys below a
+        // whole row of them at once: chunks of up to R * f * ys keys. With
+        // the phases staggered the rows interleave.
         f = (Sraw + T - 1) / T;
-        Sg = Sraw / f;
+        Sg = mwm_sub_total<SIZE_NT>(sd, R, f, wsum);
+        if (Sg > (u32)T) {  // a run's count rounds up by less than 1: one more step fits
+            f++;
+            Sg = mwm_sub_total<SIZE_NT>(sd, R, f, wsum);
+        }
+        if (Sg > (u32)T) Sg = 0;  // (R <= T / 3 rules it out) no boundaries: one chunk
+    }
+    if (N > a.cap && Sg > 0) {
         const float yeff = (float)N / (float)Sg;
         const float spread = 4.0f * yeff * sqrtf((float)R / 3.0f);
         float tgf = (float)a.cap - spread;
@@ -513,6 +544,7 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     __shared__ SortSmem<NT, (int)sizeof(K), IT> sm;
     __shared__ u32 spre[MAXR + 1];
     __shared__ u32 sbase[MAXR];  // first sample index of each run
+    __shared__ u32 spre2[MAXR + 1];  // prefix of the runs' subsample counts
     u32* vex = sm.template ex<u32>();
     const int t = threadIdx.x, R = a.R;
     const u32 nheavy = *a.nheavy;
@@ -523,23 +555,35 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
         const u32 f = uniform(gp.x), Sg = uniform(gp.y), q = uniform(gp.z), dsh = uniform(gp.w);
         const u32 gb = uniform(a.grp_base[g]), nb = uniform(a.grp_nb[g]);
         const u32* sd = a.sdesc + (i64)g * R * 4;
-        // exclusive prefix of the runs' sample counts (runs in order)
+        // exclusive prefixes of the runs' sample and subsample counts (runs in order)
         const int RPT = (R + NT - 1) / NT;
-        u32 mys = 0;
-        for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) mys += sd[r * 4 + 1];
-        u32 totS;
-        u32 ex = block_excl_scan<NT>(mys, totS, sm.wsum);
+        u32 mys = 0, myq = 0;
+        for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
+            mys += sd[r * 4 + 1];
+            myq += mwm_sub_count(sd[r * 4 + 1], r, f);
+        }
+        // one scan of both sums: sample counts (low 32 bits), subsample counts (high)
+        u64 both;
+        const u64 exb = block_excl_scan64<NT>(((u64)myq << 32) | mys, both, sm.red64);
+        u32 ex = (u32)exb, ex2 = (u32)(exb >> 32);
         for (int r = t * RPT; r < (t + 1) * RPT && r < R; r++) {
             spre[r] = ex;
+            spre2[r] = ex2;
             sbase[r] = sd[r * 4 + 0];
             ex += sd[r * 4 + 1];
+            ex2 += mwm_sub_count(sd[r * 4 + 1], r, f);
         }
-        if (t == 0) spre[R] = totS;
+        if (t == 0) {
+            spre[R] = (u32)both;
+            spre2[R] = (u32)(both >> 32);  // = Sg
+        }
         __syncthreads();
-        // load the subsample: element i is concatenated sample index (i+1)*f - 1.
-        // A thread's elements are consecutive, so the run holding its first one is
-        // found by bisection and the rest by walking; every sample index is formed
-        // first and all loads are then issued together.
+        // load the subsample: element i is run r's sample (r mod f) + (i -
+        // spre2[r]) * f, r the run with spre2[r] <= i < spre2[r + 1]; c, its
+        // concatenated sample index, increases with i. A thread's elements are
+        // consecutive, so the run holding its first one is found by bisection
+        // and the rest by walking; every sample index is formed first and all
+        // loads are then issued together.
         K mn = KeyMax<K>::v, mx = 0;
         u32 v[IT], rank[IT];
         K key[IT];
@@ -547,11 +591,10 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
             const u32 i0 = (u32)(t * IT);
             int r = 0;
             if (i0 < Sg) {
-                const u32 c0 = (i0 + 1) * f - 1;
-                int lo = 0, hi = R;  // largest r with spre[r] <= c0 (a run with samples)
+                int lo = 0, hi = R;  // largest r with spre2[r] <= i0 (a run with subsamples)
                 while (hi - lo > 1) {
                     const int mid = (lo + hi) >> 1;
-                    if (spre[mid] <= c0) lo = mid; else hi = mid;
+                    if (spre2[mid] <= i0) lo = mid; else hi = mid;
                 }
                 r = lo;
             }
@@ -561,8 +604,8 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
                 v[j] = 0;
                 key[j] = 0;
                 if (i < Sg) {
-                    const u32 c = (i + 1) * f - 1;
-                    while (spre[r + 1] <= c) r++;  // stops at r < R: spre[R] = Sraw > c
+                    while (spre2[r + 1] <= i) r++;  // stops at r < R: spre2[R] = Sg > i
+                    const u32 c = spre[r] + (u32)r % f + (i - spre2[r]) * f;
                     key[j] = (K)(sbase[r] + (c - spre[r]));
                     v[j] = c;
                 }

@@ -417,3 +417,20 @@ def test_block_shift_limit(ora, dev):
     assert st["trunc_shift"] > 0 and st["block_shift"] == 0
     st = _check(ora, dev, np.full(1 << 21, 7, dtype=np.int32), 64, 8, ora.RAN, kv=True)
     assert st["trunc_shift"] == 0 and st["block_shift"] == 0
+
+
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_merge_plan_int64_no_oversize(ora, dev, dist):
+    """The tiles of a block are alike, so every run's j-th sample sits near the
+    same quantile; the boundary pick's subsample starts each run at a
+    different phase, so that the subsamples do not line up across the runs
+    near both ends of the key range. With one phase the block merge of int64
+    key-value blocks of 128 tiles left ~10-15 chunks per block past the tile
+    (a boundary took a whole row of aligned subsamples at once); now none."""
+    n, p = 1 << 24, 16  # blocks of 2^20 int64 keys: 128 tiles of 8 Ki
+    if dist == "uniform":
+        keys = W.random_keys(n, "int64", seed=71)
+    else:
+        keys, _ = W.zipf_int64_kv(n, equal_frac=0.0, seed=72)
+    st = _check(ora, dev, keys, p, 32, ora.DET, kv=True)
+    assert st["oversize_block"] == 0
