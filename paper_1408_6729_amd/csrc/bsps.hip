@@ -497,6 +497,10 @@ bsps_status block_sort(const BlockSortBufs<K>& b, const K* in, const u32* inv, i
     // a block's groups of equal tile-shift high parts: m / 2^TRUNC_KEEPC keys
     // on average, each boundary gaining about half of one (k_trunc_probe)
     if (gsh) a.ggrow = (u32)(cdiv(cdiv((u64)n, (u64)p), (u64)1 << TRUNC_KEEPC));
+    // 8-byte keys: a block's chunks span wide key ranges (up to ten digit
+    // passes each), so fuller merge items outweigh the extra cuts; the bucket
+    // merge's narrower chunks do not gain
+    a.pack = sizeof(K) == 8 ? 1u : 0u;
     return mwm_run<K, HASV>(a, st, mkstage);
 }
 
