@@ -375,7 +375,15 @@ bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     // gridDim.y waves so that the launch still holds some 8K waves
     const u64 nwave = std::max<u64>(1, (u64)a.G * a.R);
     const u32 ysplit = (u32)std::min<u64>(64, std::max<u64>(1, cdiv(8192, nwave)));
-    LAUNCH((k_mwm_cuts<K>), dim3((u32)cdiv(nwave, CUT_NT / 64), ysplit), dim3(CUT_NT), 0, st, a);
+    // window counts by half-waves pay off with 4-byte keys and some 32 or more
+    // boundaries per group (chunks fill about 7/8 of the cap); the keys per
+    // group follow from the slot capacity S = keys / tavg + 2 G + 1
+    const u64 per_group = ((u64)a.S - 2ull * a.G - 1) * a.tavg / std::max<u64>(1, a.G);
+    const bool coop = sizeof(K) == 4 && per_group >= 28ull * a.cap;
+    if (coop)
+        LAUNCH((k_mwm_cuts<K, true>), dim3((u32)cdiv(nwave, CUT_NT / 64), ysplit), dim3(CUT_NT), 0, st, a);
+    else
+        LAUNCH((k_mwm_cuts<K, false>), dim3((u32)cdiv(nwave, CUT_NT / 64), ysplit), dim3(CUT_NT), 0, st, a);
     LAUNCH_OK();
     LAUNCH((k_mwm_below<K>), dim3((u32)std::min<u64>(cdiv(a.S, 4), (u64)cus * 16)), dim3(256), 0, st,
                        a);

@@ -687,8 +687,11 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
 // gridDim.y splits the boundaries of a (group, run) over several waves when
 // there are few runs.
 constexpr int CUT_NT = 256, CUT_SMAX = 1024;
+#ifndef BSPS_CUT_BP
+#define BSPS_CUT_BP 8  // boundary pairs whose window loads are issued together
+#endif
 
-template <typename K>
+template <typename K, bool COOP>
 __global__ __launch_bounds__(CUT_NT) void k_mwm_cuts(MwmArgs<K> a) {
     __shared__ K ls[CUT_NT / 64][CUT_SMAX];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, R = a.R;
@@ -717,31 +720,90 @@ __global__ __launch_bounds__(CUT_NT) void k_mwm_cuts(MwmArgs<K> a) {
     if (!live || nb == 0) return;
     const u32 r = (u32)(gr % R);
     const u32 step = 64u * gridDim.y;
-    for (u32 c = blockIdx.y * 64u + lane; c < nb; c += step) {
+    const int half = lane >> 5, hl = lane & 31;
+    for (u32 c0 = blockIdx.y * 64u; c0 < nb; c0 += step) {
+        const u32 c = c0 + (u32)lane;
+        const bool act = c < nb;
         const u32 slot = gb + c;
-        const K bk = a.bkey[slot];
-        const u32 bp = a.bpos[slot];
-        // J = samples of this run that are <= the boundary
-        u32 lo = 0, hi = scnt;
-        if (staged) {
-            while (lo < hi) {
-                const u32 mid = (lo + hi) >> 1;
-                if (rec_le<K>(st[mid], pb + mid * sstr, bk, bp)) lo = mid + 1; else hi = mid;
+        K bk = 0;
+        u32 bp = 0, wlo = 0, whi = 0;
+        if (act) {
+            bk = a.bkey[slot];
+            bp = a.bpos[slot];
+            // J = samples of this run that are <= the boundary
+            u32 lo = 0, hi = scnt;
+            if (staged) {
+                while (lo < hi) {
+                    const u32 mid = (lo + hi) >> 1;
+                    if (rec_le<K>(st[mid], pb + mid * sstr, bk, bp)) lo = mid + 1; else hi = mid;
+                }
+            } else {
+                while (lo < hi) {
+                    const u32 mid = (lo + hi) >> 1;
+                    if (rec_le<K>(a.smp[sidx + mid], pb + mid * sstr, bk, bp)) lo = mid + 1; else hi = mid;
+                }
             }
-        } else {
-            while (lo < hi) {
-                const u32 mid = (lo + hi) >> 1;
-                if (rec_le<K>(a.smp[sidx + mid], pb + mid * sstr, bk, bp)) lo = mid + 1; else hi = mid;
+            const u32 J = lo;
+            wlo = J > 0 ? pb + (J - 1) * sstr - rs + 1 : 0u;
+            whi = J < scnt ? pb + J * sstr - rs : len;
+        }
+        // The cut lies in [wlo, whi): the records between two neighbouring
+        // samples, fewer than the stride. COOP (4-byte keys, many boundaries per
+        // group): when every window of the wave holds at most 32 records (stride
+        // 32), a half-wave reads one boundary's window in one coalesced load and
+        // counts the records at or below the boundary with a ballot (they are a
+        // prefix of the window, the run being sorted): per boundary one request
+        // for one or two cache lines instead of a bisection's five dependent
+        // ones, each a line of its own. The windows of 2 BP boundaries are read
+        // together so their loads are in flight at once. Only for boundaries on
+        // a high part (runs sorted under a shift, which the probe allows only
+        // without heavy duplicates): where many boundaries share a key, the
+        // lanes' bisections read the same lines and are cheaper. With few
+        // boundaries per wave the batch is mostly idle, so the bisection alone
+        // is built there.
+        const u32 wl = whi - wlo;
+        constexpr int BP = BSPS_CUT_BP;  // boundary pairs per batch
+        if (COOP && __all(!act || (wl <= 32u && bp == 0xFFFFFFFFu))) {
+            const u32 nact = min(64u, nb - c0);
+            u32 res = 0;
+            for (u32 m0 = 0; m0 < nact; m0 += 2u * BP) {
+                K v[BP];
+                u32 pos[BP];
+                bool in[BP];
+#pragma unroll
+                for (int q = 0; q < BP; q++) {
+                    const int src = (int)m0 + 2 * q + half;
+                    const u32 w0 = (u32)__shfl((int)wlo, src, 64), wn = (u32)__shfl((int)wl, src, 64);
+                    in[q] = (u32)hl < wn;
+                    pos[q] = rs + w0 + (u32)hl;
+                    v[q] = in[q] ? a.src[pos[q]] : (K)0;
+                }
+#pragma unroll
+                for (int q = 0; q < BP; q++) {
+                    const int src = (int)m0 + 2 * q + half;
+                    K kq;
+                    if (sizeof(K) == 8) {
+                        const u64 kb = (u64)bk;
+                        const u32 lo32 = (u32)__shfl((int)(u32)kb, src, 64), hi32 = (u32)__shfl((int)(u32)(kb >> 32), src, 64);
+                        kq = (K)(((u64)hi32 << 32) | lo32);
+                    } else {
+                        kq = (K)(u32)__shfl((int)(u32)bk, src, 64);
+                    }
+                    const u32 pq = (u32)__shfl((int)bp, src, 64);
+                    const unsigned long long bal = __ballot(in[q] && rec_le<K>(v[q], pos[q], kq, pq));
+                    const u32 m = m0 + 2u * (u32)q;
+                    if ((u32)lane == m) res = (u32)__popcll(bal & 0xFFFFFFFFull);
+                    if ((u32)lane == m + 1u) res = (u32)__popcll(bal >> 32);
+                }
             }
+            if (act) a.cuts[(i64)slot * R + r] = wlo + res;
+        } else if (act) {
+            while (wlo < whi) {
+                const u32 mid = (wlo + whi) >> 1;
+                if (rec_le<K>(a.src[rs + mid], rs + mid, bk, bp)) wlo = mid + 1; else whi = mid;
+            }
+            a.cuts[(i64)slot * R + r] = wlo;
         }
-        const u32 J = lo;
-        u32 wlo = J > 0 ? pb + (J - 1) * sstr - rs + 1 : 0u;
-        u32 whi = J < scnt ? pb + J * sstr - rs : len;
-        while (wlo < whi) {
-            const u32 mid = (wlo + whi) >> 1;
-            if (rec_le<K>(a.src[rs + mid], rs + mid, bk, bp)) wlo = mid + 1; else whi = mid;
-        }
-        a.cuts[(i64)slot * R + r] = wlo;
     }
 }
 
