@@ -381,7 +381,7 @@ bsps_status mwm_run(const MwmArgs<K>& a, hipStream_t st, int kstage = ST_N) {
     const u64 per_group = ((u64)a.S - 2ull * a.G - 1) * a.tavg / std::max<u64>(1, a.G);
     const bool coop = sizeof(K) == 4 && per_group >= 28ull * a.cap;
     if (coop)
-        LAUNCH((k_mwm_cuts<K, true>), dim3((u32)cdiv(nwave, CUT_NT / 64), ysplit), dim3(CUT_NT), 0, st, a);
+        LAUNCH((k_mwm_cuts<K, sizeof(K) == 4>), dim3((u32)cdiv(nwave, CUT_NT / 64), ysplit), dim3(CUT_NT), 0, st, a);
     else
         LAUNCH((k_mwm_cuts<K, false>), dim3((u32)cdiv(nwave, CUT_NT / 64), ysplit), dim3(CUT_NT), 0, st, a);
     LAUNCH_OK();

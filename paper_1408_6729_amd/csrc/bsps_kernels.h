@@ -628,22 +628,29 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
             }
         }
         block_minmax<NT, K>(mn, mx, sm.red64);
-        const int nbits = bitwidth64((u64)(mx - mn));
+        // with runs cut on key >> gsh a boundary takes the upper bound of its
+        // high part, and the high part at a given rank does not depend on the
+        // order inside equal high parts: the subsample is sorted on the high
+        // part only (the minimum aligned down so that the order is key >> gsh's)
+        const K mna = gsh > 0 ? (K)(mn & ~((((K)1) << gsh) - 1)) : mn;
+        const int nbits = bitwidth64((u64)((mx - mna) >> gsh));
         if (sizeof(K) == 8 && nbits > 32) {
             u64 sk[IT];
     #pragma unroll
-            for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u64)(key[j] - mn) : (u64)(mx - mn);
+            for (int j = 0; j < IT; j++)
+                sk[j] = (u64)(((u32)(t * IT + j) < Sg ? key[j] - mna : mx - mna) >> gsh);
             wg_sort_regs<NT, IT, u64, true, false>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
             u64* e = sm.template ex<u64>();
     #pragma unroll
-            for (int j = 0; j < IT; j++) key[j] = (K)(e[padi(t * IT + j)] + (u64)mn);
+            for (int j = 0; j < IT; j++) key[j] = (K)((e[padi(t * IT + j)] << gsh) + (u64)mna);
         } else {
             u32 sk[IT];
     #pragma unroll
-            for (int j = 0; j < IT; j++) sk[j] = (u32)(t * IT + j) < Sg ? (u32)(key[j] - mn) : (u32)(mx - mn);
+            for (int j = 0; j < IT; j++)
+                sk[j] = (u32)(((u32)(t * IT + j) < Sg ? key[j] - mna : mx - mna) >> gsh);
             wg_sort_regs<NT, IT, u32, true, false>(sk, v, rank, nbits, vex, sm.cnt(), sm.wsum);
     #pragma unroll
-            for (int j = 0; j < IT; j++) key[j] = (K)vex[padi(t * IT + j)] + mn;
+            for (int j = 0; j < IT; j++) key[j] = ((K)vex[padi(t * IT + j)] << gsh) + mna;
         }
         wg_scatter_vals<NT, IT>(v, rank, vex);
         // boundary b (1..nb) = sorted element b*q - 1 - dsh
@@ -714,22 +721,33 @@ __global__ __launch_bounds__(CUT_NT) void k_mwm_cuts(MwmArgs<K> a) {
     sidx = uniform(sidx); scnt = uniform(scnt); pb = uniform(pb); sstr = uniform(sstr);
     const bool staged = scnt <= (u32)CUT_SMAX;
     K* st = ls[w];
+    const u32 step = 64u * gridDim.y;
+    // the boundaries of the wave's first pass load while the samples are
+    // staged, and every pass loads the next pass's boundaries ahead
+    K nbk = 0;
+    u32 nbp = 0;
+    if (live && blockIdx.y * 64u + (u32)lane < nb) {
+        nbk = a.bkey[gb + blockIdx.y * 64u + (u32)lane];
+        nbp = a.bpos[gb + blockIdx.y * 64u + (u32)lane];
+    }
     if (live && nb > 0 && staged)
         for (u32 j = lane; j < scnt; j += 64) st[j] = a.smp[sidx + j];
     __syncthreads();
     if (!live || nb == 0) return;
     const u32 r = (u32)(gr % R);
-    const u32 step = 64u * gridDim.y;
     const int half = lane >> 5, hl = lane & 31;
     for (u32 c0 = blockIdx.y * 64u; c0 < nb; c0 += step) {
         const u32 c = c0 + (u32)lane;
         const bool act = c < nb;
         const u32 slot = gb + c;
-        K bk = 0;
-        u32 bp = 0, wlo = 0, whi = 0;
+        const K bk = nbk;
+        const u32 bp = nbp;
+        if (c + step < nb) {
+            nbk = a.bkey[slot + step];
+            nbp = a.bpos[slot + step];
+        }
+        u32 wlo = 0, whi = 0;
         if (act) {
-            bk = a.bkey[slot];
-            bp = a.bpos[slot];
             // J = samples of this run that are <= the boundary
             u32 lo = 0, hi = scnt;
             if (staged) {
