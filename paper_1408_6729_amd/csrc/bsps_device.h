@@ -401,6 +401,57 @@ __device__ __forceinline__ void wg_sort_regs(SK (&sk)[IT], u32 (&v)[IT], u32 (&r
     }
 }
 
+// wg_sort_regs for wide 64-bit sort keys (bits [sh0, sh0 + nbits), nbits at
+// least TOPW + 2 digits), ranked on their top TOPW bits first. When no two
+// different keys share those top bits, that stable order is already the full
+// order (equal top bits then mean equal keys, which keep their input order),
+// and the passes over the lower bits are skipped: with at most 2^13 items and
+// keys spread over their range, two of them meet in 2^30 top-bit classes with
+// odds about 1/32, and inputs of few distinct keys (heavy duplicates) never.
+// Otherwise the full sort runs on the top-ordered items; being stable, it
+// keeps equal keys in the order the first sort left them, their input order.
+// Same contract as wg_sort_regs on return.
+constexpr int TOPW = 30;
+template <int NT, int IT, bool HASV, bool SMALLPASS = (bool)BSPS_SMALLPASS, bool SEP = false>
+__device__ __forceinline__ void wg_sort_regs_top(u64 (&sk)[IT], u32 (&v)[IT], u32 (&rank)[IT], int nbits, u64* exch,
+                                                 u32* cnt, u32* wsum, int sh0 = 0) {
+    const int t = threadIdx.x;
+    const bool wide = nbits >= TOPW + 2 * RB;
+    int nb = wide ? TOPW : nbits;
+    const int tsh = wide ? sh0 + nbits - TOPW : sh0;
+    // one sort call in a loop (the top bits, then if needed all bits), so that
+    // the sort's code is instantiated once
+    for (;;) {
+        wg_sort_regs<NT, IT, u64, HASV, SMALLPASS, SEP>(sk, v, rank, nb, exch, cnt, wsum, nb == nbits ? sh0 : tsh);
+        if (nb == nbits) return;
+        // sorted keys are in exch[padi(i)]; a class of equal top bits must hold one key
+        int mixed = 0;
+#pragma unroll
+        for (int j = 0; j < IT; j++) {
+            const int i = t * IT + j;
+            if (i + 1 < NT * IT) {
+                const u64 x = exch[padi(i)], y = exch[padi(i + 1)];
+                mixed |= ((x >> tsh) == (y >> tsh) && (x >> sh0) != (y >> sh0)) ? 1 : 0;
+            }
+        }
+        if (!__syncthreads_or(mixed)) return;
+        // the items in their top-bit order, payloads moved along, then the full sort
+#pragma unroll
+        for (int j = 0; j < IT; j++) sk[j] = exch[padi(t * IT + j)];
+        __syncthreads();
+        if (HASV) {
+            u32* vex = reinterpret_cast<u32*>(exch);
+#pragma unroll
+            for (int j = 0; j < IT; j++) vex[padi((int)rank[j])] = v[j];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < IT; j++) v[j] = vex[padi(t * IT + j)];
+            __syncthreads();
+        }
+        nb = nbits;
+    }
+}
+
 // Moves payloads to their final positions (after the keys were stored out of
 // the exchange buffer): vex[padi(rank[j])] = v[j].
 template <int NT, int IT>

@@ -263,8 +263,8 @@ __device__ __forceinline__ void tile_sort_body(const TileArgs<K>& a, SortSmem<Sh
         u64 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = j < valid ? (u64)(kr[j] - mn) : (u64)(mx - mn);
-        wg_sort_regs<NT, IT, u64, HASV, (bool)BSPS_SMALLPASS, !HASV>(sk, v, rank, sbits, sm.template ex<u64>(),
-                                                                     sm.cnt(), sm.wsum, gsh);
+        wg_sort_regs_top<NT, IT, HASV, (bool)BSPS_SMALLPASS, !HASV>(sk, v, rank, sbits, sm.template ex<u64>(),
+                                                                    sm.cnt(), sm.wsum, gsh);
         store_sorted<K, u64, NT, IT>(sm.template ex<u64>(), mn, cnt, out, odt, smp, sbase, ysh);
     } else {
         u32 sk[IT];
@@ -1330,7 +1330,7 @@ __device__ __forceinline__ void mwm_merge_chunk(const MwmArgs<K>& a, const uint4
         u64 sk[IT];
 #pragma unroll
         for (int j = 0; j < IT; j++) sk[j] = item_ok(j) ? (u64)(kr[j] - mn) : top;
-        wg_sort_regs<NT, IT, u64, HASV>(sk, v, rank, sbits, sm.template ex<u64>(), sm.cnt(), sm.wsum, dsh);
+        wg_sort_regs_top<NT, IT, HASV>(sk, v, rank, sbits, sm.template ex<u64>(), sm.cnt(), sm.wsum, dsh);
         const u64* e = sm.template ex<u64>();
 #pragma unroll
         for (int j = 0; j < IT; j++) {

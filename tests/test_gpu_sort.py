@@ -203,6 +203,27 @@ def test_duplicate_stress_small(ora, dev):
     assert (outv[1:][eq] > outv[:-1][eq]).all()
 
 
+@pytest.mark.parametrize("case", ["clusters", "spread_dups"])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_int64_top_first_sort(ora, dev, case, variant):
+    """Wide 64-bit keys are ranked on their top 30 bits first, and the lower
+    passes run only where two different keys share those bits. "clusters":
+    two clusters 2^63 apart of 2^16-wide offsets, so every tile and chunk has
+    many different keys per top-bit class and always takes the full sort
+    after the first; "spread_dups": 4096 values spread over the whole range,
+    each repeated, so the first sort is the whole sort and the payloads must
+    keep input order within equal keys. Key-value, against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(31 + variant))
+    n = 1 << 20
+    if case == "clusters":
+        base = np.where(rng.random(n) < 0.5, np.int64(-(1 << 62)), np.int64(1 << 62))
+        keys = base + rng.integers(0, 1 << 16, size=n, dtype=np.int64)
+    else:
+        vals = rng.integers(np.iinfo(np.int64).min, np.iinfo(np.int64).max, size=4096, dtype=np.int64)
+        keys = vals[rng.integers(0, vals.size, size=n)]
+    _check(ora, dev, keys, 32, 16, variant, seed=3, kv=True)
+
+
 def test_float_special_values(ora, dev):
     keys = W.lognormal_f32(1 << 20, zeros=1024)
     keys[:7] = np.array([np.inf, -np.inf, -0.0, 0.0, 1e-45, -1e-45, 3.4e38], dtype=np.float32)
