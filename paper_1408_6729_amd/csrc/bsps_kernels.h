@@ -639,7 +639,7 @@ __global__ __launch_bounds__(Shape<K>::NT) void k_mwm_pick(MwmArgs<K> a) {
     #pragma unroll
             for (int j = 0; j < IT; j++)
                 sk[j] = (u64)(((u32)(t * IT + j) < Sg ? key[j] - mna : mx - mna) >> gsh);
-            wg_sort_regs<NT, IT, u64, true, false>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
+            wg_sort_regs_top<NT, IT, true, false>(sk, v, rank, nbits, sm.template ex<u64>(), sm.cnt(), sm.wsum);
             u64* e = sm.template ex<u64>();
     #pragma unroll
             for (int j = 0; j < IT; j++) key[j] = (K)((e[padi(t * IT + j)] << gsh) + (u64)mna);
