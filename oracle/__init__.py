@@ -127,7 +127,7 @@ class OracleError(ValueError):
 
 def default_threads() -> int:
     """Host threads for the threaded driver: the cores this process may use,
-    at most 16 (the CPU share of one GPU on the GPU machines)."""
+    at most 16 (a host's CPU share per GPU on an 8-GPU node of 128 cores)."""
     try:
         n = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):
