@@ -201,3 +201,21 @@ def test_dry_run_rejects_like_the_call(bsps):
     prm = bsps.make_params(0, 1)
     assert bsps.check_sort(10, 0, False, prm)[0] == -bsps.EINVAL
     assert bsps.check_segmented([0, 5, 3], 0, False)[0] == -bsps.EINVAL
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "1"], {"WORLD_SIZE": "2"})])
+def test_bench_refuses_more_than_one_gpu(argv, env):
+    """The benchmark measures one GPU: asked for more (by flag or by a
+    launcher's WORLD_SIZE) it exits with status 2 and says so, before any
+    GPU work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    e = dict(os.environ)
+    e.pop("WORLD_SIZE", None)
+    e.update(env)
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *argv], capture_output=True, text=True,
+                       timeout=120, env=e, cwd=root)
+    assert r.returncode == 2
+    assert "single GPU" in r.stderr
+    assert r.stdout == ""
