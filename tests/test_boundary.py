@@ -219,3 +219,17 @@ def test_bench_refuses_more_than_one_gpu(argv, env):
     assert r.returncode == 2
     assert "single GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_import_fails_loudly_without_the_library(tmp_path):
+    """The product path has no CPU fallback: with the HIP library missing,
+    importing the package raises and names the build step."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    e = dict(os.environ)
+    e["BSPS_LIB"] = str(tmp_path / "libbsps_missing.so")
+    r = subprocess.run([sys.executable, "-c", "import paper_1408_6729_amd"], capture_output=True, text=True,
+                       timeout=120, env=e, cwd=root)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "no CPU fallback" in r.stderr
